@@ -1,0 +1,137 @@
+/*
+ * rtri.h -- C ABI of the recursive triangular multiply / solve library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Operations (paper, Sec. 2.1):
+ *   TRMM  eq. (1)  B := alpha * op(A) * B          side = RTRI_LEFT
+ *         eq. (2)  B := alpha * B * op(A)          side = RTRI_RIGHT
+ *   TRSM  eq. (3)  solve op(A) * X = alpha * B     side = RTRI_LEFT,  X overwrites B
+ *         eq. (4)  solve X * op(A) = alpha * B     side = RTRI_RIGHT, X overwrites B
+ *   op(A) = A, A^T or conj(A^T); for real data RTRI_CONJTRANS means A^T.
+ *
+ * Method (paper, Sec. 3.1-3.2): A is split at its midpoint into two triangular
+ * diagonal blocks and one off-diagonal block; the call recurses on the two
+ * diagonal blocks and applies the off-diagonal block as one GEMM update per
+ * level, until a block is at most the leaf size, where a leaf kernel solves or
+ * multiplies the diagonal block directly (Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ *   - Column-major storage: element (i, j) of a matrix X with leading
+ *     dimension ldx is X[i + j * ldx].
+ *   - For side = LEFT, A is m-by-m; for side = RIGHT, A is n-by-n; B is m-by-n.
+ *   - Only the triangle named by uplo is read.  With diag = RTRI_UNIT the
+ *     diagonal of A is not read either (taken as 1).
+ *   - A and B are DEVICE pointers, owned by the caller; the library never
+ *     frees them.  A and B must not overlap.
+ *   - Calls are asynchronous on the handle's stream: they return once the work
+ *     is enqueued.  Argument errors are reported synchronously and leave B
+ *     untouched.  Device-side errors surface as RTRI_ERR_HIP on a later call or
+ *     on rtri_sync.
+ *   - Quick return: m == 0 or n == 0 does nothing.  alpha == 0 sets B := 0
+ *     without reading A (BLAS semantics).
+ *   - A singular A (a zero diagonal entry with diag = NONUNIT) is not detected;
+ *     IEEE infinities / NaNs propagate into B, as in the reference BLAS.
+ *
+ * Return codes
+ *   0                 success
+ *   -i (i = 1..12)    argument i of the BLAS-style argument list is invalid:
+ *                     1 side, 2 uplo, 3 trans, 4 diag, 5 m < 0, 6 n < 0,
+ *                     8 A == NULL, 9 lda < max(1, ka), 10 B == NULL,
+ *                     11 ldb < max(1, m)   (ka = m for LEFT, n for RIGHT)
+ *   RTRI_ERR_HANDLE   NULL or destroyed handle
+ *   RTRI_ERR_HIP      a HIP runtime call failed (rtri_last_hip_error gives it)
+ *   RTRI_ERR_NOMEM    device workspace could not be allocated
+ *   RTRI_ERR_UNSUPPORTED  option or type combination not supported
+ */
+#ifndef RTRI_H
+#define RTRI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { RTRI_LEFT = 0, RTRI_RIGHT = 1 };
+enum { RTRI_LOWER = 0, RTRI_UPPER = 1 };
+enum { RTRI_NOTRANS = 0, RTRI_TRANS = 1, RTRI_CONJTRANS = 2 };
+enum { RTRI_NONUNIT = 0, RTRI_UNIT = 1 };
+enum { RTRI_F64 = 0, RTRI_F32 = 1, RTRI_BF16 = 2, RTRI_F16 = 3 };
+
+enum {
+    RTRI_OK = 0,
+    RTRI_ERR_HANDLE = 1,
+    RTRI_ERR_HIP = 2,
+    RTRI_ERR_NOMEM = 3,
+    RTRI_ERR_UNSUPPORTED = 4,
+    RTRI_NOT_CONVERGED = 5,
+    RTRI_ERR_INVALID = 6
+};
+
+/* Tunable options (rtri_set_option / rtri_get_option). */
+enum {
+    RTRI_OPT_LEAF_F64 = 1,   /* leaf size for FP64 (16, 32 or 64; 0 = automatic) */
+    RTRI_OPT_LEAF_F32 = 2,   /* leaf size for FP32 (16, 32, 64 or 128; 0 = automatic) */
+    RTRI_OPT_GEMM_TILE = 3   /* GEMM tile choice: 0 = automatic, 1 = 128x128, 2 = 64x64 */
+};
+
+typedef struct rtri_handle rtri_handle;
+
+/* Create a handle bound to a HIP stream (a hipStream_t passed as void*; NULL =
+ * the null stream) on the current device.  *h receives the handle. */
+int rtri_create(rtri_handle **h, void *hip_stream);
+
+/* Release a handle and any device workspace it owns.  Waits for no work:
+ * synchronise first if work using the handle may still be running. */
+int rtri_destroy(rtri_handle *h);
+
+/* Re-bind the handle to another stream (hipStream_t as void*). */
+int rtri_set_stream(rtri_handle *h, void *hip_stream);
+
+/* Block the host until all work enqueued through the handle has finished;
+ * returns RTRI_ERR_HIP if any of it failed. */
+int rtri_sync(rtri_handle *h);
+
+/* Set / read a tunable option (RTRI_OPT_*).  Invalid values return -3. */
+int rtri_set_option(rtri_handle *h, int option, int64_t value);
+int rtri_get_option(rtri_handle *h, int option, int64_t *value);
+
+/* Static description of a return code. */
+const char *rtri_status_string(int status);
+
+/* The hipError_t value behind the last RTRI_ERR_HIP returned on this handle. */
+int rtri_last_hip_error(rtri_handle *h);
+
+/* Triangular solve, eqs. (3)/(4): B := X with op(A) X = alpha B (LEFT) or
+ * X op(A) = alpha B (RIGHT).  FP64 / FP32. */
+int rtri_dtrsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+               double alpha, const double *A, int64_t lda, double *B, int64_t ldb);
+int rtri_strsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+               float alpha, const float *A, int64_t lda, float *B, int64_t ldb);
+
+/* Triangular multiply, eqs. (1)/(2): B := alpha op(A) B (LEFT) or
+ * B := alpha B op(A) (RIGHT), in place.  FP64 / FP32. */
+int rtri_dtrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+               double alpha, const double *A, int64_t lda, double *B, int64_t ldb);
+int rtri_strmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+               float alpha, const float *A, int64_t lda, float *B, int64_t ldb);
+
+/* The GEMM update of one recursion level (Sec. 3.1), callable on its own:
+ *     C := beta * C + s * op(P) * op(Q),   op(P) M-by-K, op(Q) K-by-N, C M-by-N
+ * op(P) = P (trans_p = RTRI_NOTRANS) or P^T (RTRI_TRANS); likewise op(Q).
+ * dtype is RTRI_F64 or RTRI_F32 (all of P, Q, C; alpha-like scalars passed as
+ * double and rounded to the element type).  beta == 0 writes C without reading
+ * it.  Device pointers; C must not overlap P or Q.  Asynchronous on the
+ * handle's stream.
+ * Argument codes: -2 dtype, -3 trans_p, -4 trans_q, -5 M < 0, -6 N < 0,
+ * -7 K < 0, -9 P NULL, -10 ldp < max(1, rows of P), -11 Q NULL,
+ * -12 ldq < max(1, rows of Q), -14 C NULL, -15 ldc < max(1, M). */
+int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_t M, int64_t N, int64_t K,
+                     double s, const void *P, int64_t ldp, const void *Q, int64_t ldq, double beta, void *C,
+                     int64_t ldc);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTRI_H */

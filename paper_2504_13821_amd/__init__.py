@@ -1,0 +1,195 @@
+"""Python binding of librtri.so, the recursive TRMM / TRSM library for MI355X.
+
+The functions named ``rtri_*`` mirror the C ABI in ``include/rtri.h`` one to
+one (integers for pointers and streams).  ``Handle``, ``trsm`` and ``trmm`` add
+argument marshalling for PyTorch tensors: device memory and streams come from
+PyTorch, every step of the computation runs in the library's HIP kernels.
+There is no fallback: importing this package on a machine without the built
+library raises ImportError.
+
+Matrices are column-major, as in BLAS: an m-by-n matrix is a torch tensor of
+shape (m, n) with ``stride(0) == 1`` and leading dimension ``stride(1)``; see
+``to_device``/``to_host`` for numpy Fortran-order conversion.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+try:  # load PyTorch's HIP runtime first so the library shares it (one runtime per process)
+    import torch
+except ImportError:  # pragma: no cover - the library itself does not need torch
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtri.so")
+HEADER = os.path.join(_HERE, "..", "include", "rtri.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2504_13821_amd/build.py`")
+
+_lib = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+
+LEFT, RIGHT = 0, 1
+LOWER, UPPER = 0, 1
+NOTRANS, TRANS, CONJTRANS = 0, 1, 2
+NONUNIT, UNIT = 0, 1
+F64, F32, BF16, F16 = 0, 1, 2, 3
+OK, ERR_HANDLE, ERR_HIP, ERR_NOMEM, ERR_UNSUPPORTED, NOT_CONVERGED, ERR_INVALID = range(7)
+OPT_LEAF_F64, OPT_LEAF_F32, OPT_GEMM_TILE = 1, 2, 3
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+
+
+def _sig(name, restype, *argtypes):
+    f = getattr(_lib, name)
+    f.restype = restype
+    f.argtypes = list(argtypes)
+    return f
+
+
+_OPARGS = (_vp, _int, _int, _int, _int, _i64, _i64)
+rtri_create = _sig("rtri_create", _int, ctypes.POINTER(_vp), _vp)
+rtri_destroy = _sig("rtri_destroy", _int, _vp)
+rtri_set_stream = _sig("rtri_set_stream", _int, _vp, _vp)
+rtri_sync = _sig("rtri_sync", _int, _vp)
+rtri_set_option = _sig("rtri_set_option", _int, _vp, _int, _i64)
+rtri_get_option = _sig("rtri_get_option", _int, _vp, _int, ctypes.POINTER(_i64))
+rtri_status_string = _sig("rtri_status_string", ctypes.c_char_p, _int)
+rtri_last_hip_error = _sig("rtri_last_hip_error", _int, _vp)
+rtri_dtrsm = _sig("rtri_dtrsm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
+rtri_strsm = _sig("rtri_strsm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
+rtri_dtrmm = _sig("rtri_dtrmm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
+rtri_strmm = _sig("rtri_strmm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
+rtri_gemm_update = _sig("rtri_gemm_update", _int, _vp, _int, _int, _int, _i64, _i64, _i64, ctypes.c_double, _vp,
+                        _i64, _vp, _i64, ctypes.c_double, _vp, _i64)
+
+
+class RtriError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        msg = rtri_status_string(code).decode()
+        super().__init__(f"{what}: rtri status {code} ({msg})" if what else f"rtri status {code} ({msg})")
+        self.code = code
+
+
+def check(code: int, what: str = "") -> int:
+    if code != OK:
+        raise RtriError(code, what)
+    return code
+
+
+_SIDE = {"L": LEFT, "R": RIGHT}
+_UPLO = {"L": LOWER, "U": UPPER}
+_TRANS = {"N": NOTRANS, "T": TRANS, "C": CONJTRANS}
+_DIAG = {"N": NONUNIT, "U": UNIT}
+
+
+def codes(side: str, uplo: str, trans: str, diag: str):
+    return _SIDE[side.upper()], _UPLO[uplo.upper()], _TRANS[trans.upper()], _DIAG[diag.upper()]
+
+
+class Handle:
+    """An rtri handle bound to a torch CUDA/HIP stream (default: the current one)."""
+
+    def __init__(self, stream=None):
+        if torch is not None and stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        raw = getattr(stream, "cuda_stream", stream) if stream is not None else None
+        h = _vp()
+        check(rtri_create(ctypes.byref(h), _vp(raw) if raw else None), "rtri_create")
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def set_option(self, option: int, value: int):
+        check(rtri_set_option(self._h, option, value), "rtri_set_option")
+
+    def get_option(self, option: int) -> int:
+        v = _i64()
+        check(rtri_get_option(self._h, option, ctypes.byref(v)), "rtri_get_option")
+        return v.value
+
+    def sync(self):
+        check(rtri_sync(self._h), "rtri_sync")
+
+    def close(self):
+        if self._h:
+            rtri_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _colmajor(t, name):
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if t.shape[0] > 1 and t.stride(0) != 1:
+        raise ValueError(f"{name} must be a column-major view (stride(0) == 1)")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    return max(1, t.stride(1) if t.shape[1] > 1 else t.shape[0])
+
+
+def _call(h: Handle, solve: bool, side, uplo, trans, diag, alpha, A, B):
+    lda = _colmajor(A, "A")
+    ldb = _colmajor(B, "B")
+    m, n = B.shape
+    if A.dtype != B.dtype:
+        raise TypeError("A and B must have the same dtype")
+    if B.dtype == torch.float64:
+        fn = rtri_dtrsm if solve else rtri_dtrmm
+    elif B.dtype == torch.float32:
+        fn = rtri_strsm if solve else rtri_strmm
+    else:
+        raise TypeError(f"unsupported dtype {B.dtype}")
+    rc = fn(h.ptr, *codes(side, uplo, trans, diag), m, n, alpha, A.data_ptr(), lda, B.data_ptr(), ldb)
+    check(rc, fn.__name__)
+    return B
+
+
+def trsm(h: Handle, side, uplo, trans, diag, alpha, A, B):
+    """In place: B := X with op(A) X = alpha B (side 'L') or X op(A) = alpha B (side 'R')."""
+    return _call(h, True, side, uplo, trans, diag, alpha, A, B)
+
+
+def trmm(h: Handle, side, uplo, trans, diag, alpha, A, B):
+    """In place: B := alpha op(A) B (side 'L') or alpha B op(A) (side 'R')."""
+    return _call(h, False, side, uplo, trans, diag, alpha, A, B)
+
+
+def gemm_update(h: Handle, trans_p: str, trans_q: str, s, P, Q, beta, C):
+    """In place: C := beta C + s op(P) op(Q) (the recursion's GEMM update on its own)."""
+    ldp, ldq, ldc = _colmajor(P, "P"), _colmajor(Q, "Q"), _colmajor(C, "C")
+    tp, tq = _TRANS[trans_p.upper()], _TRANS[trans_q.upper()]
+    M, N = C.shape
+    K = P.shape[0] if tp else P.shape[1]
+    dt = {torch.float64: F64, torch.float32: F32}[C.dtype]
+    check(rtri_gemm_update(h.ptr, dt, tp, tq, M, N, K, s, P.data_ptr(), ldp, Q.data_ptr(), ldq, beta,
+                           C.data_ptr(), ldc), "rtri_gemm_update")
+    return C
+
+
+def to_device(a, dtype=None, device="cuda", ld=None):
+    """numpy (any order) -> column-major device tensor of shape (m, n); optional padded leading dimension."""
+    import numpy as np
+    a = np.asarray(a)
+    m, n = a.shape
+    ld = m if ld is None else ld
+    dt = dtype if dtype is not None else {np.dtype("float64"): torch.float64, np.dtype("float32"): torch.float32}[a.dtype]
+    store = torch.zeros((n, ld), dtype=dt, device=device)
+    store[:, :m] = torch.from_numpy(np.ascontiguousarray(a.T)).to(device=device, dtype=dt)
+    return store.t()[:m, :]
+
+
+def to_host(t):
+    """column-major device tensor -> numpy Fortran-order array (float64 kept, others as stored)."""
+    return t.t().contiguous().cpu().numpy().T

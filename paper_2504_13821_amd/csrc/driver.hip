@@ -1,0 +1,421 @@
+// Recursion driver and the C ABI (include/rtri.h).
+//
+// The recursion (paper, Sec. 3.1-3.2) splits the triangular factor at its
+// midpoint: two triangular diagonal blocks and one off-diagonal block.  It is
+// written once, over the "dependency index" (rows of B for side = L, columns
+// of B for side = R), and covers all sixteen side / uplo / trans cases and
+// both diag values:
+//
+//   op(A) is effectively lower when (uplo == L) != (trans != N).
+//   TRSM visits the blocks in dependency order: block 1 first when the solve
+//   runs forward (side L with lower op(A), or side R with upper op(A)).
+//   TRMM visits them in the opposite order, so its GEMM always reads the block
+//   that has not been overwritten yet.
+//
+//   split h rows at k:  block 1 = [d0, d0+k),  block 2 = [d0+k, d0+h)
+//   TRSM: first = rec(alpha); update: B_t = alpha*B_t - (off-diagonal) * X_s;
+//         second = rec(1)              (alpha applied once, at first touch)
+//   TRMM: first = rec(alpha); update: B_t += alpha * (off-diagonal) * B_s;
+//         second = rec(alpha)
+//   side L: C = B[t rows], P = op(A)[t, s], Q = B[s rows]
+//   side R: C = B[t cols], P = B[s cols],    Q = op(A)[s, t]
+//
+// The split point is a multiple of the leaf size (half the block, rounded up),
+// so every leaf but the last one is full and GEMM operands stay aligned.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+
+using namespace rtri;
+
+struct rtri_handle {
+    uint32_t magic;
+    hipStream_t stream;
+    int leaf_f64, leaf_f32, gemm_tile;
+    hipError_t last;
+};
+
+namespace {
+
+constexpr uint32_t MAGIC = 0x72747269u;  // 'rtri'
+
+bool valid(const rtri_handle *h) { return h != nullptr && h->magic == MAGIC; }
+
+int hip_fail(rtri_handle *h, hipError_t e)
+{
+    h->last = e;
+    return e == hipErrorOutOfMemory ? RTRI_ERR_NOMEM : RTRI_ERR_HIP;
+}
+
+struct Op {
+    bool gemm;
+    GemmDesc g;
+    LeafDesc l;
+};
+
+struct Problem {
+    bool solve;
+    int side, uplo, trans, diag;
+    int64_t m, n;
+    double alpha;
+    const char *A;
+    int64_t lda;
+    char *B;
+    int64_t ldb;
+    size_t es;  // element size in bytes
+    int leaf;
+};
+
+// pointer to op(A)[r0.., c0..] and whether it reads A transposed
+inline const char *tri_block(const Problem &p, int64_t r0, int64_t c0)
+{
+    const int64_t off = p.trans ? c0 + r0 * p.lda : r0 + c0 * p.lda;
+    return p.A + off * (int64_t)p.es;
+}
+
+struct Planner {
+    const Problem &p;
+    bool low;       // op(A) lower
+    bool forward;   // TRSM order: block 1 before block 2
+    std::vector<Op> ops;
+
+    explicit Planner(const Problem &pr) : p(pr)
+    {
+        low = (p.uplo == RTRI_LOWER) != (p.trans != RTRI_NOTRANS);
+        const bool fwd_solve = p.side == RTRI_LEFT ? low : !low;
+        forward = p.solve ? fwd_solve : !fwd_solve;
+    }
+
+    void leaf(int64_t d0, int64_t h, double alpha)
+    {
+        Op op{};
+        op.gemm = false;
+        LeafDesc &l = op.l;
+        l.A = p.A + (d0 + d0 * p.lda) * (int64_t)p.es;
+        l.lda = p.lda;
+        l.nb = (int)h;
+        l.unit = p.diag == RTRI_UNIT;
+        l.alpha = alpha;
+        if (p.side == RTRI_LEFT) {
+            // Mx = op(A) block;  vectors are columns of B
+            l.mtrans = p.trans != RTRI_NOTRANS;
+            l.mlower = low;
+            l.B = p.B + d0 * (int64_t)p.es;
+            l.sd = 1;
+            l.si = p.ldb;
+            l.nvec = p.n;
+        } else {
+            // x op(A) = alpha b  <=>  op(A)^T x^T = alpha b^T;  vectors are rows of B
+            l.mtrans = p.trans == RTRI_NOTRANS;
+            l.mlower = !low;
+            l.B = p.B + d0 * p.ldb * (int64_t)p.es;
+            l.sd = p.ldb;
+            l.si = 1;
+            l.nvec = p.m;
+        }
+        ops.push_back(op);
+    }
+
+    // B[t] = beta * B[t] + s * (update from block src)
+    void update(int64_t t0, int64_t th, int64_t s0, int64_t sh, double beta, double s)
+    {
+        Op op{};
+        op.gemm = true;
+        GemmDesc &g = op.g;
+        g.beta = beta;
+        g.s = s;
+        g.K = sh;
+        const bool tr = p.trans != RTRI_NOTRANS;
+        if (p.side == RTRI_LEFT) {
+            g.M = th;
+            g.N = p.n;
+            g.P = tri_block(p, t0, s0);
+            g.ldp = p.lda;
+            g.tp = tr;
+            g.Q = p.B + s0 * (int64_t)p.es;
+            g.ldq = p.ldb;
+            g.tq = false;
+            g.C = p.B + t0 * (int64_t)p.es;
+        } else {
+            g.M = p.m;
+            g.N = th;
+            g.P = p.B + s0 * p.ldb * (int64_t)p.es;
+            g.ldp = p.ldb;
+            g.tp = false;
+            g.Q = tri_block(p, s0, t0);
+            g.ldq = p.lda;
+            g.tq = tr;
+            g.C = p.B + t0 * p.ldb * (int64_t)p.es;
+        }
+        g.ldc = p.ldb;
+        ops.push_back(op);
+    }
+
+    void rec(int64_t d0, int64_t h, double alpha)
+    {
+        if (h <= p.leaf) {
+            leaf(d0, h, alpha);
+            return;
+        }
+        const int64_t a = p.leaf;
+        const int64_t k = a * ((h + 2 * a - 1) / (2 * a));
+        const int64_t b1 = d0, h1 = k, b2 = d0 + k, h2 = h - k;
+        const int64_t f0 = forward ? b1 : b2, fh = forward ? h1 : h2;   // first block
+        const int64_t g0 = forward ? b2 : b1, gh = forward ? h2 : h1;   // second block
+        rec(f0, fh, alpha);
+        if (p.solve) {
+            update(g0, gh, f0, fh, alpha, -1.0);   // B_second = alpha B_second - off * X_first
+            rec(g0, gh, 1.0);
+        } else {
+            update(f0, fh, g0, gh, 1.0, alpha);    // B_first += alpha * off * B_second (original)
+            rec(g0, gh, alpha);
+        }
+    }
+};
+
+int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, const void *A, int64_t lda,
+               const void *B, int64_t ldb, bool need_a)
+{
+    if (side != RTRI_LEFT && side != RTRI_RIGHT) return -1;
+    if (uplo != RTRI_LOWER && uplo != RTRI_UPPER) return -2;
+    if (trans != RTRI_NOTRANS && trans != RTRI_TRANS && trans != RTRI_CONJTRANS) return -3;
+    if (diag != RTRI_NONUNIT && diag != RTRI_UNIT) return -4;
+    if (m < 0) return -5;
+    if (n < 0) return -6;
+    const int64_t ka = side == RTRI_LEFT ? m : n;
+    if (m > 0 && n > 0 && need_a && A == nullptr) return -8;
+    if (lda < std::max<int64_t>(1, ka)) return -9;
+    if (m > 0 && n > 0 && B == nullptr) return -10;
+    if (ldb < std::max<int64_t>(1, m)) return -11;
+    return 0;
+}
+
+int pick_leaf(const rtri_handle *h, DType t, int64_t ka)
+{
+    int leaf = t == DType::F64 ? h->leaf_f64 : h->leaf_f32;
+    if (leaf == 0)
+        leaf = 64;
+    (void)ka;
+    return leaf;
+}
+
+int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+        double alpha, const void *A, int64_t lda, void *B, int64_t ldb)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    const int rc = check_args(side, uplo, trans, diag, m, n, A, lda, B, ldb, alpha != 0.0);
+    if (rc != 0)
+        return rc;
+    if (m == 0 || n == 0)
+        return RTRI_OK;
+    if (alpha == 0.0) {
+        hipError_t e = launch_fill(t, B, m, n, ldb, 0.0, h->stream);
+        return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
+    }
+    Problem p{};
+    p.solve = solve;
+    p.side = side;
+    p.uplo = uplo;
+    p.trans = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    p.diag = diag;
+    p.m = m;
+    p.n = n;
+    p.alpha = alpha;
+    p.A = static_cast<const char *>(A);
+    p.lda = lda;
+    p.B = static_cast<char *>(B);
+    p.ldb = ldb;
+    p.es = t == DType::F64 ? 8 : 4;
+    const int64_t ka = side == RTRI_LEFT ? m : n;
+    p.leaf = pick_leaf(h, t, ka);
+    Planner pl(p);
+    pl.rec(0, ka, alpha);
+    for (const Op &op : pl.ops) {
+        hipError_t e = op.gemm ? launch_gemm(t, op.g, h->gemm_tile, h->stream)
+                               : launch_leaf(t, solve, p.leaf, op.l, h->stream);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+    }
+    return RTRI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rtri_create(rtri_handle **out, void *stream)
+{
+    if (out == nullptr)
+        return -1;
+    rtri_handle *h = new (std::nothrow) rtri_handle();
+    if (h == nullptr)
+        return RTRI_ERR_NOMEM;
+    h->magic = MAGIC;
+    h->stream = static_cast<hipStream_t>(stream);
+    h->leaf_f64 = 0;
+    h->leaf_f32 = 0;
+    h->gemm_tile = 0;
+    h->last = hipSuccess;
+    *out = h;
+    return RTRI_OK;
+}
+
+int rtri_destroy(rtri_handle *h)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    h->magic = 0;
+    delete h;
+    return RTRI_OK;
+}
+
+int rtri_set_stream(rtri_handle *h, void *stream)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    h->stream = static_cast<hipStream_t>(stream);
+    return RTRI_OK;
+}
+
+int rtri_sync(rtri_handle *h)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
+}
+
+int rtri_set_option(rtri_handle *h, int option, int64_t value)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    switch (option) {
+    case RTRI_OPT_LEAF_F64:
+        if (value != 0 && value != 16 && value != 32 && value != 64) return -3;
+        h->leaf_f64 = (int)value;
+        return RTRI_OK;
+    case RTRI_OPT_LEAF_F32:
+        if (value != 0 && value != 16 && value != 32 && value != 64 && value != 128) return -3;
+        h->leaf_f32 = (int)value;
+        return RTRI_OK;
+    case RTRI_OPT_GEMM_TILE:
+        if (value < 0 || value > 2) return -3;
+        h->gemm_tile = (int)value;
+        return RTRI_OK;
+    default:
+        return -2;
+    }
+}
+
+int rtri_get_option(rtri_handle *h, int option, int64_t *value)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    if (value == nullptr)
+        return -3;
+    switch (option) {
+    case RTRI_OPT_LEAF_F64: *value = h->leaf_f64; return RTRI_OK;
+    case RTRI_OPT_LEAF_F32: *value = h->leaf_f32; return RTRI_OK;
+    case RTRI_OPT_GEMM_TILE: *value = h->gemm_tile; return RTRI_OK;
+    default: return -2;
+    }
+}
+
+const char *rtri_status_string(int s)
+{
+    if (s < 0) {
+        static const char *names[] = {"invalid argument",        "invalid side",  "invalid uplo",
+                                      "invalid trans",           "invalid diag",  "m < 0",
+                                      "n < 0",                   "invalid alpha", "A is NULL",
+                                      "lda too small",           "B is NULL",     "ldb too small",
+                                      "invalid argument 12"};
+        return (-s) <= 12 ? names[-s] : names[0];
+    }
+    switch (s) {
+    case RTRI_OK: return "success";
+    case RTRI_ERR_HANDLE: return "invalid handle";
+    case RTRI_ERR_HIP: return "HIP runtime error";
+    case RTRI_ERR_NOMEM: return "out of device memory";
+    case RTRI_ERR_UNSUPPORTED: return "unsupported option or type combination";
+    case RTRI_NOT_CONVERGED: return "iterative refinement did not converge";
+    case RTRI_ERR_INVALID: return "invalid input";
+    default: return "unknown status";
+    }
+}
+
+int rtri_last_hip_error(rtri_handle *h)
+{
+    if (!valid(h))
+        return -1;
+    return (int)h->last;
+}
+
+int rtri_dtrsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha,
+               const double *A, int64_t lda, double *B, int64_t ldb)
+{
+    return run(h, DType::F64, true, side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb);
+}
+
+int rtri_strsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, float alpha,
+               const float *A, int64_t lda, float *B, int64_t ldb)
+{
+    return run(h, DType::F32, true, side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb);
+}
+
+int rtri_dtrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha,
+               const double *A, int64_t lda, double *B, int64_t ldb)
+{
+    return run(h, DType::F64, false, side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb);
+}
+
+int rtri_strmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, float alpha,
+               const float *A, int64_t lda, float *B, int64_t ldb)
+{
+    return run(h, DType::F32, false, side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb);
+}
+
+int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_t M, int64_t N, int64_t K,
+                     double s, const void *P, int64_t ldp, const void *Q, int64_t ldq, double beta, void *C,
+                     int64_t ldc)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    if (dtype != RTRI_F64 && dtype != RTRI_F32) return -2;
+    if (trans_p != RTRI_NOTRANS && trans_p != RTRI_TRANS && trans_p != RTRI_CONJTRANS) return -3;
+    if (trans_q != RTRI_NOTRANS && trans_q != RTRI_TRANS && trans_q != RTRI_CONJTRANS) return -4;
+    if (M < 0) return -5;
+    if (N < 0) return -6;
+    if (K < 0) return -7;
+    const bool tp = trans_p != RTRI_NOTRANS, tq = trans_q != RTRI_NOTRANS;
+    const bool work = M > 0 && N > 0 && K > 0 && s != 0.0;
+    if (work && P == nullptr) return -9;
+    if (ldp < std::max<int64_t>(1, tp ? K : M)) return -10;
+    if (work && Q == nullptr) return -11;
+    if (ldq < std::max<int64_t>(1, tq ? N : K)) return -12;
+    if (M > 0 && N > 0 && C == nullptr) return -14;
+    if (ldc < std::max<int64_t>(1, M)) return -15;
+    if (M == 0 || N == 0)
+        return RTRI_OK;
+    GemmDesc g{};
+    g.M = M;
+    g.N = N;
+    g.K = work ? K : 0;
+    g.s = s;
+    g.beta = beta;
+    g.P = P;
+    g.ldp = ldp;
+    g.tp = tp;
+    g.Q = Q;
+    g.ldq = ldq;
+    g.tq = tq;
+    g.C = C;
+    g.ldc = ldc;
+    const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
+    hipError_t e = launch_gemm(t, g, h->gemm_tile, h->stream);
+    return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
+}
+
+}  // extern "C"

@@ -37,9 +37,9 @@ W_TEST = 9         # ad-hoc test cases
 T_A, T_B, T_X, T_META = 1, 2, 3, 4
 
 
-def rng(workload: int, instance: int = 0, tag: int = 0, seed: int = SEED) -> np.random.Generator:
-    """Philox4x32-10 stream keyed by (seed, workload, instance, tag)."""
-    ss = np.random.SeedSequence([seed, workload, instance, tag])
+def rng(workload: int, *keys: int, seed: int = SEED) -> np.random.Generator:
+    """Philox4x32-10 stream keyed by (seed, workload, *keys), e.g. keys = (instance, tag)."""
+    ss = np.random.SeedSequence([seed, workload, *[int(k) for k in keys]])
     return np.random.Generator(np.random.Philox(ss))
 
 
