@@ -116,6 +116,31 @@ int rtri_dtrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t 
 int rtri_strmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                float alpha, const float *A, int64_t lda, float *B, int64_t ldb);
 
+/* Per-kernel profile: while a profile is open, every kernel the handle
+ * launches is bracketed by two HIP events recorded on the handle's stream, and
+ * its algorithmic work is attributed to a kernel class.  rtri_profile_end waits
+ * for the stream, fills out[] with one entry per class that ran (at most
+ * max_out entries), sets *n_out, and closes the profile.
+ *   flops: GEMM 2*M*N*K; leaf nb*nb*nvec (multiply-adds counted twice)
+ *   bytes: the minimum HBM traffic of the launch (each operand read once,
+ *          the output read and written once) */
+enum {
+    RTRI_KCLASS_GEMM = 0,        /* GEMM update (Sec. 3.1) */
+    RTRI_KCLASS_LEAF_SOLVE = 1,  /* leaf triangular solve (Sec. 3.3) */
+    RTRI_KCLASS_LEAF_MULT = 2,   /* leaf triangular multiply */
+    RTRI_KCLASS_OTHER = 3        /* fills, conversions, norms */
+};
+typedef struct {
+    int kclass;       /* RTRI_KCLASS_* */
+    int dtype;        /* RTRI_F64 / RTRI_F32 / RTRI_BF16 / RTRI_F16: element type of the inputs */
+    int64_t launches;
+    double ms;        /* summed event-to-event duration of the launches */
+    double flops;     /* summed algorithmic flops */
+    double bytes;     /* summed algorithmic bytes */
+} rtri_kernel_stat;
+int rtri_profile_begin(rtri_handle *h);
+int rtri_profile_end(rtri_handle *h, rtri_kernel_stat *out, int max_out, int *n_out);
+
 /* The GEMM update of one recursion level (Sec. 3.1), callable on its own:
  *     C := beta * C + s * op(P) * op(Q),   op(P) M-by-K, op(Q) K-by-N, C M-by-N
  * op(P) = P (trans_p = RTRI_NOTRANS) or P^T (RTRI_TRANS); likewise op(Q).

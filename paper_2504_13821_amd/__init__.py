@@ -67,6 +67,17 @@ rtri_gemm_update = _sig("rtri_gemm_update", _int, _vp, _int, _int, _int, _i64, _
                         _i64, _vp, _i64, ctypes.c_double, _vp, _i64)
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("kclass", _int), ("dtype", _int), ("launches", _i64), ("ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+KCLASS_NAMES = {0: "gemm", 1: "leaf_solve", 2: "leaf_mult", 3: "other"}
+DTYPE_NAMES = {0: "f64", 1: "f32", 2: "bf16", 3: "f16"}
+rtri_profile_begin = _sig("rtri_profile_begin", _int, _vp)
+rtri_profile_end = _sig("rtri_profile_end", _int, _vp, ctypes.POINTER(KernelStat), _int, ctypes.POINTER(_int))
+
+
 class RtriError(RuntimeError):
     def __init__(self, code: int, what: str = ""):
         msg = rtri_status_string(code).decode()
@@ -116,6 +127,17 @@ class Handle:
 
     def sync(self):
         check(rtri_sync(self._h), "rtri_sync")
+
+    def profile_begin(self):
+        check(rtri_profile_begin(self._h), "rtri_profile_begin")
+
+    def profile_end(self) -> list:
+        """Per kernel class: dicts with launches, ms, flops, bytes (waits for the stream)."""
+        buf = (KernelStat * 16)()
+        n = _int()
+        check(rtri_profile_end(self._h, buf, 16, ctypes.byref(n)), "rtri_profile_end")
+        return [dict(kclass=KCLASS_NAMES[b.kclass], dtype=DTYPE_NAMES[b.dtype], launches=b.launches, ms=b.ms,
+                     flops=b.flops, bytes=b.bytes) for b in buf[:n.value]]
 
     def close(self):
         if self._h:

@@ -34,27 +34,44 @@ struct GemmDesc {
 };
 
 // ---------------------------------------------------------------------------
-// Leaf kernel on one diagonal block.  The block's effective matrix is
-//     Mx(r, c) = mtrans ? A[c + r*lda] : A[r + c*lda],   0 <= r, c < nb,
-// lower-triangular when mlower, else upper.  The panel holds nvec independent
-// vectors of length nb: element d of vector v is B[d*sd + v*si].
-//   solve:     Mx y = alpha * b   (y overwrites b)
-//   multiply:  b := alpha * Mx b
+// Diagonal blocks.  Block b covers rows / columns [b*nbmax, min((b+1)*nbmax, ka))
+// of the effective matrix
+//     Mx(r, c) = mtrans ? A[c + r*lda] : A[r + c*lda],
+// lower-triangular when mlower, else upper.  The pack pass writes each block
+// as a canonical lower triangle L, packed column by column (L(k,k) first, then
+// L(k+1,k) ...; ascending columns for a solve, descending for a multiply),
+// with L(i,k) = Mx(p(i), p(k)), p(i) = i (lower)
+// or nb-1-i (upper); rows past the block's end and a unit diagonal become the
+// identity.  Each packed block takes tri_elems(nbmax) = nbmax*(nbmax+1)/2 slots.
 // ---------------------------------------------------------------------------
-struct LeafDesc {
-    const void *A;
+struct PackDesc {
+    const void *A;      // A of the whole problem (element (0,0) of Mx)
     int64_t lda;
+    int64_t ka;         // order of Mx
+    bool mtrans, mlower, unit;
+    void *out;          // nblocks * tri_elems(nbmax) elements
+};
+
+// Leaf kernel on one diagonal block against a panel of nvec independent
+// vectors of length nb: element d (block order) of vector v is B[d*sd + v*si].
+//   solve:     L y = alpha * b  in canonical order (y overwrites b)
+//   multiply:  b := alpha * L b
+struct LeafDesc {
+    const void *Lp;     // this block's packed canonical triangle
     void *B;
     int64_t sd, si;
     int nb;
     int64_t nvec;
-    bool mtrans, mlower, unit;
+    bool mlower, unit;
     double alpha;
 };
+
+inline int64_t tri_elems(int nb) { return (int64_t)nb * (nb + 1) / 2; }
 
 enum class DType { F64, F32 };
 
 hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st);
+hipError_t launch_pack(DType t, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);
 hipError_t launch_fill(DType t, void *B, int64_t m, int64_t n, int64_t ldb, double value, hipStream_t st);
 

@@ -30,11 +30,27 @@
 
 using namespace rtri;
 
+namespace {
+struct ProfRec {
+    int kclass, dtype;
+    double flops, bytes;
+    hipEvent_t e0, e1;
+};
+}  // namespace
+
 struct rtri_handle {
     uint32_t magic;
     hipStream_t stream;
     int leaf_f64, leaf_f32, gemm_tile;
     hipError_t last;
+    // device workspace owned by the handle (packed diagonal blocks), grown on demand
+    void *ws;
+    size_t ws_bytes;
+    // per-kernel profile (rtri_profile_begin / rtri_profile_end)
+    bool profiling;
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used;
 };
 
 namespace {
@@ -47,6 +63,77 @@ int hip_fail(rtri_handle *h, hipError_t e)
 {
     h->last = e;
     return e == hipErrorOutOfMemory ? RTRI_ERR_NOMEM : RTRI_ERR_HIP;
+}
+
+hipError_t pool_event(rtri_handle *h, hipEvent_t *ev)
+{
+    if (h->pool_used == h->pool.size()) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess)
+            return err;
+        h->pool.push_back(e);
+    }
+    *ev = h->pool[h->pool_used++];
+    return hipSuccess;
+}
+
+// Launch through f(); when a profile is open, bracket it with events on the
+// handle's stream and attribute its algorithmic work to a kernel class.
+template <class F>
+hipError_t timed(rtri_handle *h, int kclass, int dtype, double flops, double bytes, F &&f)
+{
+    if (!h->profiling)
+        return f();
+    ProfRec r{kclass, dtype, flops, bytes, nullptr, nullptr};
+    hipError_t e = pool_event(h, &r.e0);
+    if (e == hipSuccess)
+        e = pool_event(h, &r.e1);
+    if (e == hipSuccess)
+        e = hipEventRecord(r.e0, h->stream);
+    if (e != hipSuccess)
+        return e;
+    e = f();
+    if (e != hipSuccess)
+        return e;
+    e = hipEventRecord(r.e1, h->stream);
+    if (e == hipSuccess)
+        h->recs.push_back(r);
+    return e;
+}
+
+// make sure the handle's workspace holds at least `bytes`
+hipError_t ensure_ws(rtri_handle *h, size_t bytes)
+{
+    if (bytes <= h->ws_bytes)
+        return hipSuccess;
+    if (h->ws != nullptr) {
+        hipError_t e = hipStreamSynchronize(h->stream);   // earlier work may still read it
+        if (e != hipSuccess)
+            return e;
+        (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    const size_t want = std::max<size_t>(bytes, (size_t)1 << 20);
+    hipError_t e = hipMalloc(&h->ws, want);
+    if (e != hipSuccess) {
+        h->ws = nullptr;
+        return e;
+    }
+    h->ws_bytes = want;
+    return hipSuccess;
+}
+
+double gemm_flops(const GemmDesc &g) { return 2.0 * (double)g.M * (double)g.N * (double)g.K; }
+double gemm_bytes(const GemmDesc &g, size_t es)
+{
+    return (double)es * ((double)g.M * g.K + (double)g.K * g.N + (g.beta == 0.0 ? 1.0 : 2.0) * g.M * g.N);
+}
+double leaf_flops(const LeafDesc &l) { return (double)l.nb * l.nb * (double)l.nvec; }
+double leaf_bytes(const LeafDesc &l, size_t es)
+{
+    return (double)es * ((double)l.nb * (l.nb + 1) / 2.0 + 2.0 * l.nb * (double)l.nvec);
 }
 
 struct Op {
@@ -93,14 +180,12 @@ struct Planner {
         Op op{};
         op.gemm = false;
         LeafDesc &l = op.l;
-        l.A = p.A + (d0 + d0 * p.lda) * (int64_t)p.es;
-        l.lda = p.lda;
+        l.Lp = reinterpret_cast<const void *>((d0 / p.leaf) * tri_elems(p.leaf) * (int64_t)p.es);  // offset, rebased later
         l.nb = (int)h;
         l.unit = p.diag == RTRI_UNIT;
         l.alpha = alpha;
         if (p.side == RTRI_LEFT) {
             // Mx = op(A) block;  vectors are columns of B
-            l.mtrans = p.trans != RTRI_NOTRANS;
             l.mlower = low;
             l.B = p.B + d0 * (int64_t)p.es;
             l.sd = 1;
@@ -108,7 +193,6 @@ struct Planner {
             l.nvec = p.n;
         } else {
             // x op(A) = alpha b  <=>  op(A)^T x^T = alpha b^T;  vectors are rows of B
-            l.mtrans = p.trans == RTRI_NOTRANS;
             l.mlower = !low;
             l.B = p.B + d0 * p.ldb * (int64_t)p.es;
             l.sd = p.ldb;
@@ -211,8 +295,11 @@ int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int 
         return rc;
     if (m == 0 || n == 0)
         return RTRI_OK;
+    const int dcode = t == DType::F64 ? RTRI_F64 : RTRI_F32;
+    const size_t es = t == DType::F64 ? 8 : 4;
     if (alpha == 0.0) {
-        hipError_t e = launch_fill(t, B, m, n, ldb, 0.0, h->stream);
+        hipError_t e = timed(h, RTRI_KCLASS_OTHER, dcode, 0.0, (double)es * m * n,
+                             [&] { return launch_fill(t, B, m, n, ldb, 0.0, h->stream); });
         return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
     }
     Problem p{};
@@ -228,14 +315,46 @@ int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int 
     p.lda = lda;
     p.B = static_cast<char *>(B);
     p.ldb = ldb;
-    p.es = t == DType::F64 ? 8 : 4;
+    p.es = es;
     const int64_t ka = side == RTRI_LEFT ? m : n;
     p.leaf = pick_leaf(h, t, ka);
     Planner pl(p);
     pl.rec(0, ka, alpha);
+
+    // pack every diagonal block once into the canonical form the leaves read
+    const int64_t nblk = (ka + p.leaf - 1) / p.leaf;
+    hipError_t e0 = ensure_ws(h, (size_t)(nblk * tri_elems(p.leaf)) * es);
+    if (e0 != hipSuccess)
+        return hip_fail(h, e0);
+    PackDesc pk{};
+    pk.A = A;
+    pk.lda = lda;
+    pk.ka = ka;
+    pk.unit = diag == RTRI_UNIT;
+    if (side == RTRI_LEFT) {
+        pk.mtrans = p.trans != RTRI_NOTRANS;
+        pk.mlower = pl.low;
+    } else {
+        pk.mtrans = p.trans == RTRI_NOTRANS;
+        pk.mlower = !pl.low;
+    }
+    pk.out = h->ws;
+    e0 = timed(h, RTRI_KCLASS_OTHER, dcode, 0.0, (double)es * (ka * (double)p.leaf + nblk * tri_elems(p.leaf)),
+               [&] { return launch_pack(t, solve, p.leaf, pk, h->stream); });
+    if (e0 != hipSuccess)
+        return hip_fail(h, e0);
+    for (Op &op : pl.ops)
+        if (!op.gemm)
+            op.l.Lp = static_cast<const char *>(h->ws) + reinterpret_cast<intptr_t>(op.l.Lp);
+
     for (const Op &op : pl.ops) {
-        hipError_t e = op.gemm ? launch_gemm(t, op.g, h->gemm_tile, h->stream)
-                               : launch_leaf(t, solve, p.leaf, op.l, h->stream);
+        hipError_t e;
+        if (op.gemm)
+            e = timed(h, RTRI_KCLASS_GEMM, dcode, gemm_flops(op.g), gemm_bytes(op.g, es),
+                      [&] { return launch_gemm(t, op.g, h->gemm_tile, h->stream); });
+        else
+            e = timed(h, solve ? RTRI_KCLASS_LEAF_SOLVE : RTRI_KCLASS_LEAF_MULT, dcode, leaf_flops(op.l),
+                      leaf_bytes(op.l, es), [&] { return launch_leaf(t, solve, p.leaf, op.l, h->stream); });
         if (e != hipSuccess)
             return hip_fail(h, e);
     }
@@ -259,6 +378,10 @@ int rtri_create(rtri_handle **out, void *stream)
     h->leaf_f32 = 0;
     h->gemm_tile = 0;
     h->last = hipSuccess;
+    h->profiling = false;
+    h->pool_used = 0;
+    h->ws = nullptr;
+    h->ws_bytes = 0;
     *out = h;
     return RTRI_OK;
 }
@@ -268,7 +391,61 @@ int rtri_destroy(rtri_handle *h)
     if (!valid(h))
         return RTRI_ERR_HANDLE;
     h->magic = 0;
+    for (hipEvent_t e : h->pool)
+        (void)hipEventDestroy(e);
+    if (h->ws != nullptr) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->ws);
+    }
     delete h;
+    return RTRI_OK;
+}
+
+int rtri_profile_begin(rtri_handle *h)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    h->recs.clear();
+    h->pool_used = 0;
+    h->profiling = true;
+    return RTRI_OK;
+}
+
+int rtri_profile_end(rtri_handle *h, rtri_kernel_stat *out, int max_out, int *n_out)
+{
+    if (!valid(h))
+        return RTRI_ERR_HANDLE;
+    if (n_out == nullptr || (out == nullptr && max_out > 0))
+        return -2;
+    h->profiling = false;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    std::vector<rtri_kernel_stat> agg;
+    for (const ProfRec &r : h->recs) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.e0, r.e1);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        rtri_kernel_stat *slot = nullptr;
+        for (auto &a : agg)
+            if (a.kclass == r.kclass && a.dtype == r.dtype)
+                slot = &a;
+        if (slot == nullptr) {
+            agg.push_back(rtri_kernel_stat{r.kclass, r.dtype, 0, 0.0, 0.0, 0.0});
+            slot = &agg.back();
+        }
+        slot->launches += 1;
+        slot->ms += ms;
+        slot->flops += r.flops;
+        slot->bytes += r.bytes;
+    }
+    h->recs.clear();
+    h->pool_used = 0;
+    const int n = std::min<int>((int)agg.size(), std::max(0, max_out));
+    for (int i = 0; i < n; ++i)
+        out[i] = agg[i];
+    *n_out = n;
     return RTRI_OK;
 }
 
@@ -414,7 +591,8 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
     g.C = C;
     g.ldc = ldc;
     const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
-    hipError_t e = launch_gemm(t, g, h->gemm_tile, h->stream);
+    hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, t == DType::F64 ? 8 : 4),
+                         [&] { return launch_gemm(t, g, h->gemm_tile, h->stream); });
     return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
 }
 

@@ -6,8 +6,8 @@
 // wavefront owns a WMxWN block of C held in MFMA accumulators and built from
 // 16x16 MFMA blocks (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).  Operand
 // tiles of BK values along K are staged through LDS with a two-slot ring so the
-// global loads of step k+1 overlap the MFMAs of step k.  LDS rows are padded so
-// the 16-byte fragment reads are bank-conflict free.
+// global loads of step k+1 overlap the MFMAs of step k; each tile keeps its
+// global layout in LDS (padded), so the copy is a straight coalesced move.
 //
 // MFMA 16x16x4 operand layout (lane l, g = l/16, c = l%16):
 //   A operand: A[c][g]   B operand: B[g][c]
@@ -45,8 +45,22 @@ template <> struct Acc<float> {
     static __device__ inline int row(int g, int r) { return 4 * g + r; }
 };
 
-// padded LDS row length (elements) of a BK-wide operand tile
-template <typename T> constexpr int lds_row() { return sizeof(T) == 8 ? BK + 2 : BK + 4; }
+// LDS layout of an operand tile (R rows of M or N, BK along K) follows its
+// layout in global memory, so the global -> LDS copy never transposes:
+//   KC (k contiguous in memory):    Ls[row * SK + k],  SK = BK + pad
+//   MC (rows contiguous in memory): Ls[k * SM + row],  SM = R + 16
+// The paddings make the MFMA fragment reads bank-conflict free: 16-byte reads
+// of k pairs in the KC layout, 8-byte reads of 16 consecutive rows per lane
+// group (groups 1152 B apart) in the MC layout.
+template <typename T> constexpr int lds_sk() { return sizeof(T) == 8 ? BK + 2 : BK + 4; }
+template <int R> constexpr int lds_sm() { return R + 16; }
+template <typename T, int R, bool KC> constexpr int lds_elems() { return KC ? R * lds_sk<T>() : BK * lds_sm<R>(); }
+
+template <typename T, int R, bool KC>
+__device__ __forceinline__ T lds_at(const T *ls, int row, int k)
+{
+    return KC ? ls[row * lds_sk<T>() + k] : ls[k * lds_sm<R>() + row];
+}
 
 // Loader of one operand tile (R rows of the M or N dimension, BK along K) into
 // registers, then into LDS as Ls[row][k] (k contiguous, padded rows).
@@ -116,20 +130,14 @@ struct TileLoader {
 
     __device__ inline void store(T *lds, int tid) const
     {
-        constexpr int S = lds_row<T>();
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             int row, k;
             coords(v, tid, row, k);
-            if (KC) {
+            T *dst = KC ? lds + row * lds_sk<T>() + k : lds + k * lds_sm<R>() + row;
 #pragma unroll
-                for (int w = 0; w < W; ++w)
-                    lds[row * S + k + w] = reg[v * W + w];
-            } else {
-#pragma unroll
-                for (int w = 0; w < W; ++w)
-                    lds[(row + w) * S + k] = reg[v * W + w];
-            }
+            for (int w = 0; w < W; ++w)
+                dst[w] = reg[v * W + w];
         }
     }
 };
@@ -138,12 +146,12 @@ struct TileLoader {
 template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmDesc g, int tiles_m, int tiles_n)
 {
-    constexpr int S = lds_row<T>();
     constexpr int FM = BM / 32, FN = BN / 32;
+    constexpr bool KCA = TP, KCB = !TQ;           // operand layouts (see lds_at)
     using AccT = Acc<T>;
     using V = typename AccT::V;
-    __shared__ __attribute__((aligned(16))) T As[2][BM * S];
-    __shared__ __attribute__((aligned(16))) T Bs[2][BN * S];
+    __shared__ __attribute__((aligned(16))) T As[2][lds_elems<T, BM, KCA>()];
+    __shared__ __attribute__((aligned(16))) T Bs[2][lds_elems<T, BN, KCB>()];
 
     // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to
     // the 8 XCDs, so regroup them so each XCD walks a contiguous range of
@@ -219,20 +227,19 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmDesc g, int tiles_m, in
 
         // fragments: lane (lc, lg) reads row (block*16 + lc), k = 4*lg .. 4*lg+3,
         // two k values at a time (one 16-byte read for FP64)
-        const T *as = As[cur] + (wm * (BM / 2) + lc) * S + 4 * lg;
-        const T *bs = Bs[cur] + (wn * (BN / 2) + lc) * S + 4 * lg;
+        const int ra = wm * (BM / 2) + lc, rbq = wn * (BN / 2) + lc;
 #pragma unroll
         for (int t2 = 0; t2 < 4; t2 += 2) {
             T fa[FM][2], fb[FN][2];
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
-                fa[i][0] = as[i * 16 * S + t2];
-                fa[i][1] = as[i * 16 * S + t2 + 1];
+                fa[i][0] = lds_at<T, BM, KCA>(As[cur], ra + i * 16, 4 * lg + t2);
+                fa[i][1] = lds_at<T, BM, KCA>(As[cur], ra + i * 16, 4 * lg + t2 + 1);
             }
 #pragma unroll
             for (int j = 0; j < FN; ++j) {
-                fb[j][0] = bs[j * 16 * S + t2];
-                fb[j][1] = bs[j * 16 * S + t2 + 1];
+                fb[j][0] = lds_at<T, BN, KCB>(Bs[cur], rbq + j * 16, 4 * lg + t2);
+                fb[j][1] = lds_at<T, BN, KCB>(Bs[cur], rbq + j * 16, 4 * lg + t2 + 1);
             }
 #pragma unroll
             for (int t = 0; t < 2; ++t)
@@ -308,9 +315,10 @@ hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st)
     const int64_t w = t == DType::F64 ? 2 : 4;
     const bool vec = aligned16(g.P) && aligned16(g.Q) && g.ldp % w == 0 && g.ldq % w == 0;
     if (tile == 0) {
-        // enough 128x128 tiles to cover the 256 CUs at least once, else 64x64
+        // 128x128 tiles once they fill the chip (2 workgroups on each of the
+        // 256 CUs) at least twice over; smaller problems run 64x64 tiles
         const int64_t big = ((g.M + 127) / 128) * ((g.N + 127) / 128);
-        tile = big >= 256 ? 1 : 2;
+        tile = big >= 1024 ? 1 : 2;
     }
     if (t == DType::F64)
         return tile == 1 ? launch_tile<double, 128, 128>(g, vec, st) : launch_tile<double, 64, 64>(g, vec, st);

@@ -6,11 +6,17 @@
 // has a large register file, so here each lane owns one whole vector (a column
 // of B for side = L, a row of B for side = R) and keeps it in registers: the
 // row-to-row dependency becomes a register dependency inside one lane and needs
-// no barrier.  The diagonal block is staged once per workgroup in LDS, in a
-// canonical lower-triangular column-major layout, and read back as wave-uniform
-// broadcasts.  Upper-triangular blocks are handled by reversing the row order
-// (canonical row i <-> block row nb-1-i), transposed blocks by the order of the
-// global reads, so one kernel covers every side / uplo / trans combination.
+// no barrier.  The panel is transposed through LDS so that both the global
+// reads and writes are coalesced whichever side is solved.
+//
+// The diagonal block is wave-uniform data.  One pack pass per call writes every
+// diagonal block in a canonical lower-triangular packed form (upper blocks with
+// reversed row order, transposed blocks transposed), laid out in the order the
+// leaf consumes it: column by column, diagonal entry first, ascending columns
+// for the solve and descending for the multiply.  The leaf copies its block
+// into LDS and streams it through a small register ring, issuing the broadcast
+// LDS reads several chunks ahead of their use so their latency is hidden behind
+// the FMAs of the chunks before.
 //
 // Solve (right-looking forward substitution, IEEE division by the diagonal):
 //     b := alpha*b;  for k: x_k = b_k / L(k,k);  b_i -= L(i,k) x_k  (i > k)
@@ -24,56 +30,145 @@ namespace {
 
 constexpr int WAVE = 64;
 
-// packed canonical lower triangle, column-major: L(i,k), i >= k, at colstart(k) + (i - k)
-template <int NB> __host__ __device__ constexpr int colstart(int k) { return k * NB - k * (k - 1) / 2; }
-template <int NB> constexpr int tri_elems() { return NB * (NB + 1) / 2; }
+template <int NB> constexpr int tri_n() { return NB * (NB + 1) / 2; }
+// start of column k in the stream: ascending columns (solve) or descending (multiply)
+template <int NB, bool ASC> __host__ __device__ constexpr int colstart(int k)
+{
+    return ASC ? k * NB - k * (k - 1) / 2 : (NB - 1 - k) * (NB - k) / 2;
+}
+
+// one workgroup per diagonal block
+template <typename T, int NB, bool ASC>
+__global__ __launch_bounds__(256) void pack_kernel(PackDesc p)
+{
+    const int64_t d0 = (int64_t)blockIdx.x * NB;
+    const int nb = (int)min<int64_t>(NB, p.ka - d0);
+    const T *A = static_cast<const T *>(p.A) + d0 + d0 * p.lda;
+    T *out = static_cast<T *>(p.out) + (int64_t)blockIdx.x * tri_n<NB>();
+    for (int e = threadIdx.x; e < NB * NB; e += 256) {
+        const int i = e % NB, k = e / NB;
+        if (i < k)
+            continue;
+        T v = (i == k) ? T(1) : T(0);
+        if (i < nb && (i > k || !p.unit)) {
+            const int r = p.mlower ? i : nb - 1 - i;
+            const int c = p.mlower ? k : nb - 1 - k;
+            v = p.mtrans ? A[c + (int64_t)r * p.lda] : A[r + (int64_t)c * p.lda];
+        }
+        out[colstart<NB, ASC>(k) + (i - k)] = v;
+    }
+}
+
+// Stream the packed block from LDS through a register ring of D chunks of CH
+// values; chunk c + D is requested as soon as chunk c is used up.
+template <typename T, int NB, bool SOLVE, bool UNIT>
+__device__ __forceinline__ void leaf_compute(T (&b)[NB], const T *Ls)
+{
+    constexpr int TOT = tri_n<NB>();
+    constexpr int CH = 8, D = 4;
+    constexpr int NCH = (TOT + CH - 1) / CH;
+    T ring[D][CH];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int j = 0; j < CH; ++j)
+            if (c < NCH && c * CH + j < TOT)
+                ring[c][j] = Ls[c * CH + j];
+    int f = 0;   // stream position (a compile-time constant once unrolled)
+    T x = T(0), dk = T(1);
+#pragma unroll
+    for (int kk = 0; kk < NB; ++kk) {
+        const int k = SOLVE ? kk : NB - 1 - kk;
+        if (!SOLVE)
+            x = b[k];
+#pragma unroll
+        for (int i = k; i < NB; ++i) {
+            const T v = ring[(f / CH) % D][f % CH];
+            if (i == k) {
+                if (SOLVE) {
+                    if (!UNIT)
+                        b[k] = b[k] / v;
+                    x = b[k];
+                } else {
+                    dk = v;
+                }
+            } else {
+                b[i] = SOLVE ? fmat(-v, x, b[i]) : fmat(v, x, b[i]);
+            }
+            ++f;
+            if (f % CH == 0) {
+                const int c = f / CH - 1 + D;     // the chunk that reuses the slot just freed
+                if (c < NCH) {
+#pragma unroll
+                    for (int j = 0; j < CH; ++j)
+                        if (c * CH + j < TOT)
+                            ring[c % D][j] = Ls[c * CH + j];
+                }
+                // keep the LDS reads where they are; arithmetic may move across
+                __builtin_amdgcn_sched_barrier(0x7);
+            }
+        }
+        if (!SOLVE && !UNIT)
+            b[k] = dk * x;
+    }
+}
 
 template <typename T, int NB, bool SOLVE, bool UNIT>
-__global__ __launch_bounds__(WAVE) void leaf_kernel(LeafDesc d)
+__global__ __launch_bounds__(WAVE) void leaf_kernel(LeafDesc d, const T *__restrict__ L, T *__restrict__ B)
 {
     static_assert(NB <= WAVE, "one lane per block row when staging");
     constexpr int PS = NB + 1;                  // padded panel stride (odd: no bank conflicts)
-    __shared__ T Ls[tri_elems<NB>()];           // the diagonal block, canonical lower
     __shared__ T Ps[WAVE * PS];                 // the panel: vector v, canonical row i at Ps[v*PS + i]
+    __shared__ __attribute__((aligned(16))) T Ls[tri_n<NB>()];   // the packed block, in stream order
 
     const int lane = threadIdx.x;
     const int nb = d.nb;
-    const T *A = static_cast<const T *>(d.A);
-    const int64_t lda = d.lda;
 
-    // stage the block: L(i,k) = Mx(p(i), p(k)) with p(i) = i (lower) or nb-1-i (upper);
-    // rows beyond nb are padded with the identity so they are inert
-    for (int k = 0; k < NB; ++k) {
-        for (int i = k + lane; i < NB; i += WAVE) {
-            T v = T(0);
-            if (i == k) {
-                v = T(1);
-                if (!UNIT && i < nb) {
-                    const int r = d.mlower ? i : nb - 1 - i;
-                    v = A[r + (int64_t)r * lda];
-                }
-            } else if (i < nb) {
-                const int r = d.mlower ? i : nb - 1 - i;
-                const int c = d.mlower ? k : nb - 1 - k;
-                v = d.mtrans ? A[c + (int64_t)r * lda] : A[r + (int64_t)c * lda];
-            }
-            Ls[colstart<NB>(k) + (i - k)] = v;
-        }
-    }
+    // Stage the packed block (contiguous) and the panel into LDS.  All global
+    // loads of both are issued before the first LDS store so that their
+    // latencies overlap.  The panel is read coalesced: lanes run along
+    // whichever of its two dimensions is contiguous in memory.
+    constexpr int TOT = tri_n<NB>();
+    constexpr int PER = (TOT + WAVE - 1) / WAVE;
+    T tv[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j)
+        tv[j] = (j * WAVE + lane < TOT) ? L[j * WAVE + lane] : T(0);
 
-    // stage the panel with coalesced reads: lanes run along whichever of the two
-    // panel dimensions is contiguous in memory
     const int64_t v0 = (int64_t)blockIdx.x * WAVE;
     const int nv = (int)min<int64_t>(WAVE, d.nvec - v0);
-    T *B = static_cast<T *>(d.B);
     const bool along_d = d.sd == 1;
-    for (int it = 0; it < (along_d ? WAVE : NB); ++it) {
-        const int dd = along_d ? lane : it;      // element index in block order
-        const int vv = along_d ? it : lane;      // vector index within this workgroup
-        if (dd < nb && vv < nv) {
-            const int ci = d.mlower ? dd : nb - 1 - dd;
-            Ps[vv * PS + ci] = B[(v0 + vv) * d.si + (int64_t)dd * d.sd];
-        }
+    if (along_d) {
+        // side L: lane = element of a column, one column per step
+        const int dd = lane;
+        const int ci = d.mlower ? dd : nb - 1 - dd;
+        T pv[WAVE];
+#pragma unroll
+        for (int vv = 0; vv < WAVE; ++vv)
+            pv[vv] = (dd < nb && vv < nv) ? B[(v0 + vv) * d.si + dd] : T(0);
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (j * WAVE + lane < TOT)
+                Ls[j * WAVE + lane] = tv[j];
+#pragma unroll
+        for (int vv = 0; vv < WAVE; ++vv)
+            if (dd < nb)
+                Ps[vv * PS + ci] = pv[vv];
+    } else {
+        // side R: lane = one row of B, one column per step
+        const int vv = lane;
+        T pv[NB];
+#pragma unroll
+        for (int dd = 0; dd < NB; ++dd)
+            pv[dd] = (dd < nb && vv < nv) ? B[(v0 + vv) * d.si + (int64_t)dd * d.sd] : T(0);
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (j * WAVE + lane < TOT)
+                Ls[j * WAVE + lane] = tv[j];
+#pragma unroll
+        for (int dd = 0; dd < NB; ++dd)
+            if (dd < nb)
+                Ps[vv * PS + (d.mlower ? dd : nb - 1 - dd)] = pv[dd];
     }
     __syncthreads();
 
@@ -87,25 +182,9 @@ __global__ __launch_bounds__(WAVE) void leaf_kernel(LeafDesc d)
 #pragma unroll
         for (int i = 0; i < NB; ++i)
             b[i] *= alpha;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            if (!UNIT)
-                b[k] = b[k] / Ls[colstart<NB>(k)];
-            const T x = b[k];
-#pragma unroll
-            for (int i = k + 1; i < NB; ++i)
-                b[i] = fmat(-Ls[colstart<NB>(k) + (i - k)], x, b[i]);
-        }
+        leaf_compute<T, NB, true, UNIT>(b, Ls);
     } else {
-#pragma unroll
-        for (int k = NB - 1; k >= 0; --k) {
-            const T x = b[k];
-#pragma unroll
-            for (int i = k + 1; i < NB; ++i)
-                b[i] = fmat(Ls[colstart<NB>(k) + (i - k)], x, b[i]);
-            if (!UNIT)
-                b[k] = Ls[colstart<NB>(k)] * x;
-        }
+        leaf_compute<T, NB, false, UNIT>(b, Ls);
 #pragma unroll
         for (int i = 0; i < NB; ++i)
             b[i] *= alpha;
@@ -115,13 +194,19 @@ __global__ __launch_bounds__(WAVE) void leaf_kernel(LeafDesc d)
     for (int i = 0; i < NB; ++i)
         Ps[lane * PS + i] = b[i];
     __syncthreads();
-    for (int it = 0; it < (along_d ? WAVE : NB); ++it) {
-        const int dd = along_d ? lane : it;
-        const int vv = along_d ? it : lane;
-        if (dd < nb && vv < nv) {
-            const int ci = d.mlower ? dd : nb - 1 - dd;
-            B[(v0 + vv) * d.si + (int64_t)dd * d.sd] = Ps[vv * PS + ci];
-        }
+    if (along_d) {
+        const int dd = lane;
+        const int ci = d.mlower ? dd : nb - 1 - dd;
+#pragma unroll
+        for (int vv = 0; vv < WAVE; ++vv)
+            if (dd < nb && vv < nv)
+                B[(v0 + vv) * d.si + dd] = Ps[vv * PS + ci];
+    } else {
+        const int vv = lane;
+#pragma unroll
+        for (int dd = 0; dd < NB; ++dd)
+            if (dd < nb && vv < nv)
+                B[(v0 + vv) * d.si + (int64_t)dd * d.sd] = Ps[vv * PS + (d.mlower ? dd : nb - 1 - dd)];
     }
 }
 
@@ -129,21 +214,54 @@ template <typename T, int NB>
 hipError_t launch_nb(bool solve, const LeafDesc &l, hipStream_t st)
 {
     const dim3 grid((unsigned)((l.nvec + WAVE - 1) / WAVE));
+    const T *L = static_cast<const T *>(l.Lp);
+    T *B = static_cast<T *>(l.B);
     if (solve) {
         if (l.unit)
-            hipLaunchKernelGGL((leaf_kernel<T, NB, true, true>), grid, dim3(WAVE), 0, st, l);
+            hipLaunchKernelGGL((leaf_kernel<T, NB, true, true>), grid, dim3(WAVE), 0, st, l, L, B);
         else
-            hipLaunchKernelGGL((leaf_kernel<T, NB, true, false>), grid, dim3(WAVE), 0, st, l);
+            hipLaunchKernelGGL((leaf_kernel<T, NB, true, false>), grid, dim3(WAVE), 0, st, l, L, B);
     } else {
         if (l.unit)
-            hipLaunchKernelGGL((leaf_kernel<T, NB, false, true>), grid, dim3(WAVE), 0, st, l);
+            hipLaunchKernelGGL((leaf_kernel<T, NB, false, true>), grid, dim3(WAVE), 0, st, l, L, B);
         else
-            hipLaunchKernelGGL((leaf_kernel<T, NB, false, false>), grid, dim3(WAVE), 0, st, l);
+            hipLaunchKernelGGL((leaf_kernel<T, NB, false, false>), grid, dim3(WAVE), 0, st, l, L, B);
     }
     return hipGetLastError();
 }
 
+template <typename T, int NB>
+hipError_t pack_nb(bool solve, const PackDesc &p, hipStream_t st)
+{
+    const unsigned nblk = (unsigned)((p.ka + NB - 1) / NB);
+    if (solve)
+        hipLaunchKernelGGL((pack_kernel<T, NB, true>), dim3(nblk), dim3(256), 0, st, p);
+    else
+        hipLaunchKernelGGL((pack_kernel<T, NB, false>), dim3(nblk), dim3(256), 0, st, p);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_pack(DType t, bool solve, int nbmax, const PackDesc &p, hipStream_t st)
+{
+    if (p.ka <= 0)
+        return hipSuccess;
+    if (t == DType::F64) {
+        switch (nbmax) {
+        case 16: return pack_nb<double, 16>(solve, p, st);
+        case 32: return pack_nb<double, 32>(solve, p, st);
+        case 64: return pack_nb<double, 64>(solve, p, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (nbmax) {
+    case 16: return pack_nb<float, 16>(solve, p, st);
+    case 32: return pack_nb<float, 32>(solve, p, st);
+    case 64: return pack_nb<float, 64>(solve, p, st);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st)
 {

@@ -58,7 +58,11 @@ def tri(m: int, uplo: str, g: np.random.Generator, diag_kind: str = "base",
       "unit"   off-diagonals U(-1,1)/m, diagonal = ``fill`` (never read with diag=U)
     """
     uplo = uplo.upper()
-    a = _u11(g, (m, m))
+    # draw in column-major order directly (the transpose of a C-order draw is
+    # Fortran-ordered), then shape it in place, one column at a time
+    a = g.random((m, m)).T
+    a *= 2.0
+    a -= 1.0
     d = g.random(m)
     if diag_kind == "base":
         dv = m + d
@@ -69,14 +73,17 @@ def tri(m: int, uplo: str, g: np.random.Generator, diag_kind: str = "base",
             raise ValueError("diag_kind='cond' needs c")
         dv = c + d
     elif diag_kind == "unit":
-        a = a / m
+        a /= m
         dv = np.full(m, fill)
     else:
         raise ValueError(diag_kind)
-    mask = np.tril(np.ones((m, m), dtype=bool), -1) if uplo == "L" else np.triu(np.ones((m, m), dtype=bool), 1)
-    out = np.where(mask, a, fill)
-    out[np.arange(m), np.arange(m)] = dv
-    return np.asfortranarray(out)
+    for j in range(m):
+        if uplo == "L":
+            a[:j, j] = fill
+        else:
+            a[j + 1:, j] = fill
+        a[j, j] = dv[j]
+    return a
 
 
 def dense(m: int, n: int, g: np.random.Generator) -> np.ndarray:
