@@ -30,6 +30,9 @@
  *   TRSM  normwise backward error per column (Rigal-Gaches)
  *           eta_j = |alpha b_j - op(A) x_j|_inf / (|op(A)|_inf |x_j|_inf + |alpha| |b_j|_inf)
  *   TRMM  eta_j = |c^_j - c_j|_inf / (|alpha| |op(A)|_inf |b_j|_inf)
+ *   For side = R a row x_i of X solves the transposed system op(A)^T x_i^T =
+ *   alpha b_i^T, so rows take the place of columns and |op(A)^T|_inf =
+ *   |op(A)|_1 (largest column sum) takes the place of |op(A)|_inf.
  *   Residuals and the reference TRMM product used for the metrics are summed
  *   with the compensated dot product Dot2 (Ogita, Rump, Oishi, SIAM J. Sci.
  *   Comput. 2005), so their own rounding error (about u^2 * cond) is far below
@@ -195,6 +198,8 @@ static inline double dot2_value(const dot2_acc *acc)
     return acc->s + acc->c;
 }
 
+double oracle_opnorm_one(int uplo, int trans, int diag, int64_t ka, const double *A, int64_t lda);
+
 /* |op(A)|_inf: largest absolute row sum of the effective triangle (unit diagonal counts as 1) */
 double oracle_opnorm_inf(int uplo, int trans, int diag, int64_t ka, const double *A, int64_t lda)
 {
@@ -310,7 +315,8 @@ double oracle_trsm_eta(int side, int uplo, int trans, int diag, int64_t m, int64
     int64_t ka = side == 0 ? m : n;
     double *R = (double *)malloc(sizeof(double) * (size_t)(m * n));
     oracle_trsm_residual(side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb, X, ldx, R, m);
-    double an = oracle_opnorm_inf(uplo, trans, diag, ka, A, lda);
+    double an = side == 0 ? oracle_opnorm_inf(uplo, trans, diag, ka, A, lda)
+                          : oracle_opnorm_one(uplo, trans, diag, ka, A, lda);
     int64_t nvec = side == 0 ? n : m;
     double worst = 0.0;
     for (int64_t v = 0; v < nvec; ++v) {
@@ -350,7 +356,8 @@ double oracle_trmm_eta(int side, int uplo, int trans, int diag, int64_t m, int64
     int64_t ka = side == 0 ? m : n;
     double *C = (double *)malloc(sizeof(double) * (size_t)(m * n));
     oracle_trmm_dot2(side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb, C, m);
-    double an = oracle_opnorm_inf(uplo, trans, diag, ka, A, lda);
+    double an = side == 0 ? oracle_opnorm_inf(uplo, trans, diag, ka, A, lda)
+                          : oracle_opnorm_one(uplo, trans, diag, ka, A, lda);
     int64_t nvec = side == 0 ? n : m;
     double worst = 0.0;
     for (int64_t v = 0; v < nvec; ++v) {

@@ -295,6 +295,26 @@ def test_trmm_eta_definition(orc):
     assert orc.trmm_eta("L", "U", "N", "N", 1.0, A, B, C2) == pytest.approx(1.0 / den, rel=1e-12)
 
 
+def test_eta_side_right_uses_row_systems(orc):
+    """For side R the backward error of row i is that of the transposed system
+    op(A)^T x_i^T = alpha b_i^T: the eta of X for (R, A) equals the eta of X^T
+    for (L, A, flipped trans)."""
+    g = RNG(14)
+    m, n = 7, 11
+    A = synth.tri(n, "U", g, "stress")
+    B = synth.dense(m, n, g)
+    X = orc.trsm("R", "U", "N", "N", 1.0, A, B)
+    X[2, 5] += 1e-6
+    e_r = orc.trsm_eta("R", "U", "N", "N", 1.0, A, B, X)
+    e_l = orc.trsm_eta("L", "U", "T", "N", 1.0, A, np.asfortranarray(B.T), np.asfortranarray(X.T))
+    assert e_r == pytest.approx(e_l, rel=1e-14)
+    C = orc.trmm("R", "U", "N", "N", 1.0, A, B)
+    C[3, 1] += 1e-6
+    c_r = orc.trmm_eta("R", "U", "N", "N", 1.0, A, B, C)
+    c_l = orc.trmm_eta("L", "U", "T", "N", 1.0, A, np.asfortranarray(B.T), np.asfortranarray(C.T))
+    assert c_r == pytest.approx(c_l, rel=1e-14)
+
+
 def test_cond_one_diagonal(orc):
     d = np.array([1.0, 4.0, 0.5, 2.0])
     A = np.diag(d).copy(order="F")
