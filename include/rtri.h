@@ -155,6 +155,49 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
                      double s, const void *P, int64_t ldp, const void *Q, int64_t ldq, double beta, void *C,
                      int64_t ldc);
 
+/* Triangular multiply with 16-bit inputs and FP32 accumulation, out of place
+ * (eqs. (1)/(2) with the result in a separate matrix):
+ *     C := alpha * op(A) * B   (LEFT)    or    C := alpha * B * op(A)   (RIGHT)
+ * A and B are BF16 or FP16 (a_type == b_type, RTRI_BF16 or RTRI_F16); C is
+ * FP32 (c_type == RTRI_F32), m-by-n with leading dimension ldc.  Every product
+ * of two 16-bit values is exact in FP32 and the sums accumulate in FP32, so the
+ * result is the FP32-accumulated product of the 16-bit inputs.  C must not
+ * overlap A or B; A and B are not modified.
+ * Argument codes: -1..-6 as for rtri_dtrmm, -8 A NULL, -9 lda, -10 B NULL,
+ * -11 ldb < max(1, m), -12 C NULL, -13 ldc < max(1, m); RTRI_ERR_UNSUPPORTED
+ * for any other type combination. */
+int rtri_trmm_ex(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, float alpha,
+                 const void *A, int a_type, int64_t lda, const void *B, int b_type, int64_t ldb, void *C,
+                 int c_type, int64_t ldc);
+
+/* Progress of a mixed-precision solve (host memory). */
+typedef struct {
+    int iters;              /* low-precision solves performed */
+    int converged;          /* 1 if eta <= tol was reached */
+    double eta;             /* normwise backward error of the returned X (max over vectors) */
+    double anorm;           /* |op(A)|_inf (LEFT) or |op(A)|_1 (RIGHT) */
+    double eta_hist[32];    /* eta after each correction */
+} rtri_refine_info;
+
+/* Mixed-precision TRSM with iterative refinement, eqs. (3)/(4) in FP64:
+ * B := X with op(A) X = alpha B (LEFT) or X op(A) = alpha B (RIGHT), where
+ * each correction D solves op(A) D = R / s (or D op(A) = R / s) recursively
+ * with the GEMM updates run in gemm_type (RTRI_BF16 or RTRI_F32) MFMA with
+ * FP32 accumulation and FP32 leaves, and the residual
+ *     R = alpha B - op(A) X   (or alpha B - X op(A))
+ * and the update X += s D are formed in FP64 (s is a power of two scaling R
+ * into range).  Stops when the normwise backward error
+ *     eta = max_v |R_v|inf / (anorm |X_v|inf + |alpha B_v|inf)
+ * (v over columns for LEFT, rows for RIGHT) is <= tol, when eta fails to halve
+ * from one correction to the next, or after max_iter (<= 32) corrections; B
+ * always receives the last iterate.  Host-blocking: one 16-byte device-to-host
+ * read per correction.  Returns RTRI_NOT_CONVERGED (B and *info still filled)
+ * if tol was not reached.  info may be NULL.  Argument codes as rtri_dtrsm;
+ * -13 gemm_type, -14 tol < 0, -15 max_iter not in 1..32. */
+int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha,
+                     const double *A, int64_t lda, double *B, int64_t ldb, int gemm_type, double tol,
+                     int max_iter, rtri_refine_info *info);
+
 #ifdef __cplusplus
 }
 #endif

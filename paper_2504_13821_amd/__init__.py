@@ -63,6 +63,16 @@ rtri_dtrsm = _sig("rtri_dtrsm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp,
 rtri_strsm = _sig("rtri_strsm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
 rtri_dtrmm = _sig("rtri_dtrmm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
 rtri_strmm = _sig("rtri_strmm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
+rtri_trmm_ex = _sig("rtri_trmm_ex", _int, *_OPARGS, ctypes.c_float, _vp, _int, _i64, _vp, _int, _i64, _vp, _int, _i64)
+
+
+class RefineInfo(ctypes.Structure):
+    _fields_ = [("iters", _int), ("converged", _int), ("eta", ctypes.c_double), ("anorm", ctypes.c_double),
+                ("eta_hist", ctypes.c_double * 32)]
+
+
+rtri_dtrsm_mixed = _sig("rtri_dtrsm_mixed", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64, _int,
+                        ctypes.c_double, _int, ctypes.POINTER(RefineInfo))
 rtri_gemm_update = _sig("rtri_gemm_update", _int, _vp, _int, _int, _int, _i64, _i64, _i64, ctypes.c_double, _vp,
                         _i64, _vp, _i64, ctypes.c_double, _vp, _i64)
 
@@ -200,6 +210,38 @@ def gemm_update(h: Handle, trans_p: str, trans_q: str, s, P, Q, beta, C):
     return C
 
 
+def trmm_ex(h: Handle, side, uplo, trans, diag, alpha, A, B, C):
+    """Out of place: C := alpha op(A) B (side 'L') or alpha B op(A) (side 'R'); A, B bfloat16 or float16
+    (same type), C float32; FP32 accumulation."""
+    lda, ldb, ldc = _colmajor(A, "A"), _colmajor(B, "B"), _colmajor(C, "C")
+    t = {torch.bfloat16: BF16, torch.float16: F16}[A.dtype]
+    tb = {torch.bfloat16: BF16, torch.float16: F16}[B.dtype]
+    if C.dtype != torch.float32:
+        raise TypeError("C must be float32")
+    m, n = C.shape
+    check(rtri_trmm_ex(h.ptr, *codes(side, uplo, trans, diag), m, n, alpha, A.data_ptr(), t, lda, B.data_ptr(), tb,
+                       ldb, C.data_ptr(), F32, ldc), "rtri_trmm_ex")
+    return C
+
+
+def trsm_mixed(h: Handle, side, uplo, trans, diag, alpha, A, B, gemm="bf16", tol=1e-12, max_iter=20,
+               allow_not_converged=False):
+    """In place, FP64: B := X with op(A) X = alpha B (or X op(A) = alpha B) by iterative refinement
+    around a low-precision recursive solve (GEMM updates in 'bf16' or 'f32').  Returns the refinement
+    record as a dict."""
+    lda, ldb = _colmajor(A, "A"), _colmajor(B, "B")
+    if A.dtype != torch.float64 or B.dtype != torch.float64:
+        raise TypeError("A and B must be float64")
+    m, n = B.shape
+    info = RefineInfo()
+    rc = rtri_dtrsm_mixed(h.ptr, *codes(side, uplo, trans, diag), m, n, alpha, A.data_ptr(), lda, B.data_ptr(),
+                          ldb, {"bf16": BF16, "f32": F32}[gemm], tol, max_iter, ctypes.byref(info))
+    if not (rc == OK or (allow_not_converged and rc == NOT_CONVERGED)):
+        check(rc, "rtri_dtrsm_mixed")
+    return dict(status=rc, iters=info.iters, converged=bool(info.converged), eta=info.eta, anorm=info.anorm,
+                eta_hist=list(info.eta_hist[:info.iters]))
+
+
 def to_device(a, dtype=None, device="cuda", ld=None):
     """numpy (any order) -> column-major device tensor of shape (m, n); optional padded leading dimension."""
     import numpy as np
@@ -208,10 +250,14 @@ def to_device(a, dtype=None, device="cuda", ld=None):
     ld = m if ld is None else ld
     dt = dtype if dtype is not None else {np.dtype("float64"): torch.float64, np.dtype("float32"): torch.float32}[a.dtype]
     store = torch.zeros((n, ld), dtype=dt, device=device)
-    store[:, :m] = torch.from_numpy(np.ascontiguousarray(a.T)).to(device=device, dtype=dt)
+    # narrower types are rounded by torch (round to nearest even)
+    store[:, :m] = torch.from_numpy(np.ascontiguousarray(a.T)).to(device=device).to(dtype=dt)
     return store.t()[:m, :]
 
 
 def to_host(t):
-    """column-major device tensor -> numpy Fortran-order array (float64 kept, others as stored)."""
-    return t.t().contiguous().cpu().numpy().T
+    """column-major device tensor -> numpy Fortran-order array (16-bit types widened to float32)."""
+    x = t.t().contiguous()
+    if x.dtype in (torch.bfloat16, torch.float16):
+        x = x.float()
+    return x.cpu().numpy().T

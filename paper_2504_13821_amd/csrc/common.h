@@ -69,10 +69,39 @@ struct LeafDesc {
 inline int64_t tri_elems(int nb) { return (int64_t)nb * (nb + 1) / 2; }
 
 enum class DType { F64, F32 };
+// element types of matrices in memory
+enum class ElemT { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
+inline size_t elem_size(ElemT t) { return t == ElemT::F64 ? 8 : t == ElemT::F32 ? 4 : 2; }
 
 hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st);
-hipError_t launch_pack(DType t, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
+// 16-bit GEMM: the 16-bit operand is P (p16) or Q (!p16); the other operand and C are FP32
+hipError_t launch_gemm16(bool bf16, bool p16, const GemmDesc &g, hipStream_t st);
+// pack diagonal blocks read from A of type src into packed triangles of type dst
+hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);
 hipError_t launch_fill(DType t, void *B, int64_t m, int64_t n, int64_t ldb, double value, hipStream_t st);
+
+// ---- element-wise kernels (HBM-bound) ----
+// Y = fl_dst(scale * X) for an m-by-n matrix (round to nearest even; FP64 -> BF16
+// is rounded once, not through FP32)
+hipError_t launch_convert(ElemT src, ElemT dst, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
+                          int64_t n, double scale, hipStream_t st);
+// X += s * D   (X FP64, D FP32)
+hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,
+                             hipStream_t st);
+// Refinement bookkeeping.  Vectors are columns (by_cols) or rows of the m-by-n
+// matrices.  R = R0 - W; per vector v: eta_v = |R_v|inf / (anorm |X_v|inf + |R0_v|inf);
+// out[0] = max_v eta_v, out[1] = max |R| (both as ordered bit patterns of
+// non-negative doubles, combined with atomicMax; NaN propagates as +NaN bits).
+hipError_t launch_resid_eta(const double *R0, int64_t ld0, const double *W, int64_t ldw, double *R, int64_t ldr,
+                            const double *X, int64_t ldx, int64_t m, int64_t n, bool by_cols, double anorm,
+                            unsigned long long *out, hipStream_t st);
+// out[0] = max over lines of sum |Mx(line, k)| with Mx as in PackDesc (unit diagonal counts 1)
+hipError_t launch_line_norm(const double *A, int64_t lda, int64_t ka, bool mtrans, bool mlower, bool unit,
+                            unsigned long long *out, hipStream_t st);
+// out[0] = max |X|
+hipError_t launch_max_abs(const double *X, int64_t ldx, int64_t m, int64_t n, unsigned long long *out,
+                          hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t st);
 
 }  // namespace rtri

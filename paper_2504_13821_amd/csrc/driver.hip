@@ -1,4 +1,4 @@
-// Recursion driver and the C ABI (include/rtri.h).
+// Recursion driver and the core C ABI (include/rtri.h).
 //
 // The recursion (paper, Sec. 3.1-3.2) splits the triangular factor at its
 // midpoint: two triangular diagonal blocks and one off-diagonal block.  It is
@@ -21,120 +21,18 @@
 //   side R: C = B[t cols], P = B[s cols],    Q = op(A)[s, t]
 //
 // The split point is a multiple of the leaf size (half the block, rounded up),
-// so every leaf but the last one is full and GEMM operands stay aligned.
-#include <algorithm>
+// so every leaf but the last one is full and GEMM operands stay aligned.  The
+// plan is a flat list of launches; one pack pass before it writes every
+// diagonal block in the canonical form the leaf kernel reads.
 #include <cstring>
-#include <vector>
 
-#include "common.h"
+#include "handle.h"
 
 using namespace rtri;
 
 namespace {
-struct ProfRec {
-    int kclass, dtype;
-    double flops, bytes;
-    hipEvent_t e0, e1;
-};
-}  // namespace
-
-struct rtri_handle {
-    uint32_t magic;
-    hipStream_t stream;
-    int leaf_f64, leaf_f32, gemm_tile;
-    hipError_t last;
-    // device workspace owned by the handle (packed diagonal blocks), grown on demand
-    void *ws;
-    size_t ws_bytes;
-    // per-kernel profile (rtri_profile_begin / rtri_profile_end)
-    bool profiling;
-    std::vector<ProfRec> recs;
-    std::vector<hipEvent_t> pool;
-    size_t pool_used;
-};
-
-namespace {
 
 constexpr uint32_t MAGIC = 0x72747269u;  // 'rtri'
-
-bool valid(const rtri_handle *h) { return h != nullptr && h->magic == MAGIC; }
-
-int hip_fail(rtri_handle *h, hipError_t e)
-{
-    h->last = e;
-    return e == hipErrorOutOfMemory ? RTRI_ERR_NOMEM : RTRI_ERR_HIP;
-}
-
-hipError_t pool_event(rtri_handle *h, hipEvent_t *ev)
-{
-    if (h->pool_used == h->pool.size()) {
-        hipEvent_t e;
-        hipError_t err = hipEventCreate(&e);
-        if (err != hipSuccess)
-            return err;
-        h->pool.push_back(e);
-    }
-    *ev = h->pool[h->pool_used++];
-    return hipSuccess;
-}
-
-// Launch through f(); when a profile is open, bracket it with events on the
-// handle's stream and attribute its algorithmic work to a kernel class.
-template <class F>
-hipError_t timed(rtri_handle *h, int kclass, int dtype, double flops, double bytes, F &&f)
-{
-    if (!h->profiling)
-        return f();
-    ProfRec r{kclass, dtype, flops, bytes, nullptr, nullptr};
-    hipError_t e = pool_event(h, &r.e0);
-    if (e == hipSuccess)
-        e = pool_event(h, &r.e1);
-    if (e == hipSuccess)
-        e = hipEventRecord(r.e0, h->stream);
-    if (e != hipSuccess)
-        return e;
-    e = f();
-    if (e != hipSuccess)
-        return e;
-    e = hipEventRecord(r.e1, h->stream);
-    if (e == hipSuccess)
-        h->recs.push_back(r);
-    return e;
-}
-
-// make sure the handle's workspace holds at least `bytes`
-hipError_t ensure_ws(rtri_handle *h, size_t bytes)
-{
-    if (bytes <= h->ws_bytes)
-        return hipSuccess;
-    if (h->ws != nullptr) {
-        hipError_t e = hipStreamSynchronize(h->stream);   // earlier work may still read it
-        if (e != hipSuccess)
-            return e;
-        (void)hipFree(h->ws);
-        h->ws = nullptr;
-        h->ws_bytes = 0;
-    }
-    const size_t want = std::max<size_t>(bytes, (size_t)1 << 20);
-    hipError_t e = hipMalloc(&h->ws, want);
-    if (e != hipSuccess) {
-        h->ws = nullptr;
-        return e;
-    }
-    h->ws_bytes = want;
-    return hipSuccess;
-}
-
-double gemm_flops(const GemmDesc &g) { return 2.0 * (double)g.M * (double)g.N * (double)g.K; }
-double gemm_bytes(const GemmDesc &g, size_t es)
-{
-    return (double)es * ((double)g.M * g.K + (double)g.K * g.N + (g.beta == 0.0 ? 1.0 : 2.0) * g.M * g.N);
-}
-double leaf_flops(const LeafDesc &l) { return (double)l.nb * l.nb * (double)l.nvec; }
-double leaf_bytes(const LeafDesc &l, size_t es)
-{
-    return (double)es * ((double)l.nb * (l.nb + 1) / 2.0 + 2.0 * l.nb * (double)l.nvec);
-}
 
 struct Op {
     bool gemm;
@@ -142,34 +40,23 @@ struct Op {
     LeafDesc l;
 };
 
-struct Problem {
-    bool solve;
-    int side, uplo, trans, diag;
-    int64_t m, n;
-    double alpha;
-    const char *A;
-    int64_t lda;
-    char *B;
-    int64_t ldb;
-    size_t es;  // element size in bytes
-    int leaf;
-};
-
-// pointer to op(A)[r0.., c0..] and whether it reads A transposed
-inline const char *tri_block(const Problem &p, int64_t r0, int64_t c0)
+// pointer to op(A)[r0.., c0..] inside the GEMM copy of A
+inline const char *tri_block(const PlanIn &p, int64_t r0, int64_t c0)
 {
-    const int64_t off = p.trans ? c0 + r0 * p.lda : r0 + c0 * p.lda;
-    return p.A + off * (int64_t)p.es;
+    const int64_t off = p.trans ? c0 + r0 * p.ldag : r0 + c0 * p.ldag;
+    return p.Ag + off * (int64_t)elem_size(p.gt);
 }
 
 struct Planner {
-    const Problem &p;
+    const PlanIn &p;
+    size_t es;      // panel element size
     bool low;       // op(A) lower
-    bool forward;   // TRSM order: block 1 before block 2
+    bool forward;   // block 1 before block 2
     std::vector<Op> ops;
 
-    explicit Planner(const Problem &pr) : p(pr)
+    explicit Planner(const PlanIn &pr) : p(pr)
     {
+        es = p.bt == DType::F64 ? 8 : 4;
         low = (p.uplo == RTRI_LOWER) != (p.trans != RTRI_NOTRANS);
         const bool fwd_solve = p.side == RTRI_LEFT ? low : !low;
         forward = p.solve ? fwd_solve : !fwd_solve;
@@ -180,21 +67,22 @@ struct Planner {
         Op op{};
         op.gemm = false;
         LeafDesc &l = op.l;
-        l.Lp = reinterpret_cast<const void *>((d0 / p.leaf) * tri_elems(p.leaf) * (int64_t)p.es);  // offset, rebased later
+        // offset of this block inside the packed workspace; rebased at launch
+        l.Lp = reinterpret_cast<const void *>((intptr_t)((d0 / p.leaf) * tri_elems(p.leaf) * (int64_t)es));
         l.nb = (int)h;
         l.unit = p.diag == RTRI_UNIT;
         l.alpha = alpha;
         if (p.side == RTRI_LEFT) {
-            // Mx = op(A) block;  vectors are columns of B
+            // the block of op(A); vectors are columns of B
             l.mlower = low;
-            l.B = p.B + d0 * (int64_t)p.es;
+            l.B = p.B + d0 * (int64_t)es;
             l.sd = 1;
             l.si = p.ldb;
             l.nvec = p.n;
         } else {
             // x op(A) = alpha b  <=>  op(A)^T x^T = alpha b^T;  vectors are rows of B
             l.mlower = !low;
-            l.B = p.B + d0 * p.ldb * (int64_t)p.es;
+            l.B = p.B + d0 * p.ldb * (int64_t)es;
             l.sd = p.ldb;
             l.si = 1;
             l.nvec = p.m;
@@ -202,7 +90,7 @@ struct Planner {
         ops.push_back(op);
     }
 
-    // B[t] = beta * B[t] + s * (update from block src)
+    // B[t] = beta * B[t] + s * (off-diagonal block) x B[src]
     void update(int64_t t0, int64_t th, int64_t s0, int64_t sh, double beta, double s)
     {
         Op op{};
@@ -216,22 +104,22 @@ struct Planner {
             g.M = th;
             g.N = p.n;
             g.P = tri_block(p, t0, s0);
-            g.ldp = p.lda;
+            g.ldp = p.ldag;
             g.tp = tr;
-            g.Q = p.B + s0 * (int64_t)p.es;
+            g.Q = p.B + s0 * (int64_t)es;
             g.ldq = p.ldb;
             g.tq = false;
-            g.C = p.B + t0 * (int64_t)p.es;
+            g.C = p.B + t0 * (int64_t)es;
         } else {
             g.M = p.m;
             g.N = th;
-            g.P = p.B + s0 * p.ldb * (int64_t)p.es;
+            g.P = p.B + s0 * p.ldb * (int64_t)es;
             g.ldp = p.ldb;
             g.tp = false;
             g.Q = tri_block(p, s0, t0);
-            g.ldq = p.lda;
+            g.ldq = p.ldag;
             g.tq = tr;
-            g.C = p.B + t0 * p.ldb * (int64_t)p.es;
+            g.C = p.B + t0 * p.ldb * (int64_t)es;
         }
         g.ldc = p.ldb;
         ops.push_back(op);
@@ -259,6 +147,88 @@ struct Planner {
     }
 };
 
+int dtype_code(ElemT t) { return (int)t; }
+
+double gemm_flops(const GemmDesc &g) { return 2.0 * (double)g.M * (double)g.N * (double)g.K; }
+double gemm_bytes(const GemmDesc &g, size_t esp, size_t esq, size_t esc)
+{
+    return (double)esp * g.M * g.K + (double)esq * g.K * g.N + (double)esc * (g.beta == 0.0 ? 1.0 : 2.0) * g.M * g.N;
+}
+double leaf_flops(const LeafDesc &l) { return (double)l.nb * l.nb * (double)l.nvec; }
+double leaf_bytes(const LeafDesc &l, size_t es)
+{
+    return (double)es * ((double)l.nb * (l.nb + 1) / 2.0 + 2.0 * l.nb * (double)l.nvec);
+}
+
+}  // namespace
+
+namespace rtri {
+
+bool handle_valid(const rtri_handle *h) { return h != nullptr && h->magic == MAGIC; }
+
+int hip_fail(rtri_handle *h, hipError_t e)
+{
+    h->last = e;
+    return e == hipErrorOutOfMemory ? RTRI_ERR_NOMEM : RTRI_ERR_HIP;
+}
+
+hipError_t ensure_ws(rtri_handle *h, int slot, size_t bytes)
+{
+    if (bytes <= h->ws_bytes[slot])
+        return hipSuccess;
+    if (h->ws[slot] != nullptr) {
+        hipError_t e = hipStreamSynchronize(h->stream);   // earlier work may still use it
+        if (e != hipSuccess)
+            return e;
+        (void)hipFree(h->ws[slot]);
+        h->ws[slot] = nullptr;
+        h->ws_bytes[slot] = 0;
+    }
+    const size_t want = std::max<size_t>(bytes, (size_t)1 << 16);
+    hipError_t e = hipMalloc(&h->ws[slot], want);
+    if (e != hipSuccess) {
+        h->ws[slot] = nullptr;
+        return e;
+    }
+    h->ws_bytes[slot] = want;
+    return hipSuccess;
+}
+
+hipError_t pool_event(rtri_handle *h, hipEvent_t *ev)
+{
+    if (h->pool_used == h->pool.size()) {
+        hipEvent_t e;
+        hipError_t err = hipEventCreate(&e);
+        if (err != hipSuccess)
+            return err;
+        h->pool.push_back(e);
+    }
+    *ev = h->pool[h->pool_used++];
+    return hipSuccess;
+}
+
+hipError_t timed_launch(rtri_handle *h, int kclass, int dtype, double flops, double bytes, hipError_t (*fn)(void *),
+                        void *ctx)
+{
+    if (!h->profiling)
+        return fn(ctx);
+    ProfRec r{kclass, dtype, flops, bytes, nullptr, nullptr};
+    hipError_t e = pool_event(h, &r.e0);
+    if (e == hipSuccess)
+        e = pool_event(h, &r.e1);
+    if (e == hipSuccess)
+        e = hipEventRecord(r.e0, h->stream);
+    if (e != hipSuccess)
+        return e;
+    e = fn(ctx);
+    if (e != hipSuccess)
+        return e;
+    e = hipEventRecord(r.e1, h->stream);
+    if (e == hipSuccess)
+        h->recs.push_back(r);
+    return e;
+}
+
 int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, const void *A, int64_t lda,
                const void *B, int64_t ldb, bool need_a)
 {
@@ -276,19 +246,83 @@ int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, co
     return 0;
 }
 
-int pick_leaf(const rtri_handle *h, DType t, int64_t ka)
+int pick_leaf(const rtri_handle *h, DType t)
 {
-    int leaf = t == DType::F64 ? h->leaf_f64 : h->leaf_f32;
-    if (leaf == 0)
-        leaf = 64;
-    (void)ka;
-    return leaf;
+    const int leaf = t == DType::F64 ? h->leaf_f64 : h->leaf_f32;
+    return leaf == 0 ? 64 : leaf;
 }
+
+int run_plan(rtri_handle *h, const PlanIn &p)
+{
+    const int64_t ka = p.side == RTRI_LEFT ? p.m : p.n;
+    if (p.m == 0 || p.n == 0)
+        return RTRI_OK;
+    const DType bt = p.bt;
+    const size_t es = bt == DType::F64 ? 8 : 4;
+    const int pcode = bt == DType::F64 ? RTRI_F64 : RTRI_F32;
+    Planner pl(p);
+    pl.rec(0, ka, p.alpha);
+
+    // pack every diagonal block once into the canonical form the leaves read
+    const int64_t nblk = (ka + p.leaf - 1) / p.leaf;
+    if (!p.skip_pack) {
+        hipError_t e0 = ensure_ws(h, p.pack_slot, (size_t)(nblk * tri_elems(p.leaf)) * es);
+        if (e0 != hipSuccess)
+            return hip_fail(h, e0);
+        PackDesc pk{};
+        pk.A = p.As;
+        pk.lda = p.ldas;
+        pk.ka = ka;
+        pk.unit = p.diag == RTRI_UNIT;
+        if (p.side == RTRI_LEFT) {
+            pk.mtrans = p.trans != RTRI_NOTRANS;
+            pk.mlower = pl.low;
+        } else {
+            pk.mtrans = p.trans == RTRI_NOTRANS;
+            pk.mlower = !pl.low;
+        }
+        pk.out = h->ws[p.pack_slot];
+        e0 = timed(h, RTRI_KCLASS_OTHER, dtype_code(p.st), 0.0,
+                   (double)elem_size(p.st) * ka * (double)p.leaf + (double)es * nblk * tri_elems(p.leaf),
+                   [&] { return launch_pack(p.st, bt, p.solve, p.leaf, pk, h->stream); });
+        if (e0 != hipSuccess)
+            return hip_fail(h, e0);
+    }
+    for (Op &op : pl.ops)
+        if (!op.gemm)
+            op.l.Lp = static_cast<const char *>(h->ws[p.pack_slot]) + reinterpret_cast<intptr_t>(op.l.Lp);
+
+    const bool g16 = p.gt == ElemT::BF16 || p.gt == ElemT::F16;
+    const size_t ges = elem_size(p.gt);
+    for (const Op &op : pl.ops) {
+        hipError_t e;
+        if (op.gemm) {
+            const bool left = p.side == RTRI_LEFT;
+            const double bytes = gemm_bytes(op.g, left ? ges : es, left ? es : ges, es);
+            if (g16)
+                e = timed(h, RTRI_KCLASS_GEMM, dtype_code(p.gt), gemm_flops(op.g), bytes,
+                          [&] { return launch_gemm16(p.gt == ElemT::BF16, left, op.g, h->stream); });
+            else
+                e = timed(h, RTRI_KCLASS_GEMM, pcode, gemm_flops(op.g), bytes,
+                          [&] { return launch_gemm(bt, op.g, h->gemm_tile, h->stream); });
+        } else {
+            e = timed(h, p.solve ? RTRI_KCLASS_LEAF_SOLVE : RTRI_KCLASS_LEAF_MULT, pcode, leaf_flops(op.l),
+                      leaf_bytes(op.l, es), [&] { return launch_leaf(bt, p.solve, p.leaf, op.l, h->stream); });
+        }
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+    }
+    return RTRI_OK;
+}
+
+}  // namespace rtri
+
+namespace {
 
 int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
         double alpha, const void *A, int64_t lda, void *B, int64_t ldb)
 {
-    if (!valid(h))
+    if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
     const int rc = check_args(side, uplo, trans, diag, m, n, A, lda, B, ldb, alpha != 0.0);
     if (rc != 0)
@@ -302,7 +336,7 @@ int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int 
                              [&] { return launch_fill(t, B, m, n, ldb, 0.0, h->stream); });
         return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
     }
-    Problem p{};
+    PlanIn p{};
     p.solve = solve;
     p.side = side;
     p.uplo = uplo;
@@ -311,54 +345,19 @@ int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int 
     p.m = m;
     p.n = n;
     p.alpha = alpha;
-    p.A = static_cast<const char *>(A);
-    p.lda = lda;
+    p.bt = t;
     p.B = static_cast<char *>(B);
     p.ldb = ldb;
-    p.es = es;
-    const int64_t ka = side == RTRI_LEFT ? m : n;
-    p.leaf = pick_leaf(h, t, ka);
-    Planner pl(p);
-    pl.rec(0, ka, alpha);
-
-    // pack every diagonal block once into the canonical form the leaves read
-    const int64_t nblk = (ka + p.leaf - 1) / p.leaf;
-    hipError_t e0 = ensure_ws(h, (size_t)(nblk * tri_elems(p.leaf)) * es);
-    if (e0 != hipSuccess)
-        return hip_fail(h, e0);
-    PackDesc pk{};
-    pk.A = A;
-    pk.lda = lda;
-    pk.ka = ka;
-    pk.unit = diag == RTRI_UNIT;
-    if (side == RTRI_LEFT) {
-        pk.mtrans = p.trans != RTRI_NOTRANS;
-        pk.mlower = pl.low;
-    } else {
-        pk.mtrans = p.trans == RTRI_NOTRANS;
-        pk.mlower = !pl.low;
-    }
-    pk.out = h->ws;
-    e0 = timed(h, RTRI_KCLASS_OTHER, dcode, 0.0, (double)es * (ka * (double)p.leaf + nblk * tri_elems(p.leaf)),
-               [&] { return launch_pack(t, solve, p.leaf, pk, h->stream); });
-    if (e0 != hipSuccess)
-        return hip_fail(h, e0);
-    for (Op &op : pl.ops)
-        if (!op.gemm)
-            op.l.Lp = static_cast<const char *>(h->ws) + reinterpret_cast<intptr_t>(op.l.Lp);
-
-    for (const Op &op : pl.ops) {
-        hipError_t e;
-        if (op.gemm)
-            e = timed(h, RTRI_KCLASS_GEMM, dcode, gemm_flops(op.g), gemm_bytes(op.g, es),
-                      [&] { return launch_gemm(t, op.g, h->gemm_tile, h->stream); });
-        else
-            e = timed(h, solve ? RTRI_KCLASS_LEAF_SOLVE : RTRI_KCLASS_LEAF_MULT, dcode, leaf_flops(op.l),
-                      leaf_bytes(op.l, es), [&] { return launch_leaf(t, solve, p.leaf, op.l, h->stream); });
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-    }
-    return RTRI_OK;
+    p.gt = t == DType::F64 ? ElemT::F64 : ElemT::F32;
+    p.Ag = static_cast<const char *>(A);
+    p.ldag = lda;
+    p.st = p.gt;
+    p.As = A;
+    p.ldas = lda;
+    p.leaf = pick_leaf(h, t);
+    p.pack_slot = WS_PACK;
+    p.skip_pack = false;
+    return run_plan(h, p);
 }
 
 }  // namespace
@@ -378,80 +377,38 @@ int rtri_create(rtri_handle **out, void *stream)
     h->leaf_f32 = 0;
     h->gemm_tile = 0;
     h->last = hipSuccess;
+    for (int i = 0; i < WS_COUNT; ++i) {
+        h->ws[i] = nullptr;
+        h->ws_bytes[i] = 0;
+    }
     h->profiling = false;
     h->pool_used = 0;
-    h->ws = nullptr;
-    h->ws_bytes = 0;
     *out = h;
     return RTRI_OK;
 }
 
 int rtri_destroy(rtri_handle *h)
 {
-    if (!valid(h))
+    if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
     h->magic = 0;
+    bool any = false;
+    for (int i = 0; i < WS_COUNT; ++i)
+        any = any || h->ws[i] != nullptr;
+    if (any)
+        (void)hipStreamSynchronize(h->stream);
+    for (int i = 0; i < WS_COUNT; ++i)
+        if (h->ws[i] != nullptr)
+            (void)hipFree(h->ws[i]);
     for (hipEvent_t e : h->pool)
         (void)hipEventDestroy(e);
-    if (h->ws != nullptr) {
-        (void)hipStreamSynchronize(h->stream);
-        (void)hipFree(h->ws);
-    }
     delete h;
-    return RTRI_OK;
-}
-
-int rtri_profile_begin(rtri_handle *h)
-{
-    if (!valid(h))
-        return RTRI_ERR_HANDLE;
-    h->recs.clear();
-    h->pool_used = 0;
-    h->profiling = true;
-    return RTRI_OK;
-}
-
-int rtri_profile_end(rtri_handle *h, rtri_kernel_stat *out, int max_out, int *n_out)
-{
-    if (!valid(h))
-        return RTRI_ERR_HANDLE;
-    if (n_out == nullptr || (out == nullptr && max_out > 0))
-        return -2;
-    h->profiling = false;
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess)
-        return hip_fail(h, e);
-    std::vector<rtri_kernel_stat> agg;
-    for (const ProfRec &r : h->recs) {
-        float ms = 0.f;
-        e = hipEventElapsedTime(&ms, r.e0, r.e1);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        rtri_kernel_stat *slot = nullptr;
-        for (auto &a : agg)
-            if (a.kclass == r.kclass && a.dtype == r.dtype)
-                slot = &a;
-        if (slot == nullptr) {
-            agg.push_back(rtri_kernel_stat{r.kclass, r.dtype, 0, 0.0, 0.0, 0.0});
-            slot = &agg.back();
-        }
-        slot->launches += 1;
-        slot->ms += ms;
-        slot->flops += r.flops;
-        slot->bytes += r.bytes;
-    }
-    h->recs.clear();
-    h->pool_used = 0;
-    const int n = std::min<int>((int)agg.size(), std::max(0, max_out));
-    for (int i = 0; i < n; ++i)
-        out[i] = agg[i];
-    *n_out = n;
     return RTRI_OK;
 }
 
 int rtri_set_stream(rtri_handle *h, void *stream)
 {
-    if (!valid(h))
+    if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
     h->stream = static_cast<hipStream_t>(stream);
     return RTRI_OK;
@@ -459,7 +416,7 @@ int rtri_set_stream(rtri_handle *h, void *stream)
 
 int rtri_sync(rtri_handle *h)
 {
-    if (!valid(h))
+    if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
     hipError_t e = hipStreamSynchronize(h->stream);
     return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
@@ -467,7 +424,7 @@ int rtri_sync(rtri_handle *h)
 
 int rtri_set_option(rtri_handle *h, int option, int64_t value)
 {
-    if (!valid(h))
+    if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
     switch (option) {
     case RTRI_OPT_LEAF_F64:
@@ -475,7 +432,7 @@ int rtri_set_option(rtri_handle *h, int option, int64_t value)
         h->leaf_f64 = (int)value;
         return RTRI_OK;
     case RTRI_OPT_LEAF_F32:
-        if (value != 0 && value != 16 && value != 32 && value != 64 && value != 128) return -3;
+        if (value != 0 && value != 16 && value != 32 && value != 64) return -3;
         h->leaf_f32 = (int)value;
         return RTRI_OK;
     case RTRI_OPT_GEMM_TILE:
@@ -489,7 +446,7 @@ int rtri_set_option(rtri_handle *h, int option, int64_t value)
 
 int rtri_get_option(rtri_handle *h, int option, int64_t *value)
 {
-    if (!valid(h))
+    if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
     if (value == nullptr)
         return -3;
@@ -525,9 +482,57 @@ const char *rtri_status_string(int s)
 
 int rtri_last_hip_error(rtri_handle *h)
 {
-    if (!valid(h))
+    if (!handle_valid(h))
         return -1;
     return (int)h->last;
+}
+
+int rtri_profile_begin(rtri_handle *h)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    h->recs.clear();
+    h->pool_used = 0;
+    h->profiling = true;
+    return RTRI_OK;
+}
+
+int rtri_profile_end(rtri_handle *h, rtri_kernel_stat *out, int max_out, int *n_out)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    if (n_out == nullptr || (out == nullptr && max_out > 0))
+        return -2;
+    h->profiling = false;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    std::vector<rtri_kernel_stat> agg;
+    for (const ProfRec &r : h->recs) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.e0, r.e1);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        rtri_kernel_stat *slot = nullptr;
+        for (auto &a : agg)
+            if (a.kclass == r.kclass && a.dtype == r.dtype)
+                slot = &a;
+        if (slot == nullptr) {
+            agg.push_back(rtri_kernel_stat{r.kclass, r.dtype, 0, 0.0, 0.0, 0.0});
+            slot = &agg.back();
+        }
+        slot->launches += 1;
+        slot->ms += ms;
+        slot->flops += r.flops;
+        slot->bytes += r.bytes;
+    }
+    h->recs.clear();
+    h->pool_used = 0;
+    const int n = std::min<int>((int)agg.size(), std::max(0, max_out));
+    for (int i = 0; i < n; ++i)
+        out[i] = agg[i];
+    *n_out = n;
+    return RTRI_OK;
 }
 
 int rtri_dtrsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha,
@@ -558,7 +563,7 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
                      double s, const void *P, int64_t ldp, const void *Q, int64_t ldq, double beta, void *C,
                      int64_t ldc)
 {
-    if (!valid(h))
+    if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
     if (dtype != RTRI_F64 && dtype != RTRI_F32) return -2;
     if (trans_p != RTRI_NOTRANS && trans_p != RTRI_TRANS && trans_p != RTRI_CONJTRANS) return -3;
@@ -591,7 +596,8 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
     g.C = C;
     g.ldc = ldc;
     const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
-    hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, t == DType::F64 ? 8 : 4),
+    const size_t es = t == DType::F64 ? 8 : 4;
+    hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, es, es, es),
                          [&] { return launch_gemm(t, g, h->gemm_tile, h->stream); });
     return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
 }

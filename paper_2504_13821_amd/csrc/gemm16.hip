@@ -1,0 +1,268 @@
+// 16-bit GEMM update for the low-precision paths:
+//     C(MxN) = beta * C + s * op(P)(MxK) * op(Q)(KxN)
+// One of P, Q (the triangular factor's block) is stored in BF16 or FP16; the
+// other (a block of the right-hand side) and C are FP32 in memory, and that
+// operand is rounded to the 16-bit type (round to nearest even) as it is
+// loaded; products accumulate in FP32 (v_mfma_f32_16x16x32_bf16 / _f16).
+//
+// Used by (a) the TRMM with 16-bit inputs, where the Q block read by every
+// GEMM still holds original 16-bit values so the rounding is exact, and (b)
+// the low-precision solve inside the mixed-precision TRSM, whose GEMM operands
+// are rounded to BF16 by design.
+//
+// Layout: 256-thread workgroups, 128x128 tiles, four 64x64 wavefront tiles of
+// 16x16 MFMA blocks, BK = 32 (one MFMA k-step).  Operand tiles are staged in
+// LDS with k contiguous (rows padded to 40 elements, so the 16-byte fragment
+// reads of 16 consecutive rows fall in distinct banks).
+//
+// MFMA 16x16x32 operand layout (lane l, g = l/16, c = l%16): A operand row c,
+// k = 8g..8g+7; B operand column c, k = 8g..8g+7; D: slot r holds D[4g + r][c].
+#include <type_traits>
+
+#include "common.h"
+
+namespace rtri {
+
+namespace {
+
+constexpr int NT = 256;
+constexpr int BK = 32;
+constexpr int SK = BK + 8;   // padded LDS row (16-bit elements)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+// float -> 16-bit pattern, round to nearest even (NaN stays NaN)
+template <bool BF> __device__ __forceinline__ unsigned short to16(float x);
+template <> __device__ __forceinline__ unsigned short to16<true>(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return (unsigned short)((u >> 16) | 0x40u);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+template <> __device__ __forceinline__ unsigned short to16<false>(float x)
+{
+    const _Float16 h = (_Float16)x;   // v_cvt_f16_f32, round to nearest even
+    return __builtin_bit_cast(unsigned short, h);
+}
+
+template <bool BF> __device__ __forceinline__ float4_t mfma16(u16x8 a, u16x8 b, float4_t c);
+template <> __device__ __forceinline__ float4_t mfma16<true>(u16x8 a, u16x8 b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+template <> __device__ __forceinline__ float4_t mfma16<false>(u16x8 a, u16x8 b, float4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                  0, 0, 0);
+}
+
+// Load one R x BK operand tile into LDS as Ls[row * SK + k] (16-bit).
+//   SRC16: source is 16-bit (P); else FP32 rounded with to16 (Q).
+//   KC:    element (row, k) at base[k + row*ld]; else at base[row + k*ld].
+// Each thread moves PER elements; out-of-range elements are zero.
+template <int R, bool SRC16, bool KC, bool BF>
+struct Loader16 {
+    static constexpr int PER = R * BK / NT;   // 16 for R = 128
+    static constexpr int W = 8;               // elements per chunk
+    static constexpr int NCH = PER / W;
+    unsigned short reg[PER];
+
+    __device__ inline void coords(int v, int tid, int &row, int &k) const
+    {
+        const int e = v * NT + tid;
+        if (KC) {
+            k = (e % (BK / W)) * W;
+            row = e / (BK / W);
+        } else {
+            row = (e % (R / W)) * W;
+            k = e / (R / W);
+        }
+    }
+
+    __device__ inline void load(const void *base_, int64_t ld, int tid, int rlim, int klim, bool full)
+    {
+#pragma unroll
+        for (int v = 0; v < NCH; ++v) {
+            int row, k;
+            coords(v, tid, row, k);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const int rr = KC ? row : row + w;
+                const int kk = KC ? k + w : k;
+                const int64_t off = KC ? kk + (int64_t)rr * ld : rr + (int64_t)kk * ld;
+                unsigned short x = 0;
+                if (full || (rr < rlim && kk < klim)) {
+                    if (SRC16)
+                        x = static_cast<const unsigned short *>(base_)[off];
+                    else
+                        x = to16<BF>(static_cast<const float *>(base_)[off]);
+                }
+                reg[v * W + w] = x;
+            }
+        }
+    }
+
+    __device__ inline void store(unsigned short *lds, int tid) const
+    {
+#pragma unroll
+        for (int v = 0; v < NCH; ++v) {
+            int row, k;
+            coords(v, tid, row, k);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const int rr = KC ? row : row + w;
+                const int kk = KC ? k + w : k;
+                lds[rr * SK + kk] = reg[v * W + w];
+            }
+        }
+    }
+};
+
+template <int BM, int BN, bool TP, bool TQ, bool BF, bool P16>
+__global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, int tiles_n)
+{
+    constexpr int FM = BM / 32, FN = BN / 32;
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][BM * SK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][BN * SK];
+
+    const int ntiles = tiles_m * tiles_n;
+    int bid = blockIdx.x;
+    if ((ntiles & 7) == 0) {
+        const int per = ntiles >> 3;
+        bid = (bid & 7) * per + (bid >> 3);
+    }
+    constexpr int GROUP = 8;
+    const int band = bid / (GROUP * tiles_n);
+    const int first_m = band * GROUP;
+    const int gsize = min(tiles_m - first_m, GROUP);
+    const int in_band = bid - band * GROUP * tiles_n;
+    const int tm = first_m + in_band % gsize;
+    const int tn = in_band / gsize;
+
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lc = lane % 16, lg = lane / 16;
+
+    using PT = typename std::conditional<P16, unsigned short, float>::type;
+    using QT = typename std::conditional<P16, float, unsigned short>::type;
+    const PT *P = static_cast<const PT *>(g.P);
+    const QT *Q = static_cast<const QT *>(g.Q);
+    const int64_t ldp = g.ldp, ldq = g.ldq;
+    const PT *Pt = TP ? P + m0 * ldp : P + m0;
+    const QT *Qt = TQ ? Q + n0 : Q + n0 * ldq;
+    const int rlim_m = (int)min<int64_t>(BM, g.M - m0);
+    const int rlim_n = (int)min<int64_t>(BN, g.N - n0);
+    const bool full_mn = rlim_m == BM && rlim_n == BN;
+
+    Loader16<BM, P16, TP, BF> la;
+    Loader16<BN, !P16, !TQ, BF> lb;
+
+    float4_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t K = g.K;
+    const int nk = (int)((K + BK - 1) / BK);
+    auto load_step = [&](int kt) {
+        const int64_t k0 = (int64_t)kt * BK;
+        const PT *pa = TP ? Pt + k0 : Pt + k0 * ldp;
+        const QT *pb = TQ ? Qt + k0 * ldq : Qt + k0;
+        const int klim = (int)min<int64_t>(BK, K - k0);
+        const bool full = full_mn && klim == BK;
+        la.load(pa, ldp, tid, rlim_m, klim, full);
+        lb.load(pb, ldq, tid, rlim_n, klim, full);
+    };
+
+    if (nk > 0) {
+        load_step(0);
+        la.store(As[0], tid);
+        lb.store(Bs[0], tid);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk)
+            load_step(kt + 1);
+        u16x8 fa[FM], fb[FN];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+            fa[i] = *reinterpret_cast<const u16x8 *>(&As[cur][(wm * (BM / 2) + i * 16 + lc) * SK + 8 * lg]);
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            fb[j] = *reinterpret_cast<const u16x8 *>(&Bs[cur][(wn * (BN / 2) + j * 16 + lc) * SK + 8 * lg]);
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                acc[i][j] = mfma16<BF>(fa[i], fb[j], acc[i][j]);
+        if (kt + 1 < nk) {
+            la.store(As[cur ^ 1], tid);
+            lb.store(Bs[cur ^ 1], tid);
+        }
+        __syncthreads();
+    }
+
+    float *C = static_cast<float *>(g.C);
+    const int64_t ldc = g.ldc;
+    const float beta = (float)g.beta, s = (float)g.s;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int rb = wm * (BM / 2) + i * 16;
+            const int cl = wn * (BN / 2) + j * 16 + lc;
+            if (cl >= rlim_n)
+                continue;
+            float *cp = C + (m0 + rb) + (n0 + cl) * ldc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = 4 * lg + r;
+                if (rb + rr < rlim_m) {
+                    const float v = s * acc[i][j][r];
+                    cp[rr] = (g.beta == 0.0) ? v : fmat(beta, cp[rr], v);
+                }
+            }
+        }
+    }
+}
+
+template <bool TP, bool TQ, bool BF, bool P16>
+hipError_t launch_t16(const GemmDesc &g, hipStream_t st)
+{
+    constexpr int BM = 128, BN = 128;
+    const int tm = (int)((g.M + BM - 1) / BM), tn = (int)((g.N + BN - 1) / BN);
+    hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16>), dim3((unsigned)(tm * tn)), dim3(NT), 0, st, g, tm,
+                       tn);
+    return hipGetLastError();
+}
+
+template <bool BF, bool P16>
+hipError_t launch_bf(const GemmDesc &g, hipStream_t st)
+{
+    if (!g.tp && !g.tq) return launch_t16<false, false, BF, P16>(g, st);
+    if (g.tp && !g.tq) return launch_t16<true, false, BF, P16>(g, st);
+    if (!g.tp && g.tq) return launch_t16<false, true, BF, P16>(g, st);
+    return launch_t16<true, true, BF, P16>(g, st);
+}
+
+}  // namespace
+
+hipError_t launch_gemm16(bool bf16, bool p16, const GemmDesc &g, hipStream_t st)
+{
+    if (g.M <= 0 || g.N <= 0)
+        return hipSuccess;
+    if (bf16)
+        return p16 ? launch_bf<true, true>(g, st) : launch_bf<true, false>(g, st);
+    return p16 ? launch_bf<false, true>(g, st) : launch_bf<false, false>(g, st);
+}
+
+}  // namespace rtri

@@ -1,0 +1,91 @@
+// Handle internals and the recursion plan interface shared by the host sources.
+#pragma once
+
+#include <algorithm>
+#include <type_traits>
+#include <vector>
+
+#include "common.h"
+
+namespace rtri {
+
+struct ProfRec {
+    int kclass, dtype;
+    double flops, bytes;
+    hipEvent_t e0, e1;
+};
+
+// Device workspace slots owned by a handle, each grown on demand.
+enum WsSlot {
+    WS_PACK = 0,     // packed diagonal blocks of the current plan
+    WS_PACK2,        // packed blocks kept across the refinement steps
+    WS_ACOPY,        // converted copy of A (mixed precision)
+    WS_PANEL32,      // FP32 right-hand side of the low-precision solve
+    WS_X,            // FP64 iterate
+    WS_R0,           // FP64 alpha * B
+    WS_R,            // FP64 residual
+    WS_W,            // FP64 op(A) * X
+    WS_SCALARS,      // small reduction results
+    WS_COUNT
+};
+
+// One recursive TRSM / TRMM to run: the panel B (FP64 or FP32), the
+// triangular factor as read by the GEMM updates (same type as the panel, or a
+// 16-bit copy), and the factor as read by the pack pass for the leaves.
+struct PlanIn {
+    bool solve;
+    int side, uplo, trans, diag;   // trans already folded: 'C' -> 'T'
+    int64_t m, n;
+    double alpha;
+    DType bt;                      // panel type (also the leaf arithmetic)
+    char *B;
+    int64_t ldb;
+    ElemT gt;                      // type of the GEMM copy of A
+    const char *Ag;
+    int64_t ldag;
+    ElemT st;                      // type of A as read by the pack pass
+    const void *As;
+    int64_t ldas;
+    int leaf;
+    int pack_slot;                 // workspace slot holding the packed blocks
+    bool skip_pack;                // the packed blocks are already in pack_slot
+};
+
+}  // namespace rtri
+
+struct rtri_handle {
+    uint32_t magic;
+    hipStream_t stream;
+    int leaf_f64, leaf_f32, gemm_tile;
+    hipError_t last;
+    void *ws[rtri::WS_COUNT];
+    size_t ws_bytes[rtri::WS_COUNT];
+    bool profiling;
+    std::vector<rtri::ProfRec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used;
+};
+
+namespace rtri {
+
+bool handle_valid(const rtri_handle *h);
+int hip_fail(rtri_handle *h, hipError_t e);
+hipError_t ensure_ws(rtri_handle *h, int slot, size_t bytes);
+int pick_leaf(const rtri_handle *h, DType t);
+int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, const void *A, int64_t lda,
+               const void *B, int64_t ldb, bool need_a);
+// enqueue a whole plan on the handle's stream (returns an RTRI_* status)
+int run_plan(rtri_handle *h, const PlanIn &p);
+// launch through f(); inside a profile, bracket it with events and record its work
+hipError_t timed_launch(rtri_handle *h, int kclass, int dtype, double flops, double bytes, hipError_t (*fn)(void *),
+                        void *ctx);
+
+template <class F>
+hipError_t timed(rtri_handle *h, int kclass, int dtype, double flops, double bytes, F &&f)
+{
+    using FF = std::remove_reference_t<F>;
+    auto tramp = [](void *c) -> hipError_t { return (*static_cast<FF *>(c))(); };
+    return timed_launch(h, kclass, dtype, flops, bytes, tramp, (void *)&f);
+}
+
+}  // namespace rtri

@@ -37,13 +37,32 @@ template <int NB, bool ASC> __host__ __device__ constexpr int colstart(int k)
     return ASC ? k * NB - k * (k - 1) / 2 : (NB - 1 - k) * (NB - k) / 2;
 }
 
-// one workgroup per diagonal block
-template <typename T, int NB, bool ASC>
+template <ElemT S> __device__ __forceinline__ double ld_src(const void *p, int64_t off);
+template <> __device__ __forceinline__ double ld_src<ElemT::F64>(const void *p, int64_t off)
+{
+    return static_cast<const double *>(p)[off];
+}
+template <> __device__ __forceinline__ double ld_src<ElemT::F32>(const void *p, int64_t off)
+{
+    return static_cast<const float *>(p)[off];
+}
+template <> __device__ __forceinline__ double ld_src<ElemT::BF16>(const void *p, int64_t off)
+{
+    return __uint_as_float((unsigned)static_cast<const unsigned short *>(p)[off] << 16);
+}
+template <> __device__ __forceinline__ double ld_src<ElemT::F16>(const void *p, int64_t off)
+{
+    return (double)__builtin_bit_cast(_Float16, static_cast<const unsigned short *>(p)[off]);
+}
+
+// One workgroup per diagonal block.  The source may be narrower than the
+// packed type (exact widening) or FP64 packed as FP32 (one rounding, to nearest).
+template <ElemT S, typename T, int NB, bool ASC>
 __global__ __launch_bounds__(256) void pack_kernel(PackDesc p)
 {
     const int64_t d0 = (int64_t)blockIdx.x * NB;
     const int nb = (int)min<int64_t>(NB, p.ka - d0);
-    const T *A = static_cast<const T *>(p.A) + d0 + d0 * p.lda;
+    const int64_t base = d0 + d0 * p.lda;
     T *out = static_cast<T *>(p.out) + (int64_t)blockIdx.x * tri_n<NB>();
     for (int e = threadIdx.x; e < NB * NB; e += 256) {
         const int i = e % NB, k = e / NB;
@@ -53,7 +72,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackDesc p)
         if (i < nb && (i > k || !p.unit)) {
             const int r = p.mlower ? i : nb - 1 - i;
             const int c = p.mlower ? k : nb - 1 - k;
-            v = p.mtrans ? A[c + (int64_t)r * p.lda] : A[r + (int64_t)c * p.lda];
+            v = (T)ld_src<S>(p.A, base + (p.mtrans ? c + (int64_t)r * p.lda : r + (int64_t)c * p.lda));
         }
         out[colstart<NB, ASC>(k) + (i - k)] = v;
     }
@@ -230,37 +249,46 @@ hipError_t launch_nb(bool solve, const LeafDesc &l, hipStream_t st)
     return hipGetLastError();
 }
 
-template <typename T, int NB>
+template <ElemT S, typename T, int NB>
 hipError_t pack_nb(bool solve, const PackDesc &p, hipStream_t st)
 {
     const unsigned nblk = (unsigned)((p.ka + NB - 1) / NB);
     if (solve)
-        hipLaunchKernelGGL((pack_kernel<T, NB, true>), dim3(nblk), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((pack_kernel<S, T, NB, true>), dim3(nblk), dim3(256), 0, st, p);
     else
-        hipLaunchKernelGGL((pack_kernel<T, NB, false>), dim3(nblk), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((pack_kernel<S, T, NB, false>), dim3(nblk), dim3(256), 0, st, p);
     return hipGetLastError();
+}
+
+template <ElemT S, typename T>
+hipError_t pack_t(bool solve, int nbmax, const PackDesc &p, hipStream_t st)
+{
+    switch (nbmax) {
+    case 16: return pack_nb<S, T, 16>(solve, p, st);
+    case 32: return pack_nb<S, T, 32>(solve, p, st);
+    case 64: return pack_nb<S, T, 64>(solve, p, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-hipError_t launch_pack(DType t, bool solve, int nbmax, const PackDesc &p, hipStream_t st)
+hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st)
 {
     if (p.ka <= 0)
         return hipSuccess;
-    if (t == DType::F64) {
-        switch (nbmax) {
-        case 16: return pack_nb<double, 16>(solve, p, st);
-        case 32: return pack_nb<double, 32>(solve, p, st);
-        case 64: return pack_nb<double, 64>(solve, p, st);
-        default: return hipErrorInvalidValue;
-        }
+    if (dst == DType::F64) {
+        if (src != ElemT::F64)
+            return hipErrorInvalidValue;
+        return pack_t<ElemT::F64, double>(solve, nbmax, p, st);
     }
-    switch (nbmax) {
-    case 16: return pack_nb<float, 16>(solve, p, st);
-    case 32: return pack_nb<float, 32>(solve, p, st);
-    case 64: return pack_nb<float, 64>(solve, p, st);
-    default: return hipErrorInvalidValue;
+    switch (src) {
+    case ElemT::F64: return pack_t<ElemT::F64, float>(solve, nbmax, p, st);
+    case ElemT::F32: return pack_t<ElemT::F32, float>(solve, nbmax, p, st);
+    case ElemT::BF16: return pack_t<ElemT::BF16, float>(solve, nbmax, p, st);
+    case ElemT::F16: return pack_t<ElemT::F16, float>(solve, nbmax, p, st);
     }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st)

@@ -1,18 +1,241 @@
-// Small element-wise kernels.
+// Element-wise kernels: fills, precision conversions, and the bookkeeping of
+// the mixed-precision refinement (correction update, residual, norms).  All of
+// them are bound by HBM bandwidth: grid-stride loops over 256-thread
+// workgroups, with consecutive threads on consecutive addresses.
 #include "common.h"
 
 namespace rtri {
 
 namespace {
 
+constexpr int NT = 256;
+
+unsigned grid_for(int64_t total)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + NT - 1) / NT, 8192));
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void fill_kernel(T *B, int64_t m, int64_t n, int64_t ldb, T value)
+__global__ __launch_bounds__(NT) void fill_kernel(T *B, int64_t m, int64_t n, int64_t ldb, T value)
 {
     const int64_t total = m * n;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
         const int64_t i = e % m, j = e / m;
         B[i + j * ldb] = value;
     }
+}
+
+// ---- conversions ----
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+        return (unsigned short)((u >> 16) | 0x40u);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// FP64 -> FP32 rounded to odd: truncate, then set the last bit if anything was
+// dropped.  A second rounding (to nearest even) to a format at least two bits
+// narrower then equals a single correct rounding of the FP64 value.
+__device__ __forceinline__ float f64_to_f32_odd(double x)
+{
+    float r = __double2float_rz(x);
+    if ((double)r != x && x == x)
+        r = __uint_as_float(__float_as_uint(r) | 1u);
+    return r;
+}
+
+template <ElemT S> __device__ __forceinline__ double load_as_f64(const void *p, int64_t off);
+template <> __device__ __forceinline__ double load_as_f64<ElemT::F64>(const void *p, int64_t off)
+{
+    return static_cast<const double *>(p)[off];
+}
+template <> __device__ __forceinline__ double load_as_f64<ElemT::F32>(const void *p, int64_t off)
+{
+    return static_cast<const float *>(p)[off];
+}
+template <> __device__ __forceinline__ double load_as_f64<ElemT::BF16>(const void *p, int64_t off)
+{
+    return __uint_as_float((unsigned)static_cast<const unsigned short *>(p)[off] << 16);
+}
+template <> __device__ __forceinline__ double load_as_f64<ElemT::F16>(const void *p, int64_t off)
+{
+    return (double)__builtin_bit_cast(_Float16, static_cast<const unsigned short *>(p)[off]);
+}
+
+template <ElemT D> __device__ __forceinline__ void store_from_f64(void *p, int64_t off, double v);
+template <> __device__ __forceinline__ void store_from_f64<ElemT::F64>(void *p, int64_t off, double v)
+{
+    static_cast<double *>(p)[off] = v;
+}
+template <> __device__ __forceinline__ void store_from_f64<ElemT::F32>(void *p, int64_t off, double v)
+{
+    static_cast<float *>(p)[off] = (float)v;
+}
+template <> __device__ __forceinline__ void store_from_f64<ElemT::BF16>(void *p, int64_t off, double v)
+{
+    static_cast<unsigned short *>(p)[off] = f32_to_bf16_rne(f64_to_f32_odd(v));
+}
+template <> __device__ __forceinline__ void store_from_f64<ElemT::F16>(void *p, int64_t off, double v)
+{
+    const _Float16 h = (_Float16)f64_to_f32_odd(v);
+    static_cast<unsigned short *>(p)[off] = __builtin_bit_cast(unsigned short, h);
+}
+
+// every value of the 16-bit and FP32 formats is exact in FP64 and the scale is a
+// power of two or 1 at every call site, so going through FP64 adds no rounding
+template <ElemT S, ElemT D>
+__global__ __launch_bounds__(NT) void convert_kernel(const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
+                                                     int64_t n, double scale)
+{
+    const int64_t total = m * n;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+        const int64_t i = e % m, j = e / m;
+        const double v = load_as_f64<S>(X, i + j * ldx);
+        store_from_f64<D>(Y, i + j * ldy, scale == 1.0 ? v : scale * v);
+    }
+}
+
+template <ElemT S>
+hipError_t convert_from(ElemT dst, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m, int64_t n,
+                        double scale, hipStream_t st)
+{
+    const dim3 g(grid_for(m * n));
+    switch (dst) {
+    case ElemT::F64: hipLaunchKernelGGL((convert_kernel<S, ElemT::F64>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n, scale); break;
+    case ElemT::F32: hipLaunchKernelGGL((convert_kernel<S, ElemT::F32>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n, scale); break;
+    case ElemT::BF16: hipLaunchKernelGGL((convert_kernel<S, ElemT::BF16>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n, scale); break;
+    case ElemT::F16: hipLaunchKernelGGL((convert_kernel<S, ElemT::F16>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n, scale); break;
+    }
+    return hipGetLastError();
+}
+
+// ---- refinement bookkeeping ----
+
+__device__ __forceinline__ unsigned long long ordered_bits(double v)
+{
+    // non-negative doubles order like their bit patterns; NaN maps above +inf
+    return v != v ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(v);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_xor(v, o, 64);
+        v = (w > v || w != w) ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
+__global__ __launch_bounds__(NT) void add_scaled_kernel(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m,
+                                                        int64_t n, double s)
+{
+    const int64_t total = m * n;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+        const int64_t i = e % m, j = e / m;
+        X[i + j * ldx] += s * (double)D[i + j * ldd];
+    }
+}
+
+// vectors are columns: one wavefront per column, lanes run down the rows
+__global__ __launch_bounds__(NT) void resid_cols_kernel(const double *R0, int64_t ld0, const double *W, int64_t ldw,
+                                                        double *R, int64_t ldr, const double *X, int64_t ldx,
+                                                        int64_t m, int64_t n, double anorm, unsigned long long *out)
+{
+    const int lane = threadIdx.x % 64;
+    const int64_t j = (int64_t)blockIdx.x * (NT / 64) + threadIdx.x / 64;
+    if (j >= n)
+        return;
+    double rn = 0.0, xn = 0.0, bn = 0.0;
+    for (int64_t i = lane; i < m; i += 64) {
+        const double b = R0[i + j * ld0];
+        const double r = b - W[i + j * ldw];
+        R[i + j * ldr] = r;
+        rn = nmax(rn, fabs(r));
+        xn = nmax(xn, fabs(X[i + j * ldx]));
+        bn = nmax(bn, fabs(b));
+    }
+    rn = wave_max(rn);
+    xn = wave_max(xn);
+    bn = wave_max(bn);
+    if (lane == 0) {
+        const double den = anorm * xn + bn;
+        const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? __builtin_inf() : (rn != rn ? rn : 0.0));
+        atomicMax(out, ordered_bits(eta));
+        atomicMax(out + 1, ordered_bits(rn));
+    }
+}
+
+// vectors are rows: one thread per row, walking the columns (coalesced across threads)
+__global__ __launch_bounds__(NT) void resid_rows_kernel(const double *R0, int64_t ld0, const double *W, int64_t ldw,
+                                                        double *R, int64_t ldr, const double *X, int64_t ldx,
+                                                        int64_t m, int64_t n, double anorm, unsigned long long *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    double eta = 0.0, rn = 0.0;
+    if (i < m) {
+        double xn = 0.0, bn = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double b = R0[i + j * ld0];
+            const double r = b - W[i + j * ldw];
+            R[i + j * ldr] = r;
+            rn = nmax(rn, fabs(r));
+            xn = nmax(xn, fabs(X[i + j * ldx]));
+            bn = nmax(bn, fabs(b));
+        }
+        const double den = anorm * xn + bn;
+        eta = den > 0.0 ? rn / den : (rn > 0.0 ? __builtin_inf() : (rn != rn ? rn : 0.0));
+    }
+    eta = wave_max(eta);
+    rn = wave_max(rn);
+    if (threadIdx.x % 64 == 0) {
+        atomicMax(out, ordered_bits(eta));
+        atomicMax(out + 1, ordered_bits(rn));
+    }
+}
+
+// one thread per line of Mx; lines shorter than the matrix skip the unreferenced part
+__global__ __launch_bounds__(NT) void line_norm_kernel(const double *A, int64_t lda, int64_t ka, bool mtrans,
+                                                       bool mlower, bool unit, unsigned long long *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+    double s = 0.0;
+    if (i < ka) {
+        const int64_t k0 = mlower ? 0 : i, k1 = mlower ? i : ka - 1;
+        for (int64_t k = k0; k <= k1; ++k) {
+            if (k == i && unit)
+                s += 1.0;
+            else
+                s += fabs(mtrans ? A[k + i * lda] : A[i + k * lda]);
+        }
+    }
+    s = wave_max(s);
+    if (threadIdx.x % 64 == 0)
+        atomicMax(out, ordered_bits(s));
+}
+
+__global__ __launch_bounds__(NT) void max_abs_kernel(const double *X, int64_t ldx, int64_t m, int64_t n,
+                                                     unsigned long long *out)
+{
+    const int64_t total = m * n;
+    double v = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+        const int64_t i = e % m, j = e / m;
+        v = nmax(v, fabs(X[i + j * ldx]));
+    }
+    v = wave_max(v);
+    if (threadIdx.x % 64 == 0)
+        atomicMax(out, ordered_bits(v));
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int count)
+{
+    for (int i = threadIdx.x; i < count; i += blockDim.x)
+        p[i] = 0ull;
 }
 
 }  // namespace
@@ -21,14 +244,74 @@ hipError_t launch_fill(DType t, void *B, int64_t m, int64_t n, int64_t ldb, doub
 {
     if (m <= 0 || n <= 0)
         return hipSuccess;
-    const int64_t total = m * n;
-    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 4096);
+    const dim3 g(grid_for(m * n));
     if (t == DType::F64)
-        hipLaunchKernelGGL(fill_kernel<double>, dim3(blocks), dim3(256), 0, st, static_cast<double *>(B), m, n, ldb,
-                           value);
+        hipLaunchKernelGGL(fill_kernel<double>, g, dim3(NT), 0, st, static_cast<double *>(B), m, n, ldb, value);
     else
-        hipLaunchKernelGGL(fill_kernel<float>, dim3(blocks), dim3(256), 0, st, static_cast<float *>(B), m, n, ldb,
-                           (float)value);
+        hipLaunchKernelGGL(fill_kernel<float>, g, dim3(NT), 0, st, static_cast<float *>(B), m, n, ldb, (float)value);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(ElemT src, ElemT dst, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
+                          int64_t n, double scale, hipStream_t st)
+{
+    if (m <= 0 || n <= 0)
+        return hipSuccess;
+    switch (src) {
+    case ElemT::F64: return convert_from<ElemT::F64>(dst, X, ldx, Y, ldy, m, n, scale, st);
+    case ElemT::F32: return convert_from<ElemT::F32>(dst, X, ldx, Y, ldy, m, n, scale, st);
+    case ElemT::BF16: return convert_from<ElemT::BF16>(dst, X, ldx, Y, ldy, m, n, scale, st);
+    case ElemT::F16: return convert_from<ElemT::F16>(dst, X, ldx, Y, ldy, m, n, scale, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,
+                             hipStream_t st)
+{
+    if (m <= 0 || n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(add_scaled_kernel, dim3(grid_for(m * n)), dim3(NT), 0, st, X, ldx, D, ldd, m, n, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_resid_eta(const double *R0, int64_t ld0, const double *W, int64_t ldw, double *R, int64_t ldr,
+                            const double *X, int64_t ldx, int64_t m, int64_t n, bool by_cols, double anorm,
+                            unsigned long long *out, hipStream_t st)
+{
+    if (m <= 0 || n <= 0)
+        return hipSuccess;
+    if (by_cols)
+        hipLaunchKernelGGL(resid_cols_kernel, dim3((unsigned)((n + NT / 64 - 1) / (NT / 64))), dim3(NT), 0, st, R0,
+                           ld0, W, ldw, R, ldr, X, ldx, m, n, anorm, out);
+    else
+        hipLaunchKernelGGL(resid_rows_kernel, dim3((unsigned)((m + NT - 1) / NT)), dim3(NT), 0, st, R0, ld0, W, ldw,
+                           R, ldr, X, ldx, m, n, anorm, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_norm(const double *A, int64_t lda, int64_t ka, bool mtrans, bool mlower, bool unit,
+                            unsigned long long *out, hipStream_t st)
+{
+    if (ka <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(line_norm_kernel, dim3((unsigned)((ka + NT - 1) / NT)), dim3(NT), 0, st, A, lda, ka, mtrans,
+                       mlower, unit, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_abs(const double *X, int64_t ldx, int64_t m, int64_t n, unsigned long long *out,
+                          hipStream_t st)
+{
+    if (m <= 0 || n <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(max_abs_kernel, dim3(grid_for(m * n)), dim3(NT), 0, st, X, ldx, m, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long *p, int count, hipStream_t st)
+{
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, st, p, count);
     return hipGetLastError();
 }
 

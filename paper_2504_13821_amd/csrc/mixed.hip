@@ -1,0 +1,275 @@
+// Low-precision entry points built on the recursion driver:
+//   rtri_trmm_ex      TRMM with 16-bit inputs, FP32 accumulation and output
+//   rtri_dtrsm_mixed  FP64 TRSM by iterative refinement around a
+//                     low-precision recursive solve (BF16 or FP32 GEMM updates)
+//
+// Refinement (classical mixed-precision iterative refinement, in the
+// three-precision form: factor / solve precision, working precision FP64,
+// residual precision FP64):
+//     X = 0, R = alpha B
+//     repeat:  s = 2^ceil(log2 max|R|)
+//              D = s * LoSolve(fl32(R / s))       (recursive TRSM, GEMMs in BF16/FP32)
+//              X = X + D                           (FP64)
+//              R = alpha B - op(A) X               (FP64: X copied, TRMM'd, subtracted)
+//              eta = max_v |R_v| / (anorm |X_v| + |alpha B_v|)
+//     until eta <= tol, eta stops halving, or max_iter corrections.
+#include <cmath>
+#include <cstring>
+
+#include "handle.h"
+
+using namespace rtri;
+
+namespace {
+
+double from_bits(unsigned long long b)
+{
+    double d;
+    static_assert(sizeof(d) == sizeof(b), "size");
+    std::memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rtri_trmm_ex(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, float alpha,
+                 const void *A, int a_type, int64_t lda, const void *B, int b_type, int64_t ldb, void *C,
+                 int c_type, int64_t ldc)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    int rc = check_args(side, uplo, trans, diag, m, n, A, lda, B, ldb, alpha != 0.0f);
+    if (rc != 0)
+        return rc;
+    if (m > 0 && n > 0 && C == nullptr)
+        return -12;
+    if (ldc < std::max<int64_t>(1, m))
+        return -13;
+    if (!((a_type == RTRI_BF16 || a_type == RTRI_F16) && b_type == a_type && c_type == RTRI_F32))
+        return RTRI_ERR_UNSUPPORTED;
+    if (m == 0 || n == 0)
+        return RTRI_OK;
+    const ElemT et = a_type == RTRI_BF16 ? ElemT::BF16 : ElemT::F16;
+    hipError_t e;
+    if (alpha == 0.0f) {
+        e = timed(h, RTRI_KCLASS_OTHER, RTRI_F32, 0.0, 4.0 * m * n,
+                  [&] { return launch_fill(DType::F32, C, m, n, ldc, 0.0, h->stream); });
+        return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
+    }
+    // C = B widened to FP32 (exact), then C := alpha op(A) C in place
+    e = timed(h, RTRI_KCLASS_OTHER, a_type, 0.0, 6.0 * m * n,
+              [&] { return launch_convert(et, ElemT::F32, B, ldb, C, ldc, m, n, 1.0, h->stream); });
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    PlanIn p{};
+    p.solve = false;
+    p.side = side;
+    p.uplo = uplo;
+    p.trans = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    p.diag = diag;
+    p.m = m;
+    p.n = n;
+    p.alpha = alpha;
+    p.bt = DType::F32;
+    p.B = static_cast<char *>(C);
+    p.ldb = ldc;
+    p.gt = et;
+    p.Ag = static_cast<const char *>(A);
+    p.ldag = lda;
+    p.st = et;
+    p.As = A;
+    p.ldas = lda;
+    p.leaf = pick_leaf(h, DType::F32);
+    p.pack_slot = WS_PACK;
+    p.skip_pack = false;
+    return run_plan(h, p);
+}
+
+int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha,
+                     const double *A, int64_t lda, double *B, int64_t ldb, int gemm_type, double tol,
+                     int max_iter, rtri_refine_info *info)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    int rc = check_args(side, uplo, trans, diag, m, n, A, lda, B, ldb, alpha != 0.0);
+    if (rc != 0)
+        return rc;
+    if (gemm_type != RTRI_BF16 && gemm_type != RTRI_F32)
+        return -13;
+    if (!(tol >= 0.0))
+        return -14;
+    if (max_iter < 1 || max_iter > 32)
+        return -15;
+    if (info != nullptr) {
+        std::memset(info, 0, sizeof *info);
+    }
+    if (m == 0 || n == 0) {
+        if (info != nullptr)
+            info->converged = 1;
+        return RTRI_OK;
+    }
+    hipStream_t st = h->stream;
+    hipError_t e;
+    if (alpha == 0.0) {
+        e = launch_fill(DType::F64, B, m, n, ldb, 0.0, st);
+        if (info != nullptr)
+            info->converged = 1;
+        return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
+    }
+    const bool left = side == RTRI_LEFT;
+    const int64_t ka = left ? m : n;
+    const int tr = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    const bool low = (uplo == RTRI_LOWER) != (tr != RTRI_NOTRANS);
+    const ElemT gt = gemm_type == RTRI_BF16 ? ElemT::BF16 : ElemT::F32;
+    const size_t mn = (size_t)m * (size_t)n;
+
+    const size_t need[] = {(size_t)ka * ka * elem_size(gt), mn * 4, mn * 8, mn * 8, mn * 8, mn * 8, 64};
+    const int slot[] = {WS_ACOPY, WS_PANEL32, WS_X, WS_R0, WS_R, WS_W, WS_SCALARS};
+    for (int i = 0; i < 7; ++i) {
+        e = ensure_ws(h, slot[i], need[i]);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+    }
+    void *Acopy = h->ws[WS_ACOPY];
+    float *D = static_cast<float *>(h->ws[WS_PANEL32]);
+    double *X = static_cast<double *>(h->ws[WS_X]);
+    double *R0 = static_cast<double *>(h->ws[WS_R0]);
+    double *R = static_cast<double *>(h->ws[WS_R]);
+    double *W = static_cast<double *>(h->ws[WS_W]);
+    unsigned long long *sc = static_cast<unsigned long long *>(h->ws[WS_SCALARS]);
+    const int64_t ld = m;
+
+    // once per call: the GEMM copy of A, |op(A)|, alpha B, X = 0, max |R|
+    auto other = [&](double bytes, auto &&f) { return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, bytes, f); };
+    e = other(8.0 * ka * ka, [&] { return launch_convert(ElemT::F64, gt, A, lda, Acopy, ka, ka, ka, 1.0, st); });
+    if (e == hipSuccess)
+        e = launch_zero_u64(sc, 4, st);
+    if (e == hipSuccess)
+        e = other(4.0 * ka * ka, [&] {
+            // lines of op(A) (LEFT) or of op(A)^T (RIGHT): |op(A)|_inf or |op(A)|_1
+            return launch_line_norm(A, lda, ka, left ? tr != RTRI_NOTRANS : tr == RTRI_NOTRANS, left ? low : !low,
+                                    diag == RTRI_UNIT, sc + 2, st);
+        });
+    if (e == hipSuccess)
+        e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, B, ldb, R0, ld, m, n, alpha, st); });
+    if (e == hipSuccess)
+        e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, R0, ld, R, ld, m, n, 1.0, st); });
+    if (e == hipSuccess)
+        e = other(8.0 * mn, [&] { return launch_fill(DType::F64, X, m, n, ld, 0.0, st); });
+    if (e == hipSuccess)
+        e = other(8.0 * mn, [&] { return launch_max_abs(R, ld, m, n, sc + 1, st); });
+    unsigned long long host[4];
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, sc, sizeof host, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    const double anorm = from_bits(host[2]);
+    double rmax = from_bits(host[1]);
+    if (info != nullptr)
+        info->anorm = anorm;
+
+    PlanIn lo{};
+    lo.solve = true;
+    lo.side = side;
+    lo.uplo = uplo;
+    lo.trans = tr;
+    lo.diag = diag;
+    lo.m = m;
+    lo.n = n;
+    lo.alpha = 1.0;
+    lo.bt = DType::F32;
+    lo.B = reinterpret_cast<char *>(D);
+    lo.ldb = ld;
+    lo.gt = gt;
+    lo.Ag = static_cast<const char *>(Acopy);
+    lo.ldag = ka;
+    lo.st = ElemT::F64;
+    lo.As = A;
+    lo.ldas = lda;
+    lo.leaf = pick_leaf(h, DType::F32);
+    lo.pack_slot = WS_PACK2;
+    lo.skip_pack = false;
+
+    PlanIn mul{};
+    mul.solve = false;
+    mul.side = side;
+    mul.uplo = uplo;
+    mul.trans = tr;
+    mul.diag = diag;
+    mul.m = m;
+    mul.n = n;
+    mul.alpha = 1.0;
+    mul.bt = DType::F64;
+    mul.B = reinterpret_cast<char *>(W);
+    mul.ldb = ld;
+    mul.gt = ElemT::F64;
+    mul.Ag = reinterpret_cast<const char *>(A);
+    mul.ldag = lda;
+    mul.st = ElemT::F64;
+    mul.As = A;
+    mul.ldas = lda;
+    mul.leaf = pick_leaf(h, DType::F64);
+    mul.pack_slot = WS_PACK;
+    mul.skip_pack = false;
+
+    double eta = rmax == 0.0 ? 0.0 : INFINITY, eta_prev = INFINITY;
+    int iters = 0;
+    bool converged = eta <= tol;
+    while (!converged && iters < max_iter && rmax > 0.0 && std::isfinite(rmax)) {
+        const double s = std::ldexp(1.0, (int)std::ceil(std::log2(rmax)));
+        e = other(12.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F32, R, ld, D, ld, m, n, 1.0 / s, st); });
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        rc = run_plan(h, lo);
+        if (rc != RTRI_OK)
+            return rc;
+        lo.skip_pack = true;
+        e = other(20.0 * mn, [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, st); });
+        if (e == hipSuccess)
+            e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, X, ld, W, ld, m, n, 1.0, st); });
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        rc = run_plan(h, mul);
+        if (rc != RTRI_OK)
+            return rc;
+        mul.skip_pack = true;
+        e = launch_zero_u64(sc, 2, st);
+        if (e == hipSuccess)
+            e = other(32.0 * mn, [&] {
+                return launch_resid_eta(R0, ld, W, ld, R, ld, X, ld, m, n, left, anorm, sc, st);
+            });
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host, sc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        eta = from_bits(host[0]);
+        rmax = from_bits(host[1]);
+        if (info != nullptr && iters < 32)
+            info->eta_hist[iters] = eta;
+        ++iters;
+        if (eta <= tol) {
+            converged = true;
+            break;
+        }
+        if (!(eta <= 0.5 * eta_prev))   // stagnation (or NaN)
+            break;
+        eta_prev = eta;
+    }
+    e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, X, ld, B, ldb, m, n, 1.0, st); });
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    if (info != nullptr) {
+        info->iters = iters;
+        info->converged = converged ? 1 : 0;
+        info->eta = eta;
+    }
+    return converged ? RTRI_OK : RTRI_NOT_CONVERGED;
+}
+
+}  // extern "C"

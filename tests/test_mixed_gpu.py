@@ -1,0 +1,168 @@
+"""Low-precision paths against the CPU oracle.
+
+* TRMM with BF16 / FP16 inputs and FP32 accumulation: against the oracle run
+  on the same (exactly widened) 16-bit values, the error is at the FP32 level;
+  small-integer inputs agree bit for bit.
+* Mixed-precision TRSM with FP64 refinement: the returned X must have normwise
+  backward error <= 1e-12 by the oracle's own (compensated) residual, for GEMM
+  updates in BF16 and in FP32, over conditioned factors up to cond_1 ~ 1e6."""
+import numpy as np
+import pytest
+
+import synth
+from dense_ref import VARIANTS_NT
+from gpu_util import rounded, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2504_13821_amd as rt
+    return rt
+
+
+@pytest.fixture()
+def h(rt):
+    hd = rt.Handle()
+    yield hd
+    hd.close()
+
+
+def G(*k):
+    return synth.rng(synth.W_TEST, 2000, *k)
+
+
+T16 = {"bf16": "bfloat16", "f16": "float16"}
+
+
+def _run_trmm_ex(rt, h, side, uplo, trans, diag, alpha, A, B, dt):
+    td = getattr(torch, T16[dt])
+    Ad = rt.to_device(A, td)
+    Bd = rt.to_device(B, td)
+    m, n = B.shape
+    Cd = torch.full((n, m), float("nan"), dtype=torch.float32, device="cuda").t()
+    rt.trmm_ex(h, side, uplo, trans, diag, alpha, Ad, Bd, Cd)
+    torch.cuda.synchronize()
+    return rt.to_host(Cd).astype(np.float64)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("diag", "NU")
+@pytest.mark.parametrize("side,uplo,trans", VARIANTS_NT)
+def test_trmm_ex_parity(rt, h, orc, dt, diag, side, uplo, trans):
+    m, n = (300, 90) if side == "L" else (90, 300)
+    say("trmm_ex", dt, side, uplo, trans, diag)
+    g = G(1, m)
+    ka = m if side == "L" else n
+    A = rounded(synth.tri(ka, uplo, g, "unit" if diag == "U" else "stress"), dt)
+    B = rounded(synth.dense(m, n, g), dt)
+    C = _run_trmm_ex(rt, h, side, uplo, trans, diag, 0.5, A, B, dt)
+    e = orc.trmm_eta(side, uplo, trans, diag, 0.5, A, B, C)
+    # FP32 accumulation over at most ka terms: 7 sqrt(ka) u32 (same margin as the FP32 path)
+    assert e <= 7 * np.sqrt(ka) * 2.0 ** -24, e
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("side,uplo,trans", VARIANTS_NT)
+def test_trmm_ex_exact(rt, h, orc, dt, side, uplo, trans):
+    ka, other = 70, 11
+    m, n = (ka, other) if side == "L" else (other, ka)
+    say("trmm_ex exact", dt, side, uplo, trans)
+    g = G(2, ka)
+    A = synth.exact_tri(ka, uplo, g, offdiag=(-1, 0, 1), diag=(1.0, -1.0, 2.0))
+    B = synth.exact_dense(m, n, g)
+    C = _run_trmm_ex(rt, h, side, uplo, trans, "N", 2.0, A, B, dt)
+    assert np.array_equal(C, orc.trmm(side, uplo, trans, "N", 2.0, A, B))
+
+
+def test_trmm_ex_rejects_types(rt, h):
+    A = torch.zeros((4, 4), dtype=torch.float32, device="cuda")
+    B = torch.zeros((4, 4), dtype=torch.float32, device="cuda")
+    C = torch.zeros((4, 4), dtype=torch.float32, device="cuda")
+    rc = rt.rtri_trmm_ex(h.ptr, 0, 0, 0, 0, 4, 4, 1.0, A.data_ptr(), rt.F32, 4, B.data_ptr(), rt.F32, 4,
+                         C.data_ptr(), rt.F32, 4)
+    assert rc == rt.ERR_UNSUPPORTED
+
+
+# ---- mixed-precision refined TRSM ------------------------------------------------
+
+def _mixed(rt, h, orc, side, uplo, trans, diag, alpha, A, B, gemm, **kw):
+    Ad = rt.to_device(A, torch.float64)
+    Bd = rt.to_device(B, torch.float64)
+    info = rt.trsm_mixed(h, side, uplo, trans, diag, alpha, Ad, Bd, gemm=gemm, **kw)
+    torch.cuda.synchronize()
+    X = rt.to_host(Bd)
+    return X, info, orc.trsm_eta(side, uplo, trans, diag, alpha, A, B, X)
+
+
+@pytest.mark.parametrize("gemm", ["bf16", "f32"])
+@pytest.mark.parametrize("diag", "NU")
+@pytest.mark.parametrize("side,uplo,trans", VARIANTS_NT)
+def test_mixed_variants(rt, h, orc, gemm, diag, side, uplo, trans):
+    m, n = (260, 70) if side == "L" else (70, 260)
+    say("mixed", gemm, side, uplo, trans, diag)
+    g = G(3, m)
+    ka = m if side == "L" else n
+    A = synth.tri(ka, uplo, g, "unit" if diag == "U" else "stress")
+    B = synth.dense(m, n, g)
+    X, info, e = _mixed(rt, h, orc, side, uplo, trans, diag, -0.75, A, B, gemm)
+    assert info["converged"] and e <= 1e-12, (info, e)
+    assert info["eta"] <= 1e-12
+    # the library's own eta and the oracle's compensated eta describe the same residual
+    assert e <= 4 * max(info["eta"], 1e-16)
+
+
+@pytest.mark.parametrize("gemm", ["bf16", "f32"])
+@pytest.mark.parametrize("c", [40.0, 8.0, 4.5])
+def test_mixed_conditioned(rt, h, orc, gemm, c):
+    """Diagonal c + U(0,1) at m = 1024 spans cond_1 from ~1e2 to ~1e6."""
+    m, n = 1024, 64
+    g = G(4, int(c * 10))
+    A = synth.tri(m, "L", g, "cond", c=c)
+    kappa = orc.cond_one("L", "N", A)
+    say("mixed cond", gemm, c, f"{kappa:.2e}")
+    B = synth.dense(m, n, g)
+    X, info, e = _mixed(rt, h, orc, "L", "L", "N", "N", 1.0, A, B, gemm, max_iter=30)
+    assert info["converged"] and e <= 1e-12, (kappa, info, e)
+
+
+def test_mixed_not_converged_status(rt, h, orc):
+    m, n = 200, 20
+    g = G(5)
+    A = synth.tri(m, "U", g, "stress")
+    B = synth.dense(m, n, g)
+    X, info, e = _mixed(rt, h, orc, "L", "U", "N", "N", 1.0, A, B, "bf16", tol=0.0, max_iter=1,
+                        allow_not_converged=True)
+    assert info["status"] == rt.NOT_CONVERGED and info["iters"] == 1 and not info["converged"]
+    # the iterate after one low-precision solve is returned and is a BF16-level solution
+    assert e <= 1e-2
+
+
+def test_mixed_alpha_zero(rt, h):
+    A = torch.full((8, 8), float("nan"), dtype=torch.float64, device="cuda").t()
+    B = torch.ones((8, 3), dtype=torch.float64, device="cuda").t().contiguous().t()
+    info = rt.trsm_mixed(h, "L", "L", "N", "N", 0.0, A, B)
+    torch.cuda.synchronize()
+    assert info["converged"] and torch.count_nonzero(B).item() == 0
+
+
+def test_mixed_8192_sampled(rt, h, orc):
+    """The mixed-precision workload size, m = n = 8192, BF16 GEMM updates, checked on sampled columns."""
+    m = n = 8192
+    g = synth.rng(synth.W_MIXED, 0, 45)
+    A = synth.tri(m, "L", g, "cond", c=45.0)
+    B = synth.dense(m, n, g)
+    say("mixed 8192")
+    Ad = rt.to_device(A, torch.float64)
+    Bd = rt.to_device(B, torch.float64)
+    info = rt.trsm_mixed(h, "L", "L", "N", "N", 1.0, Ad, Bd, gemm="bf16")
+    torch.cuda.synchronize()
+    idx = np.sort(synth.rng(synth.W_MIXED, 1).choice(n, 8, replace=False))
+    Xs = np.asfortranarray(Bd[:, torch.as_tensor(idx, device="cuda")].cpu().numpy())
+    e = orc.trsm_eta("L", "L", "N", "N", 1.0, A, np.asfortranarray(B[:, idx]), Xs)
+    assert info["converged"] and e <= 1e-12, (info, e)
