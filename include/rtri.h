@@ -128,7 +128,8 @@ enum {
     RTRI_KCLASS_GEMM = 0,        /* GEMM update (Sec. 3.1) */
     RTRI_KCLASS_LEAF_SOLVE = 1,  /* leaf triangular solve (Sec. 3.3) */
     RTRI_KCLASS_LEAF_MULT = 2,   /* leaf triangular multiply */
-    RTRI_KCLASS_OTHER = 3        /* fills, conversions, norms */
+    RTRI_KCLASS_OTHER = 3,       /* fills, conversions, norms */
+    RTRI_KCLASS_BATCHED = 4      /* one launch of a batch plan (flops: sum of ka^2 * vectors) */
 };
 typedef struct {
     int kclass;       /* RTRI_KCLASS_* */
@@ -197,6 +198,52 @@ typedef struct {
 int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha,
                      const double *A, int64_t lda, double *B, int64_t ldb, int gemm_type, double tol,
                      int max_iter, rtri_refine_info *info);
+
+/* ---- batched independent problems (one persistent launch) ----------------- */
+
+/* One problem of a batch: TRSM (op = 0, eqs. (3)/(4)) or TRMM (op = 1,
+ * eqs. (1)/(2)), in place on B, with the same argument meaning as
+ * rtri_dtrsm / rtri_dtrmm.  A and B are device pointers; problems of one batch
+ * must not write overlapping B regions. */
+typedef struct {
+    int op, side, uplo, trans, diag;
+    int64_t m, n;
+    double alpha;
+    const void *A;
+    int64_t lda;
+    void *B;
+    int64_t ldb;
+} rtri_batch_entry;
+
+typedef struct rtri_batch_plan rtri_batch_plan;
+
+/* Build a reusable plan for `count` problems of one element type (dtype
+ * RTRI_F64 or RTRI_F32): every problem's recursion is laid out as an op list
+ * (the same splits, leaf size and order as the single-call path, so each
+ * result is bitwise the one rtri_?trsm / rtri_?trmm would give), its
+ * independent right-hand-side vectors are cut into chunks of 64, and the
+ * chunks are queued longest first.  The plan owns device copies of these
+ * tables and a captured hipGraph of the launch (a queue reset and one
+ * persistent kernel whose workgroups pull chunks until the queue is empty).
+ * entries is host memory and is not kept.  On an invalid entry returns its
+ * argument code (as rtri_dtrsm, or -1 for op) and sets *bad_index (nullable);
+ * RTRI_ERR_UNSUPPORTED for another dtype.  Blocking (uploads the tables). */
+int rtri_batch_plan_create(rtri_handle *h, int dtype, int count, const rtri_batch_entry *entries,
+                           rtri_batch_plan **plan, int *bad_index);
+
+/* Launch the plan's graph on the handle's current stream (asynchronous).  The
+ * problems read and write the A / B memory named at plan creation. */
+int rtri_batch_plan_run(rtri_batch_plan *plan);
+
+/* Number of work chunks in the plan (for reporting). */
+int rtri_batch_plan_chunks(const rtri_batch_plan *plan, int64_t *chunks);
+
+/* Free a plan (waits for its last launch). */
+int rtri_batch_plan_destroy(rtri_batch_plan *plan);
+
+/* One-shot convenience: create a plan, run it once without graph capture,
+ * wait for it, destroy it. */
+int rtri_batched(rtri_handle *h, int dtype, int count, const rtri_batch_entry *entries, int *bad_index);
 
 #ifdef __cplusplus
 }

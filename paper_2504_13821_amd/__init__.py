@@ -73,6 +73,17 @@ class RefineInfo(ctypes.Structure):
 
 rtri_dtrsm_mixed = _sig("rtri_dtrsm_mixed", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64, _int,
                         ctypes.c_double, _int, ctypes.POINTER(RefineInfo))
+class BatchEntry(ctypes.Structure):
+    _fields_ = [("op", _int), ("side", _int), ("uplo", _int), ("trans", _int), ("diag", _int), ("m", _i64),
+                ("n", _i64), ("alpha", ctypes.c_double), ("A", _vp), ("lda", _i64), ("B", _vp), ("ldb", _i64)]
+
+
+rtri_batch_plan_create = _sig("rtri_batch_plan_create", _int, _vp, _int, _int, ctypes.POINTER(BatchEntry),
+                              ctypes.POINTER(_vp), ctypes.POINTER(_int))
+rtri_batch_plan_run = _sig("rtri_batch_plan_run", _int, _vp)
+rtri_batch_plan_chunks = _sig("rtri_batch_plan_chunks", _int, _vp, ctypes.POINTER(_i64))
+rtri_batch_plan_destroy = _sig("rtri_batch_plan_destroy", _int, _vp)
+rtri_batched = _sig("rtri_batched", _int, _vp, _int, _int, ctypes.POINTER(BatchEntry), ctypes.POINTER(_int))
 rtri_gemm_update = _sig("rtri_gemm_update", _int, _vp, _int, _int, _int, _i64, _i64, _i64, ctypes.c_double, _vp,
                         _i64, _vp, _i64, ctypes.c_double, _vp, _i64)
 
@@ -82,7 +93,7 @@ class KernelStat(ctypes.Structure):
                 ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
-KCLASS_NAMES = {0: "gemm", 1: "leaf_solve", 2: "leaf_mult", 3: "other"}
+KCLASS_NAMES = {0: "gemm", 1: "leaf_solve", 2: "leaf_mult", 3: "other", 4: "batched"}
 DTYPE_NAMES = {0: "f64", 1: "f32", 2: "bf16", 3: "f16"}
 rtri_profile_begin = _sig("rtri_profile_begin", _int, _vp)
 rtri_profile_end = _sig("rtri_profile_end", _int, _vp, ctypes.POINTER(KernelStat), _int, ctypes.POINTER(_int))
@@ -240,6 +251,68 @@ def trsm_mixed(h: Handle, side, uplo, trans, diag, alpha, A, B, gemm="bf16", tol
         check(rc, "rtri_dtrsm_mixed")
     return dict(status=rc, iters=info.iters, converged=bool(info.converged), eta=info.eta, anorm=info.anorm,
                 eta_hist=list(info.eta_hist[:info.iters]))
+
+
+def batch_entries(problems):
+    """problems: iterable of (op 'trsm'|'trmm', side, uplo, trans, diag, alpha, A, B) with column-major
+    device tensors of one dtype.  Returns (ctypes array of BatchEntry, dtype code)."""
+    problems = list(problems)
+    arr = (BatchEntry * max(1, len(problems)))()
+    dt = None
+    for i, (op, side, uplo, trans, diag, alpha, A, B) in enumerate(problems):
+        lda, ldb = _colmajor(A, "A"), _colmajor(B, "B")
+        d = {torch.float64: F64, torch.float32: F32}[B.dtype]
+        if dt is None:
+            dt = d
+        elif d != dt or A.dtype != B.dtype:
+            raise TypeError("one dtype per batch")
+        s, u, t, g = codes(side, uplo, trans, diag)
+        arr[i] = BatchEntry({"trsm": 0, "trmm": 1}[op], s, u, t, g, B.shape[0], B.shape[1], alpha, A.data_ptr(), lda,
+                            B.data_ptr(), ldb)
+    return arr, (dt if dt is not None else F64), len(problems)
+
+
+class BatchPlan:
+    """A reusable batch plan (graph-captured persistent launch)."""
+
+    def __init__(self, h: Handle, problems):
+        self.h = h
+        arr, dt, n = batch_entries(problems)
+        self._arr = arr
+        p = _vp()
+        bad = _int(-1)
+        rc = rtri_batch_plan_create(h.ptr, dt, n, arr, ctypes.byref(p), ctypes.byref(bad))
+        if rc != OK:
+            raise RtriError(rc, f"rtri_batch_plan_create (entry {bad.value})")
+        self._p = p
+
+    def run(self):
+        check(rtri_batch_plan_run(self._p), "rtri_batch_plan_run")
+
+    def chunks(self) -> int:
+        c = _i64()
+        check(rtri_batch_plan_chunks(self._p, ctypes.byref(c)), "rtri_batch_plan_chunks")
+        return c.value
+
+    def close(self):
+        if self._p:
+            rtri_batch_plan_destroy(self._p)
+            self._p = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batched(h: Handle, problems):
+    """One-shot batch (blocking)."""
+    arr, dt, n = batch_entries(problems)
+    bad = _int(-1)
+    rc = rtri_batched(h.ptr, dt, n, arr, ctypes.byref(bad))
+    if rc != OK:
+        raise RtriError(rc, f"rtri_batched (entry {bad.value})")
 
 
 def to_device(a, dtype=None, device="cuda", ld=None):

@@ -28,8 +28,18 @@ DEVICE_FLAGS = [
 ]
 
 
-def _compile(src: str) -> str:
+def _fresh(obj: str, src: str) -> bool:
+    """True if obj is newer than src and every header under csrc/ and include/."""
+    if not os.path.exists(obj):
+        return False
+    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(HERE, "..", "include", "*.h"))
+    return os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps)
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if incremental and _fresh(obj, src):
+        return obj
     cmd = [HIPCC, *DEVICE_FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -41,12 +51,14 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile and link.  incremental=True reuses objects newer than their
+    sources and all headers (a full rebuild otherwise)."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda s: _compile(s, incremental), srcs))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
@@ -57,4 +69,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, incremental="--incremental" in sys.argv)

@@ -1,0 +1,254 @@
+// Device-side building blocks of the GEMM update (see gemm.hip), shared with
+// the batched kernel.
+#pragma once
+
+#include "common.h"
+
+namespace rtri {
+namespace gk {
+
+constexpr int NT = 256;   // threads per workgroup
+constexpr int BK = 16;
+
+// Accumulator row held in slot r of lane group g: the FP32 instruction returns
+// four consecutive rows per lane (4g + r), the FP64 one interleaves them (g + 4r).
+template <typename T> struct Acc;
+template <> struct Acc<double> {
+    using V = double4_t;
+    static __device__ inline V mfma(double a, double b, V c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int g, int r) { return g + 4 * r; }
+};
+template <> struct Acc<float> {
+    using V = float4_t;
+    static __device__ inline V mfma(float a, float b, V c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int g, int r) { return 4 * g + r; }
+};
+
+// LDS layout of an operand tile (R rows of M or N, BK along K) follows its
+// layout in global memory, so the global -> LDS copy never transposes:
+//   KC (k contiguous in memory):    Ls[row * SK + k],  SK = BK + pad
+//   MC (rows contiguous in memory): Ls[k * SM + row],  SM = R + 16
+// The paddings make the MFMA fragment reads bank-conflict free: 16-byte reads
+// of k pairs in the KC layout, 8-byte reads of 16 consecutive rows per lane
+// group (groups 1152 B apart) in the MC layout.
+template <typename T> constexpr int lds_sk() { return sizeof(T) == 8 ? BK + 2 : BK + 4; }
+template <int R> constexpr int lds_sm() { return R + 16; }
+template <typename T, int R, bool KC> constexpr int lds_elems() { return KC ? R * lds_sk<T>() : BK * lds_sm<R>(); }
+
+template <typename T, int R, bool KC>
+__device__ __forceinline__ T lds_at(const T *ls, int row, int k)
+{
+    return KC ? ls[row * lds_sk<T>() + k] : ls[k * lds_sm<R>() + row];
+}
+
+// Loader of one operand tile (R rows of the M or N dimension, BK along K) into
+// registers, then into LDS as Ls[row][k] (k contiguous, padded rows).
+//   KC = true : element (row, k) at base[k + row*ld]   (k contiguous in memory)
+//   KC = false: element (row, k) at base[row + k*ld]   (rows contiguous in memory)
+template <typename T, int R, bool KC, bool VEC>
+struct TileLoader {
+    static constexpr int W = 16 / sizeof(T);               // elements per 16-byte load
+    static constexpr int PER = R * BK / NT;                 // elements per thread
+    static constexpr int NV = PER / W;                      // 16-byte loads per thread
+    static_assert(PER % W == 0, "tile too small");
+    T reg[PER];
+
+    __device__ inline void coords(int v, int tid, int &row, int &k) const
+    {
+        const int e = v * NT + tid;                          // index of the W-vector
+        if (KC) {
+            k = (e % (BK / W)) * W;
+            row = e / (BK / W);
+        } else {
+            row = (e % (R / W)) * W;
+            k = e / (R / W);
+        }
+    }
+
+    // full tile, no bounds checks
+    __device__ inline void load_full(const T *base, int64_t ld, int tid)
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            int row, k;
+            coords(v, tid, row, k);
+            const T *p = KC ? base + k + (int64_t)row * ld : base + row + (int64_t)k * ld;
+            if (VEC) {
+                using V4 = int __attribute__((ext_vector_type(4)));
+                V4 x = *reinterpret_cast<const V4 *>(p);
+                const T *xs = reinterpret_cast<const T *>(&x);
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    reg[v * W + w] = xs[w];
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    reg[v * W + w] = p[w];
+            }
+        }
+    }
+
+    // edge tile: rows >= rlim or k >= klim read as zero
+    __device__ inline void load_edge(const T *base, int64_t ld, int tid, int rlim, int klim)
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            int row, k;
+            coords(v, tid, row, k);
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const int rr = KC ? row : row + w;
+                const int kk = KC ? k + w : k;
+                T x = T(0);
+                if (rr < rlim && kk < klim)
+                    x = KC ? base[kk + (int64_t)rr * ld] : base[rr + (int64_t)kk * ld];
+                reg[v * W + w] = x;
+            }
+        }
+    }
+
+    __device__ inline void store(T *lds, int tid) const
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            int row, k;
+            coords(v, tid, row, k);
+            T *dst = KC ? lds + row * lds_sk<T>() + k : lds + k * lds_sm<R>() + row;
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                dst[w] = reg[v * W + w];
+        }
+    }
+};
+
+// One BM x BN tile of C at (m0, n0), computed by the NT threads of the
+// workgroup.  As / Bs: two LDS slots each (lds_elems elements per slot).
+// Ends with a barrier, so the LDS slots may be reused right after it returns.
+template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC>
+__device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t n0, T *As, T *Bs)
+{
+    constexpr int FM = BM / 32, FN = BN / 32;
+    constexpr bool KCA = TP, KCB = !TQ;           // operand layouts (see lds_at)
+    constexpr int EA = lds_elems<T, BM, KCA>(), EB = lds_elems<T, BN, KCB>();
+    using AccT = Acc<T>;
+    using V = typename AccT::V;
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lc = lane % 16, lg = lane / 16;
+
+    const T *P = static_cast<const T *>(g.P);
+    const T *Q = static_cast<const T *>(g.Q);
+    const int64_t ldp = g.ldp, ldq = g.ldq;
+    // tile origins: op(P) rows m0.., op(Q) columns n0..
+    const T *Pt = TP ? P + m0 * ldp : P + m0;
+    const T *Qt = TQ ? Q + n0 : Q + n0 * ldq;
+    const int rlim_m = (int)min<int64_t>(BM, g.M - m0);
+    const int rlim_n = (int)min<int64_t>(BN, g.N - n0);
+    const bool full_mn = rlim_m == BM && rlim_n == BN;
+
+    TileLoader<T, BM, TP, VEC> la;
+    TileLoader<T, BN, !TQ, VEC> lb;
+
+    V acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = V{0, 0, 0, 0};
+
+    const int64_t K = g.K;
+    const int nk = (int)((K + BK - 1) / BK);
+
+    auto load_step = [&](int kt) {
+        const int64_t k0 = (int64_t)kt * BK;
+        const T *pa = TP ? Pt + k0 : Pt + k0 * ldp;
+        const T *pb = TQ ? Qt + k0 * ldq : Qt + k0;
+        if (full_mn && k0 + BK <= K) {
+            la.load_full(pa, ldp, tid);
+            lb.load_full(pb, ldq, tid);
+        } else {
+            const int klim = (int)min<int64_t>(BK, K - k0);
+            la.load_edge(pa, ldp, tid, rlim_m, klim);
+            lb.load_edge(pb, ldq, tid, rlim_n, klim);
+        }
+    };
+
+    if (nk > 0) {
+        load_step(0);
+        la.store(As, tid);
+        lb.store(Bs, tid);
+    }
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk)
+            load_step(kt + 1);
+
+        // fragments: lane (lc, lg) reads row (block*16 + lc), k = 4*lg .. 4*lg+3,
+        // two k values at a time (one 16-byte read for FP64)
+        const int ra = wm * (BM / 2) + lc, rbq = wn * (BN / 2) + lc;
+#pragma unroll
+        for (int t2 = 0; t2 < 4; t2 += 2) {
+            T fa[FM][2], fb[FN][2];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                fa[i][0] = lds_at<T, BM, KCA>((As + cur * EA), ra + i * 16, 4 * lg + t2);
+                fa[i][1] = lds_at<T, BM, KCA>((As + cur * EA), ra + i * 16, 4 * lg + t2 + 1);
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                fb[j][0] = lds_at<T, BN, KCB>((Bs + cur * EB), rbq + j * 16, 4 * lg + t2);
+                fb[j][1] = lds_at<T, BN, KCB>((Bs + cur * EB), rbq + j * 16, 4 * lg + t2 + 1);
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = AccT::mfma(fa[i][t], fb[j][t], acc[i][j]);
+        }
+
+        if (kt + 1 < nk) {
+            la.store(As + (cur ^ 1) * EA, tid);
+            lb.store(Bs + (cur ^ 1) * EB, tid);
+        }
+        __syncthreads();
+    }
+
+    // epilogue: slot r of lane (lc, lg) holds row AccT::row(lg, r), column lc of every 16x16 block
+    T *C = static_cast<T *>(g.C);
+    const int64_t ldc = g.ldc;
+    const T beta = T(g.beta), s = T(g.s);
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int rb = wm * (BM / 2) + i * 16;              // local row of the block
+            const int cl = wn * (BN / 2) + j * 16 + lc;        // local column
+            if (cl >= rlim_n)
+                continue;
+            T *cp = C + (m0 + rb) + (n0 + cl) * ldc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = AccT::row(lg, r);
+                if (rb + rr < rlim_m) {
+                    const T v = s * acc[i][j][r];
+                    cp[rr] = (g.beta == 0.0) ? v : fmat(beta, cp[rr], v);
+                }
+            }
+        }
+    }
+}
+
+
+}  // namespace gk
+}  // namespace rtri

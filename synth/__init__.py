@@ -143,3 +143,13 @@ def loguniform_int(g: np.random.Generator, lo: int, hi: int, size) -> np.ndarray
     """Integers log-uniform on [lo, hi] (rounded)."""
     v = np.exp(g.uniform(np.log(lo), np.log(hi), size=size))
     return np.clip(np.rint(v).astype(np.int64), lo, hi)
+
+
+def batch_shapes(count: int, g: np.random.Generator, m_lo: int = 16, m_hi: int = 1024, n_lo: int = 1,
+                 n_hi: int = 128):
+    """Shapes of a batch of independent problems: m log-uniform on [m_lo, m_hi],
+    number of right-hand sides uniform on [n_lo, n_hi], uplo 'L'/'U' 50/50."""
+    ms = loguniform_int(g, m_lo, m_hi, count)
+    ns = g.integers(n_lo, n_hi + 1, size=count)
+    uplos = np.where(g.random(count) < 0.5, "L", "U")
+    return [(int(m), int(n), str(u)) for m, n, u in zip(ms, ns, uplos)]
