@@ -199,6 +199,20 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
                      const double *A, int64_t lda, double *B, int64_t ldb, int gemm_type, double tol,
                      int max_iter, rtri_refine_info *info);
 
+/* Synthetic inputs for benchmarks and serving workloads (not part of the
+ * method).  Fills an m-by-n column-major matrix X (device, ldx) with values
+ * from Philox4x32-10 (Salmon et al., SC'11): element (i, j) uses counter
+ * (i, j, id low word, id high word) and key (seed low word XOR stream, seed high
+ * word); u = 53 bits of the first two output words (word 1 high) times 2^-53.
+ *   kind 0: U(-1,1) = 2u - 1 everywhere
+ *   kind 1: lower triangular, off-diagonal 2u - 1, diagonal param + u, zero above
+ *   kind 2: upper triangular, likewise, zero below
+ * dtype RTRI_F64 or RTRI_F32 (the FP64 value rounded to nearest).  Asynchronous
+ * on the handle's stream.  Codes: -2 dtype, -3 kind, -7 m or n < 0, -10 X NULL,
+ * -11 ldx < max(1, m). */
+int rtri_synth_fill(rtri_handle *h, int dtype, int kind, uint64_t seed, uint32_t stream, uint64_t id, int64_t m,
+                    int64_t n, double param, void *X, int64_t ldx);
+
 /* ---- batched independent problems (one persistent launch) ----------------- */
 
 /* One problem of a batch: TRSM (op = 0, eqs. (3)/(4)) or TRMM (op = 1,
@@ -244,6 +258,79 @@ int rtri_batch_plan_destroy(rtri_batch_plan *plan);
 /* One-shot convenience: create a plan, run it once without graph capture,
  * wait for it, destroy it. */
 int rtri_batched(rtri_handle *h, int dtype, int count, const rtri_batch_entry *entries, int *bad_index);
+
+/* ---- serving: continuous batching of solve / multiply requests ------------- */
+
+enum { RTRI_PREC_F64 = 0, RTRI_PREC_MIXED_BF16 = 1, RTRI_PREC_MIXED_F32 = 2 };
+
+typedef struct {
+    int slots;              /* concurrent executors (a stream, a handle and a worker thread each), 1..16 */
+    int64_t hbm_budget;     /* device bytes the server may hold: cached factors, right-hand sides, workspace */
+    int max_batch;          /* most requests folded into one batched launch */
+    int64_t small_max;      /* FP64 requests with factor order <= small_max join batched launches */
+    uint64_t synth_seed;    /* seed of synthetic factors and right-hand sides (rtri_synth_fill) */
+} rtri_server_cfg;
+
+/* One request: a TRSM (op 0) or TRMM (op 1) with the argument meaning of
+ * rtri_dtrsm / rtri_dtrmm, on a factor named by factor_id (order ka = m for
+ * LEFT, n for RIGHT).  A factor registered with rtri_server_register_factor is
+ * used as is; any other id names a synthetic factor (rtri_synth_fill kind
+ * 1 / 2 by uplo, diagonal ka + U(0,1), stream 1, id = factor_id) generated on
+ * the device on first use and cached (evicted least recently used when the
+ * budget needs room; never while a request uses it).  The right-hand side is
+ * synthetic (kind 0, stream 2, id = rhs_id).  precision selects the FP64 path
+ * or the mixed-precision refined TRSM (TRSM only).  If result != NULL the
+ * m-by-n result is copied there (host, column-major, ld = m) before the
+ * request completes; the buffer must stay valid until then.  t_arrival is the
+ * scheduled arrival time on the server clock; latency is measured from it. */
+typedef struct {
+    int op, side, uplo, trans, diag;
+    int64_t m, n;
+    double alpha;
+    int precision;
+    uint64_t factor_id;
+    uint64_t rhs_id;
+    double *result;
+    double t_arrival;
+} rtri_request;
+
+typedef struct {
+    uint64_t ticket;
+    int status;             /* RTRI_OK, RTRI_NOT_CONVERGED, or an error code */
+    int batched;            /* 1 if it ran inside a batched launch */
+    int iters;              /* refinement corrections (mixed precision) */
+    double eta;             /* refinement backward error (mixed precision), else 0 */
+    double t_arrival, t_start, t_done;   /* server clock, seconds */
+} rtri_completion;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t launches, batched_launches, batched_requests;
+    int64_t factor_hits, factor_misses, evictions;
+    int64_t hbm_in_use, hbm_peak;
+    double useful_flops;    /* sum of ka^2 * vectors over completed requests */
+} rtri_server_counters;
+
+typedef struct rtri_server rtri_server;
+
+/* Start a server on the current device.  Codes: -1 cfg NULL or out NULL,
+ * -2 slots, -3 budget <= 0, -4 max_batch < 1. */
+int rtri_server_create(const rtri_server_cfg *cfg, rtri_server **out);
+/* Register a caller-owned FP64 factor (device memory, kept valid while the
+ * server may use it; not counted against the budget, never evicted). */
+int rtri_server_register_factor(rtri_server *s, uint64_t factor_id, int64_t ka, int uplo, const double *A,
+                                int64_t lda);
+/* Queue a request (thread safe, never blocks on the GPU); *ticket numbers it. */
+int rtri_server_submit(rtri_server *s, const rtri_request *req, uint64_t *ticket);
+/* Collect up to max completions (in completion order); *n receives the count. */
+int rtri_server_poll(rtri_server *s, rtri_completion *out, int max, int *n);
+/* Block until every submitted request has completed. */
+int rtri_server_drain(rtri_server *s);
+int rtri_server_stats(rtri_server *s, rtri_server_counters *out);
+/* Seconds since the server started (the clock of t_arrival / t_done). */
+double rtri_server_now(rtri_server *s);
+/* Drain, stop the workers and free everything the server owns. */
+int rtri_server_destroy(rtri_server *s);
 
 #ifdef __cplusplus
 }

@@ -84,6 +84,43 @@ rtri_batch_plan_run = _sig("rtri_batch_plan_run", _int, _vp)
 rtri_batch_plan_chunks = _sig("rtri_batch_plan_chunks", _int, _vp, ctypes.POINTER(_i64))
 rtri_batch_plan_destroy = _sig("rtri_batch_plan_destroy", _int, _vp)
 rtri_batched = _sig("rtri_batched", _int, _vp, _int, _int, ctypes.POINTER(BatchEntry), ctypes.POINTER(_int))
+rtri_synth_fill = _sig("rtri_synth_fill", _int, _vp, _int, _int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                       _i64, _i64, ctypes.c_double, _vp, _i64)
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("slots", _int), ("hbm_budget", _i64), ("max_batch", _int), ("small_max", _i64),
+                ("synth_seed", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("op", _int), ("side", _int), ("uplo", _int), ("trans", _int), ("diag", _int), ("m", _i64),
+                ("n", _i64), ("alpha", ctypes.c_double), ("precision", _int), ("factor_id", ctypes.c_uint64),
+                ("rhs_id", ctypes.c_uint64), ("result", _vp), ("t_arrival", ctypes.c_double)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", _int), ("batched", _int), ("iters", _int),
+                ("eta", ctypes.c_double), ("t_arrival", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [("submitted", _i64), ("completed", _i64), ("failed", _i64), ("launches", _i64),
+                ("batched_launches", _i64), ("batched_requests", _i64), ("factor_hits", _i64),
+                ("factor_misses", _i64), ("evictions", _i64), ("hbm_in_use", _i64), ("hbm_peak", _i64),
+                ("useful_flops", ctypes.c_double)]
+
+
+PREC_F64, PREC_MIXED_BF16, PREC_MIXED_F32 = 0, 1, 2
+rtri_server_create = _sig("rtri_server_create", _int, ctypes.POINTER(ServerCfg), ctypes.POINTER(_vp))
+rtri_server_register_factor = _sig("rtri_server_register_factor", _int, _vp, ctypes.c_uint64, _i64, _int, _vp, _i64)
+rtri_server_submit = _sig("rtri_server_submit", _int, _vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64))
+rtri_server_poll = _sig("rtri_server_poll", _int, _vp, ctypes.POINTER(Completion), _int, ctypes.POINTER(_int))
+rtri_server_drain = _sig("rtri_server_drain", _int, _vp)
+rtri_server_stats = _sig("rtri_server_stats", _int, _vp, ctypes.POINTER(Counters))
+rtri_server_now = _sig("rtri_server_now", ctypes.c_double, _vp)
+rtri_server_destroy = _sig("rtri_server_destroy", _int, _vp)
 rtri_gemm_update = _sig("rtri_gemm_update", _int, _vp, _int, _int, _int, _i64, _i64, _i64, ctypes.c_double, _vp,
                         _i64, _vp, _i64, ctypes.c_double, _vp, _i64)
 
@@ -313,6 +350,77 @@ def batched(h: Handle, problems):
     rc = rtri_batched(h.ptr, dt, n, arr, ctypes.byref(bad))
     if rc != OK:
         raise RtriError(rc, f"rtri_batched (entry {bad.value})")
+
+
+def synth_fill(h: Handle, kind: int, seed: int, stream: int, ident: int, X, param: float = 0.0):
+    """On-device Philox4x32-10 fill of a column-major tensor (see rtri_synth_fill)."""
+    ldx = _colmajor(X, "X")
+    dt = {torch.float64: F64, torch.float32: F32}[X.dtype]
+    check(rtri_synth_fill(h.ptr, dt, kind, seed, stream, ident, X.shape[0], X.shape[1], param, X.data_ptr(), ldx),
+          "rtri_synth_fill")
+    return X
+
+
+class Server:
+    """Continuous-batching server (see rtri_server_*).  Requests are dicts with
+    the rtri_request fields; 'result' may be a float64 numpy array (m x n,
+    Fortran order) that receives the result."""
+
+    def __init__(self, slots=4, hbm_budget=64 << 30, max_batch=256, small_max=1024, seed=250413821):
+        cfg = ServerCfg(slots, hbm_budget, max_batch, small_max, seed)
+        p = _vp()
+        check(rtri_server_create(ctypes.byref(cfg), ctypes.byref(p)), "rtri_server_create")
+        self._s = p
+        self._keep = {}
+
+    def now(self) -> float:
+        return rtri_server_now(self._s)
+
+    def submit(self, op="trsm", side="L", uplo="L", trans="N", diag="N", m=1, n=1, alpha=1.0, precision=PREC_F64,
+               factor_id=1, rhs_id=1, result=None, t_arrival=0.0) -> int:
+        s, u, t, d = codes(side, uplo, trans, diag)
+        ptr = None
+        if result is not None:
+            if result.dtype.name != "float64" or not result.flags["F_CONTIGUOUS"] or result.shape != (m, n):
+                raise ValueError("result must be a Fortran-ordered float64 m x n array")
+            ptr = result.ctypes.data
+        req = Request({"trsm": 0, "trmm": 1}[op], s, u, t, d, m, n, alpha, precision, factor_id, rhs_id, ptr,
+                      t_arrival)
+        tk = ctypes.c_uint64()
+        check(rtri_server_submit(self._s, ctypes.byref(req), ctypes.byref(tk)), "rtri_server_submit")
+        if result is not None:
+            self._keep[tk.value] = result
+        return tk.value
+
+    def poll(self, max_n=4096) -> list:
+        buf = (Completion * max_n)()
+        n = _int()
+        check(rtri_server_poll(self._s, buf, max_n, ctypes.byref(n)), "rtri_server_poll")
+        out = []
+        for c in buf[:n.value]:
+            self._keep.pop(c.ticket, None)
+            out.append(dict(ticket=c.ticket, status=c.status, batched=bool(c.batched), iters=c.iters, eta=c.eta,
+                            t_arrival=c.t_arrival, t_start=c.t_start, t_done=c.t_done))
+        return out
+
+    def drain(self):
+        check(rtri_server_drain(self._s), "rtri_server_drain")
+
+    def stats(self) -> dict:
+        c = Counters()
+        check(rtri_server_stats(self._s, ctypes.byref(c)), "rtri_server_stats")
+        return {f: getattr(c, f) for f, _ in Counters._fields_}
+
+    def close(self):
+        if self._s:
+            rtri_server_destroy(self._s)
+            self._s = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def to_device(a, dtype=None, device="cuda", ld=None):

@@ -13,6 +13,7 @@
 //   gemm: all 256 threads run 64x64 MFMA tiles of the update (gemm_core.h).
 // Per element the arithmetic is the single-call path's (same GEMM k order,
 // same leaf), so a problem's result does not depend on the batch around it.
+#include <cstring>
 #include <map>
 #include <tuple>
 
@@ -90,20 +91,27 @@ struct rtri_batch_plan {
 
 namespace {
 
-int build_plan(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e, rtri_batch_plan **out,
-               int *bad_index, bool capture)
+struct Tables {
+    DType t;
+    int nb;
+    std::vector<BInst> insts;
+    std::vector<BItem> sorted;
+    std::vector<BOp> ops;
+    double flops;
+};
+
+// validate the entries and lay out instances, work items (longest first) and op lists
+int build_tables(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e, Tables &tb, int *bad_index)
 {
-    if (!handle_valid(h))
-        return RTRI_ERR_HANDLE;
-    if (out == nullptr || count < 0 || (count > 0 && e == nullptr))
+    if (count < 0 || (count > 0 && e == nullptr))
         return -4;
     if (dtype != RTRI_F64 && dtype != RTRI_F32)
         return RTRI_ERR_UNSUPPORTED;
     const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
     const int nb = pick_leaf(h, t) <= 32 ? 32 : 64;
-    std::vector<BInst> insts;
+    std::vector<BInst> &insts = tb.insts;
     std::vector<BItem> items;
-    std::vector<BOp> ops;
+    std::vector<BOp> &ops = tb.ops;
     std::vector<double> cost;
     std::map<std::tuple<int64_t, bool, bool, bool>, std::pair<int, int>> cache;
     double flops = 0.0;
@@ -166,9 +174,60 @@ int build_plan(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e, 
     for (size_t i = 0; i < order.size(); ++i)
         order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<BItem> sorted(items.size());
+    tb.sorted.resize(items.size());
     for (size_t i = 0; i < order.size(); ++i)
-        sorted[i] = items[order[i]];
+        tb.sorted[i] = items[order[i]];
+    tb.t = t;
+    tb.nb = nb;
+    tb.flops = flops;
+    return RTRI_OK;
+}
+
+// byte offsets of the three tables and the counter inside one device block
+struct Layout {
+    size_t items, ops, counter, total;
+};
+Layout layout_of(const Tables &tb)
+{
+    const size_t bi = tb.insts.size() * sizeof(BInst), bt = tb.sorted.size() * sizeof(BItem);
+    const size_t bo = tb.ops.size() * sizeof(BOp);
+    Layout L;
+    L.items = (bi + 255) & ~(size_t)255;
+    L.ops = L.items + ((bt + 255) & ~(size_t)255);
+    L.counter = L.ops + ((bo + 255) & ~(size_t)255);
+    L.total = L.counter + 256;
+    return L;
+}
+
+hipError_t grid_for(DType t, int nb, int nitems, unsigned *grid)
+{
+    int dev = 0, cus = 256, per = 1;
+    hipError_t err = hipGetDevice(&dev);
+    if (err == hipSuccess)
+        err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (err == hipSuccess)
+        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pick_kernel(t, nb), NT, 0);
+    *grid = (unsigned)std::max(1, std::min(nitems, cus * std::max(1, per)));
+    return err;
+}
+
+int build_plan(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e, rtri_batch_plan **out,
+               int *bad_index, bool capture)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    if (out == nullptr)
+        return -4;
+    Tables tb;
+    int rc = build_tables(h, dtype, count, e, tb, bad_index);
+    if (rc != RTRI_OK)
+        return rc;
+    const DType t = tb.t;
+    const int nb = tb.nb;
+    const std::vector<BInst> &insts = tb.insts;
+    const std::vector<BItem> &sorted = tb.sorted;
+    const std::vector<BOp> &ops = tb.ops;
+    const double flops = tb.flops;
 
     rtri_batch_plan *p = new (std::nothrow) rtri_batch_plan();
     if (p == nullptr)
@@ -197,14 +256,8 @@ int build_plan(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e, 
         err = hipMemcpy(p->items, sorted.data(), bt, hipMemcpyHostToDevice);
     if (err == hipSuccess && bo)
         err = hipMemcpy(p->ops, ops.data(), bo, hipMemcpyHostToDevice);
-    int dev = 0, cus = 256, per = 1;
     if (err == hipSuccess)
-        err = hipGetDevice(&dev);
-    if (err == hipSuccess)
-        err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (err == hipSuccess)
-        err = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pick_kernel(t, nb), NT, 0);
-    p->grid = (unsigned)std::max(1, std::min(p->nitems, cus * std::max(1, per)));
+        err = grid_for(t, nb, p->nitems, &p->grid);
     p->graph = nullptr;
     p->exec = nullptr;
     if (err == hipSuccess && capture && p->nitems > 0) {
@@ -237,6 +290,75 @@ int build_plan(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e, 
 }
 
 }  // namespace
+
+namespace rtri {
+
+void batch_scratch_free(BatchScratch &sc)
+{
+    if (sc.dev != nullptr)
+        (void)hipFree(sc.dev);
+    if (sc.host != nullptr)
+        (void)hipHostFree(sc.host);
+    sc = BatchScratch{};
+}
+
+int batch_run_async(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e, BatchScratch &sc,
+                    int *bad_index, double *flops)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    Tables tb;
+    int rc = build_tables(h, dtype, count, e, tb, bad_index);
+    if (rc != RTRI_OK)
+        return rc;
+    if (flops != nullptr)
+        *flops = tb.flops;
+    const int nitems = (int)tb.sorted.size();
+    if (nitems == 0)
+        return RTRI_OK;
+    const Layout L = layout_of(tb);
+    hipError_t err = hipSuccess;
+    // the caller waits for the stream before the next call, so the staging can be reused
+    if (L.total > sc.host_bytes) {
+        if (sc.host != nullptr)
+            (void)hipHostFree(sc.host);
+        sc.host = nullptr;
+        sc.host_bytes = 0;
+        err = hipHostMalloc(&sc.host, L.total * 2, 0);
+        if (err != hipSuccess)
+            return hip_fail(h, err);
+        sc.host_bytes = L.total * 2;
+    }
+    if (L.total > sc.dev_bytes) {
+        if (sc.dev != nullptr)
+            (void)hipFree(sc.dev);
+        sc.dev = nullptr;
+        sc.dev_bytes = 0;
+        err = hipMalloc(&sc.dev, L.total * 2);
+        if (err != hipSuccess)
+            return hip_fail(h, err);
+        sc.dev_bytes = L.total * 2;
+    }
+    char *hb = static_cast<char *>(sc.host);
+    std::memcpy(hb, tb.insts.data(), tb.insts.size() * sizeof(BInst));
+    std::memcpy(hb + L.items, tb.sorted.data(), tb.sorted.size() * sizeof(BItem));
+    std::memcpy(hb + L.ops, tb.ops.data(), tb.ops.size() * sizeof(BOp));
+    char *db = static_cast<char *>(sc.dev);
+    err = hipMemcpyAsync(db, hb, L.counter, hipMemcpyHostToDevice, h->stream);
+    unsigned grid = 1;
+    if (err == hipSuccess)
+        err = grid_for(tb.t, tb.nb, nitems, &grid);
+    if (err == hipSuccess)
+        err = timed(h, RTRI_KCLASS_BATCHED, dtype, tb.flops, 0.0, [&] {
+            return launch_batched(tb.t, tb.nb, grid, reinterpret_cast<const BInst *>(db),
+                                  reinterpret_cast<const BItem *>(db + L.items), nitems,
+                                  reinterpret_cast<const BOp *>(db + L.ops), reinterpret_cast<unsigned *>(db + L.counter),
+                                  h->stream);
+        });
+    return err == hipSuccess ? RTRI_OK : hip_fail(h, err);
+}
+
+}  // namespace rtri
 
 extern "C" {
 

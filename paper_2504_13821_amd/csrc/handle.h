@@ -80,6 +80,20 @@ int run_plan(rtri_handle *h, const PlanIn &p);
 hipError_t timed_launch(rtri_handle *h, int kclass, int dtype, double flops, double bytes, hipError_t (*fn)(void *),
                         void *ctx);
 
+// Reusable staging for batched launches issued by a long-lived caller (a
+// serving slot): pinned host tables and their device copy, grown on demand.
+struct BatchScratch {
+    void *dev = nullptr;
+    size_t dev_bytes = 0;
+    void *host = nullptr;
+    size_t host_bytes = 0;
+};
+// Enqueue one batched launch on h's stream (no graph).  The caller must wait
+// for the stream before reusing sc.  *flops (nullable) gets the useful flops.
+int batch_run_async(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e, BatchScratch &sc,
+                    int *bad_index, double *flops);
+void batch_scratch_free(BatchScratch &sc);
+
 template <class F>
 hipError_t timed(rtri_handle *h, int kclass, int dtype, double flops, double bytes, F &&f)
 {

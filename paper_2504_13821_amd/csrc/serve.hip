@@ -1,0 +1,552 @@
+// Serving loop: continuous batching of TRSM / TRMM requests on one GPU.
+//
+// Requests become visible to the scheduler at their scheduled arrival time.
+// Each slot (a worker thread with its own stream and handle) loops:
+//   1. under the server lock, take work from the head of the arrival queue:
+//      - a small FP64 request (factor order <= small_max) opens a batch: the
+//        slot keeps taking small FP64 requests from the queue front, up to
+//        max_batch, while their memory fits the budget;
+//      - any other request (large, or mixed precision) runs alone;
+//      admission reserves the request's right-hand side and workspace and, for
+//      a factor not resident yet, the factor itself; least-recently-used
+//      factors nobody is using are evicted when the budget needs room.  A new
+//      synthetic factor is allocated and generated on the admitting slot's
+//      stream right away, and an event marks it ready for any other slot.
+//   2. without the lock: wait for the factors' events, generate the
+//      right-hand sides, run one batched launch (or the single-call recursion,
+//      or the mixed-precision refined solve), copy requested results to the
+//      host, wait for the stream.
+//   3. under the lock: release the reservations, record the completions.
+// Several slots run at once, so requests arriving while others run are
+// admitted as slots and memory free up, and their work overlaps on the device.
+// Per request the arithmetic is the same alone or in any batch (the batched
+// kernel reproduces the single-call path bit for bit).
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "handle.h"
+
+using namespace rtri;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+    uint64_t ticket;
+    rtri_request r;
+    int64_t ka;
+    size_t rhs_bytes, ws_bytes;
+    bool small;
+};
+
+struct Factor {
+    double *ptr = nullptr;
+    int64_t ka = 0, lda = 0;
+    int uplo = 0;
+    size_t bytes = 0;
+    int refs = 0;
+    uint64_t last_use = 0;
+    bool registered = false;
+    hipEvent_t ready = nullptr;   // recorded after generation (synthetic factors)
+};
+
+struct Work {
+    std::vector<Req> reqs;
+    bool batched = false;
+    size_t ws_extra = 0;
+};
+
+}  // namespace
+
+struct rtri_server {
+    rtri_server_cfg cfg;
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req> pending;
+    std::unordered_map<uint64_t, Factor> factors;
+    std::vector<rtri_completion> done;
+    int64_t used = 0;
+    uint64_t next_ticket = 1, use_clock = 0;
+    int64_t outstanding = 0;
+    rtri_server_counters st{};
+    bool stopping = false;
+    Clock::time_point t0;
+    struct Slot {
+        std::thread th;
+        hipStream_t stream = nullptr;
+        rtri_handle *h = nullptr;
+        BatchScratch sc;
+        size_t ws_held = 0;   // workspace the slot's handle keeps allocated (counted in used)
+    };
+    std::vector<Slot> slots;
+};
+
+namespace {
+
+double now_s(const rtri_server *s) { return std::chrono::duration<double>(Clock::now() - s->t0).count(); }
+
+size_t handle_ws_bytes(const rtri_handle *h)
+{
+    size_t b = 0;
+    for (int i = 0; i < WS_COUNT; ++i)
+        b += h->ws_bytes[i];
+    return b;
+}
+
+// workspace a request needs in its slot's handle (upper estimate)
+size_t ws_estimate(const rtri_request &r, int64_t ka)
+{
+    const size_t mn = (size_t)r.m * (size_t)r.n;
+    const size_t pack = (size_t)((ka + 63) / 64) * 2080 * 8;
+    if (r.precision == RTRI_PREC_F64)
+        return 2 * pack;
+    return (size_t)ka * ka * 4 + mn * (4 + 8 * 4) + 4 * pack + 64;
+}
+
+bool evict_one(rtri_server *s, hipStream_t st)
+{
+    auto victim = s->factors.end();
+    for (auto it = s->factors.begin(); it != s->factors.end(); ++it) {
+        const Factor &f = it->second;
+        if (f.registered || f.refs > 0)
+            continue;
+        if (victim == s->factors.end() || f.last_use < victim->second.last_use)
+            victim = it;
+    }
+    if (victim == s->factors.end())
+        return false;
+    Factor &f = victim->second;
+    // no request uses it and every earlier user has completed on the host side
+    (void)hipFreeAsync(f.ptr, st);
+    if (f.ready != nullptr)
+        (void)hipEventDestroy(f.ready);
+    s->used -= (int64_t)f.bytes;
+    s->factors.erase(victim);
+    s->st.evictions += 1;
+    return true;
+}
+
+void complete_now(rtri_server *s, const Req &q, int status)
+{
+    rtri_completion c{};
+    c.ticket = q.ticket;
+    c.status = status;
+    c.t_arrival = q.r.t_arrival;
+    c.t_start = c.t_done = now_s(s);
+    s->done.push_back(c);
+    s->st.completed += 1;
+    s->st.failed += 1;
+    s->outstanding -= 1;
+}
+
+// Reserve what request q needs for slot `slot`; creates (and starts generating)
+// a missing synthetic factor.  Returns false if it does not fit right now.
+bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w)
+{
+    auto it = s->factors.find(q.r.factor_id);
+    const bool have = it != s->factors.end();
+    const size_t fbytes = have ? 0 : (size_t)q.ka * q.ka * 8;
+    size_t ws_extra = 0;
+    if (q.ws_bytes > slot.ws_held + w.ws_extra)
+        ws_extra = q.ws_bytes - (slot.ws_held + w.ws_extra);
+    const int64_t need = (int64_t)(fbytes + q.rhs_bytes + ws_extra);
+    while (s->used + need > s->cfg.hbm_budget)
+        if (!evict_one(s, slot.stream))
+            return false;
+    Factor *f;
+    if (!have) {
+        Factor nf;
+        nf.ka = q.ka;
+        nf.lda = q.ka;
+        nf.uplo = q.r.uplo;
+        nf.bytes = fbytes;
+        hipError_t e = hipMallocAsync((void **)&nf.ptr, fbytes, slot.stream);
+        if (e == hipSuccess) {
+            const int kind = q.r.uplo == RTRI_LOWER ? 1 : 2;
+            int rc = rtri_synth_fill(slot.h, RTRI_F64, kind, s->cfg.synth_seed, 1u, q.r.factor_id, q.ka, q.ka,
+                                     (double)q.ka, nf.ptr, q.ka);
+            e = rc == RTRI_OK ? hipSuccess : hipErrorUnknown;
+        }
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&nf.ready, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(nf.ready, slot.stream);
+        if (e != hipSuccess)
+            return false;
+        it = s->factors.emplace(q.r.factor_id, nf).first;
+        s->st.factor_misses += 1;
+        s->used += (int64_t)fbytes;
+    } else {
+        s->st.factor_hits += 1;
+    }
+    f = &it->second;
+    f->refs += 1;
+    f->last_use = ++s->use_clock;
+    s->used += (int64_t)(q.rhs_bytes + ws_extra);
+    w.ws_extra += ws_extra;
+    s->st.hbm_in_use = s->used;
+    s->st.hbm_peak = std::max(s->st.hbm_peak, s->used);
+    w.reqs.push_back(q);
+    return true;
+}
+
+// a factor id already in the cache must describe the same factor
+bool consistent(rtri_server *s, const Req &q)
+{
+    auto it = s->factors.find(q.r.factor_id);
+    return it == s->factors.end() || (it->second.ka == q.ka && it->second.uplo == q.r.uplo);
+}
+
+// called with the lock held; fills w (possibly empty)
+void take_work(rtri_server *s, rtri_server::Slot &slot, Work &w)
+{
+    const double t = now_s(s);
+    while (!s->pending.empty() && s->pending.front().r.t_arrival <= t) {
+        Req &head = s->pending.front();
+        if (!consistent(s, head)) {
+            complete_now(s, head, RTRI_ERR_INVALID);
+            s->pending.pop_front();
+            continue;
+        }
+        if ((int64_t)(head.ka * head.ka * 8 + head.rhs_bytes + head.ws_bytes) > s->cfg.hbm_budget) {
+            complete_now(s, head, RTRI_ERR_NOMEM);
+            s->pending.pop_front();
+            continue;
+        }
+        break;
+    }
+    if (s->pending.empty() || s->pending.front().r.t_arrival > t)
+        return;
+    const Req head = s->pending.front();
+    if (!admit(s, slot, head, w))
+        return;
+    s->pending.pop_front();
+    if (!head.small)
+        return;
+    w.batched = true;
+    // continuous batching: more small FP64 requests that have arrived, in order
+    while ((int)w.reqs.size() < s->cfg.max_batch && !s->pending.empty()) {
+        const Req &q = s->pending.front();
+        if (q.r.t_arrival > t || !q.small || !consistent(s, q))
+            break;
+        if (!admit(s, slot, q, w))
+            break;
+        s->pending.pop_front();
+    }
+}
+
+void execute(rtri_server *s, rtri_server::Slot &slot, Work &w, std::vector<rtri_completion> &out)
+{
+    rtri_handle *h = slot.h;
+    hipStream_t st = slot.stream;
+    const double t_start = now_s(s);
+    std::vector<double *> rhs(w.reqs.size(), nullptr);
+    std::vector<const Factor *> fac(w.reqs.size(), nullptr);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (size_t i = 0; i < w.reqs.size(); ++i)
+            fac[i] = &s->factors.at(w.reqs[i].r.factor_id);   // pinned by refs: the entry stays
+    }
+    std::vector<int> status(w.reqs.size(), RTRI_OK);
+    std::vector<rtri_refine_info> info(w.reqs.size());
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < w.reqs.size() && e == hipSuccess; ++i) {
+        const rtri_request &r = w.reqs[i].r;
+        if (fac[i]->ready != nullptr)
+            e = hipStreamWaitEvent(st, fac[i]->ready, 0);
+        if (e == hipSuccess)
+            e = hipMallocAsync((void **)&rhs[i], w.reqs[i].rhs_bytes, st);
+        if (e == hipSuccess && rtri_synth_fill(h, RTRI_F64, 0, s->cfg.synth_seed, 2u, r.rhs_id, r.m, r.n, 0.0, rhs[i],
+                                               r.m) != RTRI_OK)
+            e = hipErrorUnknown;
+    }
+    if (e == hipSuccess) {
+        if (w.batched) {
+            std::vector<rtri_batch_entry> be(w.reqs.size());
+            for (size_t i = 0; i < w.reqs.size(); ++i) {
+                const rtri_request &r = w.reqs[i].r;
+                be[i] = rtri_batch_entry{r.op, r.side, r.uplo, r.trans, r.diag, r.m, r.n, r.alpha, fac[i]->ptr,
+                                         fac[i]->lda, rhs[i], r.m};
+            }
+            int bad = -1;
+            const int rc = batch_run_async(h, RTRI_F64, (int)be.size(), be.data(), slot.sc, &bad, nullptr);
+            for (auto &x : status)
+                x = rc;
+        } else {
+            const rtri_request &r = w.reqs[0].r;
+            int rc;
+            if (r.precision == RTRI_PREC_F64)
+                rc = r.op == 0 ? rtri_dtrsm(h, r.side, r.uplo, r.trans, r.diag, r.m, r.n, r.alpha, fac[0]->ptr,
+                                            fac[0]->lda, rhs[0], r.m)
+                               : rtri_dtrmm(h, r.side, r.uplo, r.trans, r.diag, r.m, r.n, r.alpha, fac[0]->ptr,
+                                            fac[0]->lda, rhs[0], r.m);
+            else if (r.op != 0)
+                rc = RTRI_ERR_UNSUPPORTED;
+            else
+                rc = rtri_dtrsm_mixed(h, r.side, r.uplo, r.trans, r.diag, r.m, r.n, r.alpha, fac[0]->ptr, fac[0]->lda,
+                                      rhs[0], r.m, r.precision == RTRI_PREC_MIXED_BF16 ? RTRI_BF16 : RTRI_F32, 1e-12,
+                                      30, &info[0]);
+            status[0] = rc;
+        }
+        for (size_t i = 0; i < w.reqs.size() && e == hipSuccess; ++i)
+            if (w.reqs[i].r.result != nullptr && status[i] == RTRI_OK)
+                e = hipMemcpyAsync(w.reqs[i].r.result, rhs[i], w.reqs[i].rhs_bytes, hipMemcpyDeviceToHost, st);
+    }
+    for (size_t i = 0; i < w.reqs.size(); ++i)
+        if (rhs[i] != nullptr)
+            (void)hipFreeAsync(rhs[i], st);
+    const hipError_t se = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = se;
+    const double t_done = now_s(s);
+    for (size_t i = 0; i < w.reqs.size(); ++i) {
+        rtri_completion c{};
+        c.ticket = w.reqs[i].ticket;
+        c.status = e != hipSuccess ? RTRI_ERR_HIP : status[i];
+        c.batched = w.batched ? 1 : 0;
+        c.iters = info[i].iters;
+        c.eta = info[i].eta;
+        c.t_arrival = w.reqs[i].r.t_arrival;
+        c.t_start = t_start;
+        c.t_done = t_done;
+        out.push_back(c);
+    }
+}
+
+void worker(rtri_server *s, int idx)
+{
+    rtri_server::Slot &slot = s->slots[idx];
+    (void)hipSetDevice(s->device);
+    std::vector<rtri_completion> out;
+    for (;;) {
+        Work w;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (;;) {
+                if (s->stopping && s->pending.empty())
+                    return;
+                take_work(s, slot, w);
+                if (!w.reqs.empty())
+                    break;
+                if (!s->pending.empty()) {
+                    const double wait = s->pending.front().r.t_arrival - now_s(s);
+                    // not yet arrived, or waiting for memory: wake at the arrival or on any release
+                    s->cv.wait_for(lk, std::chrono::duration<double>(wait > 0 ? std::min(wait, 0.01) : 0.001));
+                } else {
+                    s->cv.wait(lk);
+                }
+            }
+        }
+        out.clear();
+        execute(s, slot, w, out);
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t i = 0; i < w.reqs.size(); ++i) {
+                const Req &q = w.reqs[i];
+                Factor &f = s->factors.at(q.r.factor_id);
+                f.refs -= 1;
+                s->used -= (int64_t)q.rhs_bytes;
+                const int64_t vecs = q.r.side == RTRI_LEFT ? q.r.n : q.r.m;
+                if (out[i].status == RTRI_OK)
+                    s->st.useful_flops += (double)q.ka * q.ka * (double)vecs;
+                else
+                    s->st.failed += 1;
+            }
+            // the slot's handle keeps its largest workspace: count what it holds now
+            const size_t held = handle_ws_bytes(slot.h);
+            s->used += (int64_t)held - (int64_t)(slot.ws_held + w.ws_extra);
+            slot.ws_held = held;
+            s->st.completed += (int64_t)w.reqs.size();
+            s->st.launches += 1;
+            if (w.batched) {
+                s->st.batched_launches += 1;
+                s->st.batched_requests += (int64_t)w.reqs.size();
+            }
+            s->st.hbm_in_use = s->used;
+            s->st.hbm_peak = std::max(s->st.hbm_peak, s->used);
+            s->done.insert(s->done.end(), out.begin(), out.end());
+            s->outstanding -= (int64_t)w.reqs.size();
+        }
+        s->cv.notify_all();
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int rtri_server_create(const rtri_server_cfg *cfg, rtri_server **out)
+{
+    if (cfg == nullptr || out == nullptr)
+        return -1;
+    if (cfg->slots < 1 || cfg->slots > 16)
+        return -2;
+    if (cfg->hbm_budget <= 0)
+        return -3;
+    if (cfg->max_batch < 1)
+        return -4;
+    rtri_server *s = new (std::nothrow) rtri_server();
+    if (s == nullptr)
+        return RTRI_ERR_NOMEM;
+    s->cfg = *cfg;
+    s->t0 = Clock::now();
+    hipError_t e = hipGetDevice(&s->device);
+    s->slots.resize(cfg->slots);
+    for (auto &sl : s->slots) {
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess && rtri_create(&sl.h, sl.stream) != RTRI_OK)
+            e = hipErrorOutOfMemory;
+    }
+    if (e != hipSuccess) {
+        for (auto &sl : s->slots) {
+            if (sl.h)
+                rtri_destroy(sl.h);
+            if (sl.stream)
+                (void)hipStreamDestroy(sl.stream);
+        }
+        delete s;
+        return RTRI_ERR_HIP;
+    }
+    for (int i = 0; i < cfg->slots; ++i)
+        s->slots[i].th = std::thread(worker, s, i);
+    *out = s;
+    return RTRI_OK;
+}
+
+int rtri_server_register_factor(rtri_server *s, uint64_t id, int64_t ka, int uplo, const double *A, int64_t lda)
+{
+    if (s == nullptr)
+        return -1;
+    if (ka < 0)
+        return -3;
+    if (uplo != RTRI_LOWER && uplo != RTRI_UPPER)
+        return -4;
+    if (A == nullptr && ka > 0)
+        return -5;
+    if (lda < std::max<int64_t>(1, ka))
+        return -6;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->factors.count(id))
+        return RTRI_ERR_INVALID;
+    Factor f;
+    f.ptr = const_cast<double *>(A);
+    f.ka = ka;
+    f.lda = lda;
+    f.uplo = uplo;
+    f.registered = true;
+    s->factors.emplace(id, f);
+    return RTRI_OK;
+}
+
+int rtri_server_submit(rtri_server *s, const rtri_request *r, uint64_t *ticket)
+{
+    if (s == nullptr || r == nullptr)
+        return -1;
+    int rc = (r->op == 0 || r->op == 1) ? check_args(r->side, r->uplo, r->trans, r->diag, r->m, r->n,
+                                                     (const void *)1, r->side == RTRI_LEFT ? r->m : r->n,
+                                                     (const void *)1, std::max<int64_t>(1, r->m), false)
+                                        : -2;
+    if (rc != 0)
+        return rc;
+    if (r->precision < RTRI_PREC_F64 || r->precision > RTRI_PREC_MIXED_F32 || (r->precision != RTRI_PREC_F64 && r->op != 0))
+        return RTRI_ERR_UNSUPPORTED;
+    Req q;
+    q.r = *r;
+    q.ka = r->side == RTRI_LEFT ? r->m : r->n;
+    q.rhs_bytes = (size_t)std::max<int64_t>(1, r->m * r->n) * 8;
+    q.ws_bytes = ws_estimate(*r, q.ka);
+    q.small = r->precision == RTRI_PREC_F64 && q.ka <= s->cfg.small_max && r->m > 0 && r->n > 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        q.ticket = s->next_ticket++;
+        if (ticket != nullptr)
+            *ticket = q.ticket;
+        s->st.submitted += 1;
+        s->outstanding += 1;
+        if (r->m == 0 || r->n == 0) {
+            rtri_completion c{};
+            c.ticket = q.ticket;
+            c.t_arrival = r->t_arrival;
+            c.t_start = c.t_done = now_s(s);
+            s->done.push_back(c);
+            s->st.completed += 1;
+            s->outstanding -= 1;
+        } else {
+            s->pending.push_back(q);
+        }
+    }
+    s->cv.notify_all();
+    return RTRI_OK;
+}
+
+int rtri_server_poll(rtri_server *s, rtri_completion *out, int max, int *n)
+{
+    if (s == nullptr || n == nullptr || (out == nullptr && max > 0))
+        return -1;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const int k = std::min<int>(std::max(0, max), (int)s->done.size());
+    for (int i = 0; i < k; ++i)
+        out[i] = s->done[i];
+    s->done.erase(s->done.begin(), s->done.begin() + k);
+    *n = k;
+    return RTRI_OK;
+}
+
+int rtri_server_drain(rtri_server *s)
+{
+    if (s == nullptr)
+        return -1;
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv.wait(lk, [&] { return s->outstanding == 0; });
+    return RTRI_OK;
+}
+
+int rtri_server_stats(rtri_server *s, rtri_server_counters *out)
+{
+    if (s == nullptr || out == nullptr)
+        return -1;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    return RTRI_OK;
+}
+
+double rtri_server_now(rtri_server *s) { return s == nullptr ? 0.0 : now_s(s); }
+
+int rtri_server_destroy(rtri_server *s)
+{
+    if (s == nullptr)
+        return -1;
+    rtri_server_drain(s);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv.notify_all();
+    for (auto &sl : s->slots)
+        if (sl.th.joinable())
+            sl.th.join();
+    for (auto &sl : s->slots)
+        (void)hipStreamSynchronize(sl.stream);
+    for (auto &kv : s->factors) {
+        if (!kv.second.registered && kv.second.ptr != nullptr)
+            (void)hipFree(kv.second.ptr);
+        if (kv.second.ready != nullptr)
+            (void)hipEventDestroy(kv.second.ready);
+    }
+    for (auto &sl : s->slots) {
+        batch_scratch_free(sl.sc);
+        rtri_destroy(sl.h);
+        (void)hipStreamDestroy(sl.stream);
+    }
+    delete s;
+    return RTRI_OK;
+}
+
+}  // extern "C"

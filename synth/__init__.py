@@ -153,3 +153,46 @@ def batch_shapes(count: int, g: np.random.Generator, m_lo: int = 16, m_hi: int =
     ns = g.integers(n_lo, n_hi + 1, size=count)
     uplos = np.where(g.random(count) < 0.5, "L", "U")
     return [(int(m), int(n), str(u)) for m, n, u in zip(ms, ns, uplos)]
+
+
+# ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), counter-based -------
+_PHILOX_M0, _PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+_PHILOX_W0, _PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+_M32 = 0xFFFFFFFF
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Vectorised Philox4x32-10 on arrays of 32-bit words (held as uint64)."""
+    c0, c1, c2, c3 = (np.asarray(x, dtype=np.uint64) & _M32 for x in (c0, c1, c2, c3))
+    k0 = np.asarray(k0, dtype=np.uint64) & _M32
+    k1 = np.asarray(k1, dtype=np.uint64) & _M32
+    for _ in range(10):
+        p0 = np.uint64(_PHILOX_M0) * c0
+        p1 = np.uint64(_PHILOX_M1) * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & np.uint64(_M32)
+        hi1, lo1 = p1 >> np.uint64(32), p1 & np.uint64(_M32)
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+        k0 = (k0 + np.uint64(_PHILOX_W0)) & np.uint64(_M32)
+        k1 = (k1 + np.uint64(_PHILOX_W1)) & np.uint64(_M32)
+    return c0, c1, c2, c3
+
+
+def philox_matrix(kind: int, seed: int, stream: int, ident: int, m: int, n: int, param: float = 0.0) -> np.ndarray:
+    """The host twin of the library's on-device synthetic fill: element (i, j)
+    from counter (i, j, id_lo, id_hi), key (seed_lo ^ stream, seed_hi);
+    u = 53 bits of words (1, 0) * 2^-53.  kind 0: 2u-1; kind 1 / 2: lower / upper
+    triangular with off-diagonal 2u-1, diagonal param + u, zero elsewhere."""
+    i = np.repeat(np.arange(m, dtype=np.uint64)[:, None], n, axis=1)
+    j = np.repeat(np.arange(n, dtype=np.uint64)[None, :], m, axis=0)
+    k0 = (seed & _M32) ^ (stream & _M32)
+    k1 = (seed >> 32) & _M32
+    x0, x1, _, _ = philox4x32_10(i, j, ident & _M32, (ident >> 32) & _M32, k0, k1)
+    bits = ((x1 << np.uint64(32)) | x0) >> np.uint64(11)
+    u = bits.astype(np.float64) * 2.0 ** -53
+    if kind == 0:
+        out = 2.0 * u - 1.0
+    else:
+        ii, jj = np.indices((m, n))
+        tri = (ii >= jj) if kind == 1 else (ii <= jj)
+        out = np.where(tri, np.where(ii == jj, param + u, 2.0 * u - 1.0), 0.0)
+    return np.asfortranarray(out)

@@ -319,3 +319,19 @@ def test_cond_one_diagonal(orc):
     d = np.array([1.0, 4.0, 0.5, 2.0])
     A = np.diag(d).copy(order="F")
     assert orc.cond_one("L", "N", A) == pytest.approx(d.max() / d.min(), rel=1e-15)
+
+
+# ---- the counter-based input generator against its published answers ----------
+
+def test_philox_known_answers():
+    """Known-answer vectors of Philox4x32-10 published with the Random123
+    library (Salmon et al., SC'11): zero, all-ones and pi-digit inputs."""
+    cases = [
+        ((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+        ((0xffffffff,) * 4, (0xffffffff,) * 2, (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+        ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+         (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+    ]
+    for c, k, want in cases:
+        got = tuple(int(v) for v in synth.philox4x32_10(*c, *k))
+        assert got == want, [hex(v) for v in got]
