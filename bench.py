@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--leaf", type=int, default=0)
+    ap.add_argument("--no-extras", action="store_true", help="only the headline step")
+    ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--tuning", default="", help="tuning database (default: the package's, if present)")
     return ap.parse_args()
 
 
@@ -61,6 +64,9 @@ def main():
     B0d = rt.to_device(B0, torch.float64)
     Bd = rt.to_device(B0, torch.float64)
     h = rt.Handle()
+    tuning = args.tuning or (rt.TUNING_DB if os.path.exists(rt.TUNING_DB) else "")
+    if tuning:
+        h.load_tuning(tuning)
     if args.leaf:
         h.set_option(rt.OPT_LEAF_F64, args.leaf)
 
@@ -144,9 +150,171 @@ def main():
         "profiled_kernel_ms_per_step": round(prof_total_ms, 3),
     }
 
+    out["tuning_db"] = os.path.basename(tuning) if tuning else None
     if not args.no_cpu:
         out["cpu_baseline"], out["eta_sampled"] = cpu_baseline(rt, torch, h, A, B0, B0d, Ad, Bd, m, n)
+    del Ad, Bd, B0d
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["mixed"] = bench_mixed(rt, torch, h)
+        out["batched"] = bench_batched(rt, torch, h)
+        out["serving"] = bench_serving(rt, args.serve_requests)
     print(json.dumps(out), flush=True)
+
+
+def _event_ms(torch, fn, prep=None, reps=3):
+    ts = []
+    for _ in range(reps):
+        if prep is not None:
+            prep()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return min(ts)
+
+
+def bench_mixed(rt, torch, h, m=8192):
+    """Mixed-precision refined TRSM against the plain FP64 TRSM on the same
+    system: m = n = 8192, lower factor with off-diagonal U(-1,1) and diagonal
+    45 + U(0,1) (cond_1 ~ 1e4), dense right-hand sides U(-1,1); inputs drawn on
+    the device (Philox)."""
+    import synth
+    Ad = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
+    B0 = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
+    rt.synth_fill(h, 1, synth.SEED, synth.W_MIXED, 1, Ad, param=45.0)
+    rt.synth_fill(h, 0, synth.SEED, synth.W_MIXED, 2, B0)
+    Bd = B0.clone()
+    res = {"workload": f"FP64-accurate TRSM L/L/N/N m=n={m}, diagonal 45+U(0,1) (cond_1 ~ 1e4), tol 1e-12"}
+    t_plain = _event_ms(torch, lambda: rt.trsm(h, "L", "L", "N", "N", 1.0, Ad, Bd), lambda: Bd.copy_(B0))
+    res["fp64_ms"] = round(t_plain, 3)
+    for gemm in ("bf16", "f32"):
+        info = {}
+
+        def run():
+            info.update(rt.trsm_mixed(h, "L", "L", "N", "N", 1.0, Ad, Bd, gemm=gemm, tol=1e-12, max_iter=30))
+        t = _event_ms(torch, run, lambda: Bd.copy_(B0))
+        res[gemm] = {"ms": round(t, 3), "speedup_vs_fp64": round(t_plain / t, 3), "iters": info["iters"],
+                     "eta": info["eta"], "converged": info["converged"],
+                     "useful_tflops": round(m ** 3 / (t * 1e-3) / 1e12, 3)}
+    return res
+
+
+def bench_batched(rt, torch, h, count=4096):
+    """4096 independent problems, m log-uniform [16,1024], nrhs uniform [1,128],
+    uplo 50/50, factors with diagonal m + U(0,1); one graph-replayed persistent
+    launch per dtype and op.  TRSM and TRMM run in place on the same operands, so
+    the values stay bounded across repetitions."""
+    import synth
+    res = {"workload": f"{count} problems, m log-uniform [16,1024], nrhs uniform [1,128], side L, trans N"}
+    for dt, td, es in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        g = synth.rng(synth.W_BATCH, 0)
+        shapes = synth.batch_shapes(count, g)
+        As, Bs = [], []
+        for i, (mm, nn, u) in enumerate(shapes):
+            As.append(rt.synth_fill(h, 1 if u == "L" else 2, synth.SEED, synth.W_BATCH, 2 * i,
+                                    torch.empty((mm, mm), dtype=td, device="cuda").t(), param=float(mm)))
+            Bs.append(rt.synth_fill(h, 0, synth.SEED, synth.W_BATCH, 2 * i + 1,
+                                    torch.empty((nn, mm), dtype=td, device="cuda").t()))
+        flops = sum(mm * mm * nn for (mm, nn, u) in shapes)
+        byts = sum(es * (mm * (mm + 1) / 2 + 2 * mm * nn) for (mm, nn, u) in shapes)
+        peak = 78.6e12 if dt == "f64" else 157.3e12
+        bound_ms = sum(max(mm * mm * nn / peak, es * (mm * (mm + 1) / 2 + 2 * mm * nn) / 8e12)
+                       for (mm, nn, u) in shapes) * 1e3
+        for op in ("trsm", "trmm"):
+            plan = rt.BatchPlan(h, [(op, "L", u, "N", "N", 1.0, As[i], Bs[i]) for i, (mm, nn, u) in enumerate(shapes)])
+            plan.run()
+            torch.cuda.synchronize()
+            t = _event_ms(torch, plan.run, reps=5)
+            res[f"{op}_{dt}"] = {"ms": round(t, 4), "tflops": round(flops / (t * 1e-3) / 1e12, 3),
+                                 "bound_ms": round(bound_ms, 4), "frac_of_bound": round(bound_ms / t, 3),
+                                 "chunks": plan.chunks(), "algorithmic_GB": round(byts / 1e9, 3)}
+            plan.close()
+        del As, Bs
+    return res
+
+
+def serving_stream(count, seed_key=0):
+    """TRSM 80 % / TRMM 20 %; m log-uniform [32,8192]; nrhs log-uniform [1,512];
+    FP64 or mixed (BF16) 50/50 for TRSM; factors shared by 1-16 requests spread
+    over a 256-request window; uplo and trans 50/50; side L."""
+    import numpy as np
+    import synth
+    g = synth.rng(synth.W_SERVE, 1000, seed_key)
+    reqs = [None] * count
+    slots = list(range(count))
+    fid = 0
+    free = list(range(count))
+    g.shuffle(free)
+    order = np.argsort(g.random(count))
+    i = 0
+    pos = 0
+    while pos < count:
+        fid += 1
+        uses = int(g.integers(1, 17))
+        ka = int(synth.loguniform_int(g, 32, 8192, 1)[0])
+        uplo = "L" if g.random() < 0.5 else "U"
+        start = pos
+        idxs = [start]
+        for _ in range(uses - 1):
+            j = start + int(g.integers(1, 256))
+            if j < count:
+                idxs.append(j)
+        for j in idxs:
+            while j < count and reqs[j] is not None:
+                j += 1
+            if j >= count:
+                continue
+            op = "trsm" if g.random() < 0.8 else "trmm"
+            prec = (0 if g.random() < 0.5 else 1) if op == "trsm" else 0
+            reqs[j] = dict(op=op, side="L", uplo=uplo, trans="N" if g.random() < 0.5 else "T", diag="N", m=ka,
+                           n=int(synth.loguniform_int(g, 1, 512, 1)[0]), alpha=1.0, precision=prec, factor_id=fid,
+                           rhs_id=j + 1)
+        while pos < count and reqs[pos] is not None:
+            pos += 1
+    return reqs
+
+
+def bench_serving(rt, count):
+    import numpy as np
+    import synth
+    reqs = serving_stream(count)
+    flops = sum(r["m"] * r["m"] * r["n"] for r in reqs)
+    res = {"workload": f"{count} requests (TRSM 80%/TRMM 20%, m log-uniform [32,8192], nrhs log-uniform [1,512], "
+                       "FP64 or mixed+IR 50/50 for TRSM, factors shared by 1-16 requests), 64 GB budget",
+           "requests": count}
+
+    def run(rate):
+        srv = rt.Server(slots=4, hbm_budget=64 << 30, max_batch=128, small_max=1024)
+        t0 = srv.now() + 0.02
+        if rate is None:
+            arr = np.full(count, t0)
+        else:
+            arr = t0 + np.cumsum(synth.rng(synth.W_SERVE, 2000, int(rate)).exponential(1.0 / rate, count))
+        for r, ta in zip(reqs, arr):
+            srv.submit(t_arrival=float(ta), **r)
+        srv.drain()
+        comps = srv.poll(count + 16)
+        st = srv.stats()
+        srv.close()
+        lat = np.array([c["t_done"] - c["t_arrival"] for c in comps])
+        span = max(c["t_done"] for c in comps) - t0
+        bad = sum(1 for c in comps if c["status"] not in (0,))
+        return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                "solves_per_s": round(count / span, 1), "busy_tflops": round(flops / span / 1e12, 3),
+                "errors": bad, "batched_requests": st["batched_requests"], "launches": st["launches"],
+                "factor_hits": st["factor_hits"], "factor_misses": st["factor_misses"],
+                "evictions": st["evictions"], "hbm_peak_GB": round(st["hbm_peak"] / 1e9, 2)}
+    sat = run(None)
+    res["saturation"] = sat
+    mu = sat["solves_per_s"]
+    res["rates"] = {}
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        res["rates"][str(frac)] = dict(run(frac * mu), rate_per_s=round(frac * mu, 1))
+    return res
 
 
 def cpu_baseline(rt, torch, h, A, B0, B0d, Ad, Bd, m, n):

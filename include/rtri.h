@@ -213,6 +213,22 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
 int rtri_synth_fill(rtri_handle *h, int dtype, int kind, uint64_t seed, uint32_t stream, uint64_t id, int64_t m,
                     int64_t n, double param, void *X, int64_t ldx);
 
+/* Tuning: time leaf sizes (16 / 32 / 64) for TRSM and TRMM at factor orders
+ * 256, 512, ... up to max_order and 64 / 512 / 4096 vectors, and the GEMM tile
+ * (128x128 or 64x64) at M = K = 64 ... min(max_order / 2, 8192) and the same
+ * vector counts, on synthetic inputs in device memory the call allocates and
+ * frees; keep the winners in the handle (rules for the other dtype are kept)
+ * and, if db_path != NULL, write them there as JSON.  Blocking.  Options set
+ * with rtri_set_option still take precedence.  Codes: -2 dtype, -3 max_order
+ * < 256; RTRI_ERR_INVALID if the file cannot be written. */
+int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path);
+
+/* Load a tuning database written by rtri_tune into the handle (replacing any
+ * earlier one).  A handle created while the environment variable RTRI_TUNE_DB
+ * names such a file loads it automatically.  RTRI_ERR_INVALID if the file is
+ * missing or malformed. */
+int rtri_load_tuning(rtri_handle *h, const char *path);
+
 /* ---- batched independent problems (one persistent launch) ----------------- */
 
 /* One problem of a batch: TRSM (op = 0, eqs. (3)/(4)) or TRMM (op = 1,

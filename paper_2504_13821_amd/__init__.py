@@ -121,6 +121,9 @@ rtri_server_drain = _sig("rtri_server_drain", _int, _vp)
 rtri_server_stats = _sig("rtri_server_stats", _int, _vp, ctypes.POINTER(Counters))
 rtri_server_now = _sig("rtri_server_now", ctypes.c_double, _vp)
 rtri_server_destroy = _sig("rtri_server_destroy", _int, _vp)
+rtri_tune = _sig("rtri_tune", _int, _vp, _int, _i64, ctypes.c_char_p)
+rtri_load_tuning = _sig("rtri_load_tuning", _int, _vp, ctypes.c_char_p)
+TUNING_DB = os.path.join(_HERE, "tuning", "gfx950.json")
 rtri_gemm_update = _sig("rtri_gemm_update", _int, _vp, _int, _int, _int, _i64, _i64, _i64, ctypes.c_double, _vp,
                         _i64, _vp, _i64, ctypes.c_double, _vp, _i64)
 
@@ -185,6 +188,14 @@ class Handle:
 
     def sync(self):
         check(rtri_sync(self._h), "rtri_sync")
+
+    def tune(self, dtype="f64", max_order=16384, db_path=None):
+        """Run the tuning sweep (blocking) and keep its rules; optionally write them as JSON."""
+        check(rtri_tune(self._h, {"f64": F64, "f32": F32}[dtype], max_order,
+                        db_path.encode() if db_path else None), "rtri_tune")
+
+    def load_tuning(self, path=TUNING_DB):
+        check(rtri_load_tuning(self._h, path.encode()), "rtri_load_tuning")
 
     def profile_begin(self):
         check(rtri_profile_begin(self._h), "rtri_profile_begin")

@@ -24,6 +24,7 @@
 // so every leaf but the last one is full and GEMM operands stay aligned.  The
 // plan is a flat list of launches; one pack pass before it writes every
 // diagonal block in the canonical form the leaf kernel reads.
+#include <cstdlib>
 #include <cstring>
 
 #include "handle.h"
@@ -246,9 +247,11 @@ int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, co
     return 0;
 }
 
-int pick_leaf(const rtri_handle *h, DType t)
+int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nvec)
 {
-    const int leaf = t == DType::F64 ? h->leaf_f64 : h->leaf_f32;
+    int leaf = t == DType::F64 ? h->leaf_f64 : h->leaf_f32;
+    if (leaf == 0)
+        leaf = tuned_leaf(h->tune, t == DType::F64 ? RTRI_F64 : RTRI_F32, solve, ka, nvec);
     return leaf == 0 ? 64 : leaf;
 }
 
@@ -303,8 +306,10 @@ int run_plan(rtri_handle *h, const PlanIn &p)
                 e = timed(h, RTRI_KCLASS_GEMM, dtype_code(p.gt), gemm_flops(op.g), bytes,
                           [&] { return launch_gemm16(p.gt == ElemT::BF16, left, op.g, h->stream); });
             else
-                e = timed(h, RTRI_KCLASS_GEMM, pcode, gemm_flops(op.g), bytes,
-                          [&] { return launch_gemm(bt, op.g, h->gemm_tile, h->stream); });
+                e = timed(h, RTRI_KCLASS_GEMM, pcode, gemm_flops(op.g), bytes, [&] {
+                    const int tile = h->gemm_tile ? h->gemm_tile : tuned_tile(h->tune, pcode, op.g.M, op.g.N);
+                    return launch_gemm(bt, op.g, tile, h->stream);
+                });
         } else {
             e = timed(h, p.solve ? RTRI_KCLASS_LEAF_SOLVE : RTRI_KCLASS_LEAF_MULT, pcode, leaf_flops(op.l),
                       leaf_bytes(op.l, es), [&] { return launch_leaf(bt, p.solve, p.leaf, op.l, h->stream); });
@@ -354,7 +359,7 @@ int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int 
     p.st = p.gt;
     p.As = A;
     p.ldas = lda;
-    p.leaf = pick_leaf(h, t);
+    p.leaf = pick_leaf(h, t, solve, side == RTRI_LEFT ? m : n, side == RTRI_LEFT ? n : m);
     p.pack_slot = WS_PACK;
     p.skip_pack = false;
     return run_plan(h, p);
@@ -376,6 +381,7 @@ int rtri_create(rtri_handle **out, void *stream)
     h->leaf_f64 = 0;
     h->leaf_f32 = 0;
     h->gemm_tile = 0;
+    h->tune = nullptr;
     h->last = hipSuccess;
     for (int i = 0; i < WS_COUNT; ++i) {
         h->ws[i] = nullptr;
@@ -383,6 +389,9 @@ int rtri_create(rtri_handle **out, void *stream)
     }
     h->profiling = false;
     h->pool_used = 0;
+    // a tuning database named by the environment applies to every new handle
+    if (const char *db = std::getenv("RTRI_TUNE_DB"))
+        (void)load_tuning_file(h, db);
     *out = h;
     return RTRI_OK;
 }
@@ -402,6 +411,7 @@ int rtri_destroy(rtri_handle *h)
             (void)hipFree(h->ws[i]);
     for (hipEvent_t e : h->pool)
         (void)hipEventDestroy(e);
+    tune_db_free(h->tune);
     delete h;
     return RTRI_OK;
 }
@@ -597,8 +607,10 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
     g.ldc = ldc;
     const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
     const size_t es = t == DType::F64 ? 8 : 4;
-    hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, es, es, es),
-                         [&] { return launch_gemm(t, g, h->gemm_tile, h->stream); });
+    hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, es, es, es), [&] {
+        const int tile = h->gemm_tile ? h->gemm_tile : tuned_tile(h->tune, dtype, g.M, g.N);
+        return launch_gemm(t, g, tile, h->stream);
+    });
     return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
 }
 

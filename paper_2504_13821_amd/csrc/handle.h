@@ -9,6 +9,13 @@
 
 namespace rtri {
 
+struct TuneDB;   // tuned leaf sizes and GEMM tiles (tune.hip)
+void tune_db_free(TuneDB *db);
+// 0 when the database has no rule for the case
+int tuned_leaf(const TuneDB *db, int dtype, bool solve, int64_t ka, int64_t nvec);
+int tuned_tile(const TuneDB *db, int dtype, int64_t M, int64_t N);
+int load_tuning_file(rtri_handle *h, const char *path);
+
 struct ProfRec {
     int kclass, dtype;
     double flops, bytes;
@@ -57,6 +64,7 @@ struct rtri_handle {
     uint32_t magic;
     hipStream_t stream;
     int leaf_f64, leaf_f32, gemm_tile;
+    rtri::TuneDB *tune;
     hipError_t last;
     void *ws[rtri::WS_COUNT];
     size_t ws_bytes[rtri::WS_COUNT];
@@ -71,7 +79,8 @@ namespace rtri {
 bool handle_valid(const rtri_handle *h);
 int hip_fail(rtri_handle *h, hipError_t e);
 hipError_t ensure_ws(rtri_handle *h, int slot, size_t bytes);
-int pick_leaf(const rtri_handle *h, DType t);
+// leaf size: the handle's option, else the tuning database, else 64
+int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nvec);
 int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, const void *A, int64_t lda,
                const void *B, int64_t ldb, bool need_a);
 // enqueue a whole plan on the handle's stream (returns an RTRI_* status)

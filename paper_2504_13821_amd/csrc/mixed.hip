@@ -81,7 +81,7 @@ int rtri_trmm_ex(rtri_handle *h, int side, int uplo, int trans, int diag, int64_
     p.st = et;
     p.As = A;
     p.ldas = lda;
-    p.leaf = pick_leaf(h, DType::F32);
+    p.leaf = pick_leaf(h, DType::F32, false, side == RTRI_LEFT ? m : n, side == RTRI_LEFT ? n : m);
     p.pack_slot = WS_PACK;
     p.skip_pack = false;
     return run_plan(h, p);
@@ -190,7 +190,7 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
     lo.st = ElemT::F64;
     lo.As = A;
     lo.ldas = lda;
-    lo.leaf = pick_leaf(h, DType::F32);
+    lo.leaf = pick_leaf(h, DType::F32, true, ka, left ? n : m);
     lo.pack_slot = WS_PACK2;
     lo.skip_pack = false;
 
@@ -212,7 +212,7 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
     mul.st = ElemT::F64;
     mul.As = A;
     mul.ldas = lda;
-    mul.leaf = pick_leaf(h, DType::F64);
+    mul.leaf = pick_leaf(h, DType::F64, false, ka, left ? n : m);
     mul.pack_slot = WS_PACK;
     mul.skip_pack = false;
 

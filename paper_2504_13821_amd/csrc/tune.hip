@@ -1,0 +1,454 @@
+// Tuning: choose the leaf size (the recursion's cut-over, "a chosen
+// threshold" in the paper, Sec. 3.1) and the GEMM tile shape by timing real
+// shapes on the device, keep the winners as rules in a small JSON database,
+// and consult them when a call does not fix the choice itself.
+//
+// Database (one file per architecture):
+//   {"arch": "gfx950", "version": 1,
+//    "leaf": [{"dtype": "f64", "op": "trsm", "ka_max": 1024, "n_max": 512, "leaf": 32}, ...],
+//    "gemm_tile": [{"dtype": "f64", "m_max": 256, "n_max": 4096, "tile": 2}, ...]}
+// A leaf rule covers factor orders up to ka_max and vector counts up to n_max
+// (the smallest covering bucket wins; beyond the largest, the largest applies).
+#include <algorithm>
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+
+#include "handle.h"
+
+using namespace rtri;
+
+namespace rtri {
+
+struct TuneDB {
+    struct Leaf {
+        int dtype, solve;
+        int64_t ka_max, n_max;
+        int leaf;
+    };
+    struct Tile {
+        int dtype;
+        int64_t m_max, n_max;
+        int tile;
+    };
+    std::vector<Leaf> leaf;
+    std::vector<Tile> tile;
+};
+
+namespace {
+
+// ---- a minimal JSON reader for the database schema (objects, arrays, strings, numbers) ----
+struct JVal {
+    enum Kind { NUL, NUM, STR, ARR, OBJ } kind = NUL;
+    double num = 0;
+    std::string str;
+    std::vector<JVal> arr;
+    std::map<std::string, JVal> obj;
+};
+
+struct JParser {
+    const char *p, *end;
+    bool ok = true;
+    void ws()
+    {
+        while (p < end && std::isspace((unsigned char)*p))
+            ++p;
+    }
+    bool eat(char c)
+    {
+        ws();
+        if (p < end && *p == c) {
+            ++p;
+            return true;
+        }
+        return false;
+    }
+    std::string string_lit()
+    {
+        std::string s;
+        if (!eat('"')) {
+            ok = false;
+            return s;
+        }
+        while (p < end && *p != '"') {
+            if (*p == '\\' && p + 1 < end)
+                ++p;
+            s.push_back(*p++);
+        }
+        if (p < end)
+            ++p;
+        else
+            ok = false;
+        return s;
+    }
+    JVal value()
+    {
+        JVal v;
+        ws();
+        if (p >= end) {
+            ok = false;
+            return v;
+        }
+        if (*p == '{') {
+            ++p;
+            v.kind = JVal::OBJ;
+            if (eat('}'))
+                return v;
+            do {
+                std::string k = string_lit();
+                if (!eat(':')) {
+                    ok = false;
+                    return v;
+                }
+                v.obj[k] = value();
+            } while (ok && eat(','));
+            if (!eat('}'))
+                ok = false;
+        } else if (*p == '[') {
+            ++p;
+            v.kind = JVal::ARR;
+            if (eat(']'))
+                return v;
+            do {
+                v.arr.push_back(value());
+            } while (ok && eat(','));
+            if (!eat(']'))
+                ok = false;
+        } else if (*p == '"') {
+            v.kind = JVal::STR;
+            v.str = string_lit();
+        } else {
+            char *q = nullptr;
+            v.num = std::strtod(p, &q);
+            if (q == p)
+                ok = false;
+            else
+                v.kind = JVal::NUM;
+            p = q;
+        }
+        return v;
+    }
+};
+
+int dtype_of(const std::string &s) { return s == "f64" ? RTRI_F64 : s == "f32" ? RTRI_F32 : -1; }
+const char *dtype_name(int d) { return d == RTRI_F64 ? "f64" : "f32"; }
+
+double num_of(const JVal &o, const char *k, bool &ok)
+{
+    auto it = o.obj.find(k);
+    if (it == o.obj.end() || it->second.kind != JVal::NUM) {
+        ok = false;
+        return 0;
+    }
+    return it->second.num;
+}
+std::string str_of(const JVal &o, const char *k, bool &ok)
+{
+    auto it = o.obj.find(k);
+    if (it == o.obj.end() || it->second.kind != JVal::STR) {
+        ok = false;
+        return "";
+    }
+    return it->second.str;
+}
+
+bool parse_db(const std::string &text, TuneDB &db)
+{
+    JParser jp{text.data(), text.data() + text.size()};
+    JVal root = jp.value();
+    if (!jp.ok || root.kind != JVal::OBJ)
+        return false;
+    bool ok = true;
+    auto lr = root.obj.find("leaf");
+    if (lr != root.obj.end() && lr->second.kind == JVal::ARR)
+        for (const JVal &e : lr->second.arr) {
+            TuneDB::Leaf r{dtype_of(str_of(e, "dtype", ok)), str_of(e, "op", ok) == "trsm" ? 1 : 0,
+                           (int64_t)num_of(e, "ka_max", ok), (int64_t)num_of(e, "n_max", ok),
+                           (int)num_of(e, "leaf", ok)};
+            if (r.dtype < 0 || (r.leaf != 16 && r.leaf != 32 && r.leaf != 64))
+                ok = false;
+            db.leaf.push_back(r);
+        }
+    auto tr = root.obj.find("gemm_tile");
+    if (tr != root.obj.end() && tr->second.kind == JVal::ARR)
+        for (const JVal &e : tr->second.arr) {
+            TuneDB::Tile r{dtype_of(str_of(e, "dtype", ok)), (int64_t)num_of(e, "m_max", ok),
+                           (int64_t)num_of(e, "n_max", ok), (int)num_of(e, "tile", ok)};
+            if (r.dtype < 0 || (r.tile != 1 && r.tile != 2))
+                ok = false;
+            db.tile.push_back(r);
+        }
+    return ok;
+}
+
+bool write_db(const char *path, const TuneDB &db)
+{
+    FILE *f = std::fopen(path, "w");
+    if (f == nullptr)
+        return false;
+    std::fprintf(f, "{\"arch\": \"gfx950\", \"version\": 1,\n \"leaf\": [");
+    for (size_t i = 0; i < db.leaf.size(); ++i) {
+        const auto &r = db.leaf[i];
+        std::fprintf(f, "%s\n  {\"dtype\": \"%s\", \"op\": \"%s\", \"ka_max\": %lld, \"n_max\": %lld, \"leaf\": %d}",
+                     i ? "," : "", dtype_name(r.dtype), r.solve ? "trsm" : "trmm", (long long)r.ka_max,
+                     (long long)r.n_max, r.leaf);
+    }
+    std::fprintf(f, "],\n \"gemm_tile\": [");
+    for (size_t i = 0; i < db.tile.size(); ++i) {
+        const auto &r = db.tile[i];
+        std::fprintf(f, "%s\n  {\"dtype\": \"%s\", \"m_max\": %lld, \"n_max\": %lld, \"tile\": %d}", i ? "," : "",
+                     dtype_name(r.dtype), (long long)r.m_max, (long long)r.n_max, r.tile);
+    }
+    std::fprintf(f, "]}\n");
+    return std::fclose(f) == 0;
+}
+
+// the smallest bucket covering x, or the largest if none covers it
+template <class R, class Get>
+const R *pick_bucket(const std::vector<const R *> &c, int64_t x, Get get)
+{
+    const R *best = nullptr, *largest = nullptr;
+    for (const R *r : c) {
+        if (largest == nullptr || get(*r) > get(*largest))
+            largest = r;
+        if (get(*r) >= x && (best == nullptr || get(*r) < get(*best)))
+            best = r;
+    }
+    return best ? best : largest;
+}
+
+}  // namespace
+
+void tune_db_free(TuneDB *db) { delete db; }
+
+int tuned_leaf(const TuneDB *db, int dtype, bool solve, int64_t ka, int64_t nvec)
+{
+    if (db == nullptr)
+        return 0;
+    std::vector<const TuneDB::Leaf *> c;
+    for (const auto &r : db->leaf)
+        if (r.dtype == dtype && r.solve == (solve ? 1 : 0))
+            c.push_back(&r);
+    if (c.empty())
+        return 0;
+    const TuneDB::Leaf *k = pick_bucket(c, ka, [](const TuneDB::Leaf &r) { return r.ka_max; });
+    std::vector<const TuneDB::Leaf *> c2;
+    for (const auto *r : c)
+        if (r->ka_max == k->ka_max)
+            c2.push_back(r);
+    return pick_bucket(c2, nvec, [](const TuneDB::Leaf &r) { return r.n_max; })->leaf;
+}
+
+int tuned_tile(const TuneDB *db, int dtype, int64_t M, int64_t N)
+{
+    if (db == nullptr)
+        return 0;
+    std::vector<const TuneDB::Tile *> c;
+    for (const auto &r : db->tile)
+        if (r.dtype == dtype)
+            c.push_back(&r);
+    if (c.empty())
+        return 0;
+    const TuneDB::Tile *k = pick_bucket(c, M, [](const TuneDB::Tile &r) { return r.m_max; });
+    std::vector<const TuneDB::Tile *> c2;
+    for (const auto *r : c)
+        if (r->m_max == k->m_max)
+            c2.push_back(r);
+    return pick_bucket(c2, N, [](const TuneDB::Tile &r) { return r.n_max; })->tile;
+}
+
+int load_tuning_file(rtri_handle *h, const char *path)
+{
+    FILE *f = std::fopen(path, "r");
+    if (f == nullptr)
+        return RTRI_ERR_INVALID;
+    std::string text;
+    char buf[4096];
+    size_t k;
+    while ((k = std::fread(buf, 1, sizeof buf, f)) > 0)
+        text.append(buf, k);
+    std::fclose(f);
+    TuneDB *db = new (std::nothrow) TuneDB();
+    if (db == nullptr)
+        return RTRI_ERR_NOMEM;
+    if (!parse_db(text, *db)) {
+        delete db;
+        return RTRI_ERR_INVALID;
+    }
+    delete h->tune;
+    h->tune = db;
+    return RTRI_OK;
+}
+
+}  // namespace rtri
+
+namespace {
+
+// median of `reps` event-timed runs of f, each after prep (untimed)
+template <class Prep, class F>
+float time_median(hipStream_t st, int reps, Prep &&prep, F &&f)
+{
+    std::vector<float> t;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    for (int r = 0; r <= reps; ++r) {
+        prep();
+        (void)hipEventRecord(a, st);
+        f();
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (r > 0)   // the first run is a warm-up
+            t.push_back(ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+}  // namespace
+
+extern "C" {
+
+int rtri_load_tuning(rtri_handle *h, const char *path)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    if (path == nullptr)
+        return -2;
+    return load_tuning_file(h, path);
+}
+
+int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    if (dtype != RTRI_F64 && dtype != RTRI_F32)
+        return -2;
+    if (max_order < 256)
+        return -3;
+    const size_t es = dtype == RTRI_F64 ? 8 : 4;
+    const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
+    const int64_t max_n = std::min<int64_t>(max_order, 4096);
+    void *A = nullptr, *B = nullptr, *C = nullptr;
+    hipError_t e = hipMalloc(&A, (size_t)max_order * max_order * es);
+    if (e == hipSuccess)
+        e = hipMalloc(&B, (size_t)max_order * max_n * es);
+    if (e == hipSuccess)
+        e = hipMalloc(&C, (size_t)max_order * max_n * es);
+    if (e != hipSuccess) {
+        (void)hipFree(A);
+        (void)hipFree(B);
+        (void)hipFree(C);
+        return hip_fail(h, e);
+    }
+    const int saved_f64 = h->leaf_f64, saved_f32 = h->leaf_f32, saved_tile = h->gemm_tile;
+    TuneDB *old = h->tune;
+    h->tune = nullptr;
+    TuneDB db;
+    if (old != nullptr)   // keep the other dtype's rules
+        for (const auto &r : old->leaf)
+            if (r.dtype != dtype)
+                db.leaf.push_back(r);
+    if (old != nullptr)
+        for (const auto &r : old->tile)
+            if (r.dtype != dtype)
+                db.tile.push_back(r);
+    int rc = RTRI_OK;
+    // leaf size per (op, order, vector count)
+    for (int64_t ka = 256; ka <= max_order && rc == RTRI_OK; ka *= 2) {
+        rc = rtri_synth_fill(h, dtype, 1, 77, 5, (uint64_t)ka, ka, ka, (double)ka, A, max_order);
+        for (int64_t n : {64, 512, 4096}) {
+            if (n > max_n || rc != RTRI_OK)
+                continue;
+            for (int solve = 1; solve >= 0; --solve) {
+                int best = 64;
+                float best_ms = 1e30f;
+                for (int leaf : {16, 32, 64}) {
+                    (dtype == RTRI_F64 ? h->leaf_f64 : h->leaf_f32) = leaf;
+                    int rr = RTRI_OK;
+                    const float ms = time_median(
+                        h->stream, 3,
+                        [&] {
+                            if (rr == RTRI_OK)
+                                rr = rtri_synth_fill(h, dtype, 0, 77, 6, 1, ka, n, 0.0, B, max_order);
+                        },
+                        [&] {
+                            if (rr != RTRI_OK)
+                                return;
+                            if (dtype == RTRI_F64)
+                                rr = solve ? rtri_dtrsm(h, 0, 0, 0, 0, ka, n, 1.0, (const double *)A, max_order,
+                                                        (double *)B, max_order)
+                                           : rtri_dtrmm(h, 0, 0, 0, 0, ka, n, 1.0, (const double *)A, max_order,
+                                                        (double *)B, max_order);
+                            else
+                                rr = solve ? rtri_strsm(h, 0, 0, 0, 0, ka, n, 1.0f, (const float *)A, max_order,
+                                                        (float *)B, max_order)
+                                           : rtri_strmm(h, 0, 0, 0, 0, ka, n, 1.0f, (const float *)A, max_order,
+                                                        (float *)B, max_order);
+                        });
+                    if (rr != RTRI_OK) {
+                        rc = rr;
+                        break;
+                    }
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = leaf;
+                    }
+                }
+                db.leaf.push_back(TuneDB::Leaf{dtype, solve, ka, n, best});
+            }
+        }
+    }
+    (dtype == RTRI_F64 ? h->leaf_f64 : h->leaf_f32) = dtype == RTRI_F64 ? saved_f64 : saved_f32;
+    // GEMM tile per (M = K, N)
+    for (int64_t mk = 64; mk <= std::min<int64_t>(max_order / 2, 8192) && rc == RTRI_OK; mk *= 2) {
+        for (int64_t n : {64, 512, 4096}) {
+            if (n > max_n)
+                continue;
+            int best = 1;
+            float best_ms = 1e30f;
+            for (int tile : {1, 2}) {
+                h->gemm_tile = tile;
+                int rr = RTRI_OK;
+                const float ms = time_median(
+                    h->stream, 3, [] {},
+                    [&] {
+                        rr = rtri_gemm_update(h, dtype, 0, 0, mk, n, mk, -1.0, A, max_order, B, max_order, 1.0, C,
+                                              max_order);
+                    });
+                if (rr != RTRI_OK) {
+                    rc = rr;
+                    break;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = tile;
+                }
+            }
+            db.tile.push_back(TuneDB::Tile{dtype, mk, n, best});
+        }
+    }
+    h->gemm_tile = saved_tile;
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(A);
+    (void)hipFree(B);
+    (void)hipFree(C);
+    delete old;
+    if (rc != RTRI_OK)
+        return rc;
+    h->tune = new (std::nothrow) TuneDB(db);
+    if (h->tune == nullptr)
+        return RTRI_ERR_NOMEM;
+    if (db_path != nullptr && !write_db(db_path, db))
+        return RTRI_ERR_INVALID;
+    return RTRI_OK;
+}
+
+}  // extern "C"

@@ -94,3 +94,16 @@ def test_status_strings(rt):
     assert rt.rtri_status_string(0) == b"success"
     assert rt.rtri_status_string(-9) == b"lda too small"
     assert rt.rtri_status_string(rt.ERR_HIP) == b"HIP runtime error"
+
+
+def test_tuning_db_load(rt, handle, tmp_path):
+    good = tmp_path / "t.json"
+    good.write_text('{"arch": "gfx950", "version": 1, "leaf": [{"dtype": "f64", "op": "trsm", "ka_max": 1024, '
+                    '"n_max": 512, "leaf": 32}], "gemm_tile": [{"dtype": "f32", "m_max": 256, "n_max": 4096, "tile": 2}]}')
+    assert rt.rtri_load_tuning(handle, str(good).encode()) == rt.OK
+    bad = tmp_path / "b.json"
+    bad.write_text('{"leaf": [{"dtype": "f64", "op": "trsm", "ka_max": 1024, "n_max": 512, "leaf": 48}]}')
+    assert rt.rtri_load_tuning(handle, str(bad).encode()) == rt.ERR_INVALID
+    assert rt.rtri_load_tuning(handle, str(tmp_path / "missing.json").encode()) == rt.ERR_INVALID
+    (tmp_path / "trunc.json").write_text('{"leaf": [')
+    assert rt.rtri_load_tuning(handle, str(tmp_path / "trunc.json").encode()) == rt.ERR_INVALID
