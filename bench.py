@@ -45,6 +45,10 @@ def parse():
     return ap.parse_args()
 
 
+def progress(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -70,6 +74,8 @@ def main():
     if args.leaf:
         h.set_option(rt.OPT_LEAF_F64, args.leaf)
 
+    progress("inputs resident", m, n)
+
     def step():
         rt.trsm(h, "L", "L", "N", "N", 1.0, Ad, Bd)
         rt.trmm(h, "L", "L", "N", "N", 1.0, Ad, Bd)
@@ -83,6 +89,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
+    progress("timed steps done", round(ms_step, 3), "ms/step")
     flops_step = 2.0 * m * m * n
     value = flops_step / (ms_step * 1e-3) / 1e12
 
@@ -153,12 +160,16 @@ def main():
     out["tuning_db"] = os.path.basename(tuning) if tuning else None
     if not args.no_cpu:
         out["cpu_baseline"], out["eta_sampled"] = cpu_baseline(rt, torch, h, A, B0, B0d, Ad, Bd, m, n)
+        progress("cpu baseline done")
     del Ad, Bd, B0d
     torch.cuda.empty_cache()
     if not args.no_extras:
         out["mixed"] = bench_mixed(rt, torch, h)
+        progress("mixed done")
         out["batched"] = bench_batched(rt, torch, h)
+        progress("batched done")
         out["serving"] = bench_serving(rt, args.serve_requests)
+        progress("serving done")
     print(json.dumps(out), flush=True)
 
 
@@ -176,29 +187,38 @@ def _event_ms(torch, fn, prep=None, reps=3):
     return min(ts)
 
 
+# diagonal offset c of the m = 8192 mixed-precision factor (diagonal c + U(0,1),
+# off-diagonal U(-1,1), device Philox fill, id 1) -> its 1-norm condition
+# number, computed on the host with LAPACK dtrtri on the bit-identical host twin
+MIXED_COND = ((450.0, 1.04e2), (45.0, 1.15e4), (17.0, 1.17e6))
+
+
 def bench_mixed(rt, torch, h, m=8192):
     """Mixed-precision refined TRSM against the plain FP64 TRSM on the same
     system: m = n = 8192, lower factor with off-diagonal U(-1,1) and diagonal
-    45 + U(0,1) (cond_1 ~ 1e4), dense right-hand sides U(-1,1); inputs drawn on
-    the device (Philox)."""
+    c + U(0,1) for three condition classes, dense right-hand sides U(-1,1);
+    inputs drawn on the device (Philox)."""
     import synth
     Ad = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
     B0 = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
-    rt.synth_fill(h, 1, synth.SEED, synth.W_MIXED, 1, Ad, param=45.0)
     rt.synth_fill(h, 0, synth.SEED, synth.W_MIXED, 2, B0)
     Bd = B0.clone()
-    res = {"workload": f"FP64-accurate TRSM L/L/N/N m=n={m}, diagonal 45+U(0,1) (cond_1 ~ 1e4), tol 1e-12"}
-    t_plain = _event_ms(torch, lambda: rt.trsm(h, "L", "L", "N", "N", 1.0, Ad, Bd), lambda: Bd.copy_(B0))
-    res["fp64_ms"] = round(t_plain, 3)
-    for gemm in ("bf16", "f32"):
-        info = {}
+    res = {"workload": f"FP64-accurate TRSM L/L/N/N m=n={m}, diagonal c+U(0,1), tol 1e-12", "cases": []}
+    for c, kappa in MIXED_COND:
+        rt.synth_fill(h, 1, synth.SEED, synth.W_MIXED, 1, Ad, param=c)
+        t_plain = _event_ms(torch, lambda: rt.trsm(h, "L", "L", "N", "N", 1.0, Ad, Bd), lambda: Bd.copy_(B0))
+        case = {"c": c, "cond1": kappa, "fp64_ms": round(t_plain, 3)}
+        for gemm in ("bf16", "f32"):
+            info = {}
 
-        def run():
-            info.update(rt.trsm_mixed(h, "L", "L", "N", "N", 1.0, Ad, Bd, gemm=gemm, tol=1e-12, max_iter=30))
-        t = _event_ms(torch, run, lambda: Bd.copy_(B0))
-        res[gemm] = {"ms": round(t, 3), "speedup_vs_fp64": round(t_plain / t, 3), "iters": info["iters"],
-                     "eta": info["eta"], "converged": info["converged"],
-                     "useful_tflops": round(m ** 3 / (t * 1e-3) / 1e12, 3)}
+            def run():
+                info.update(rt.trsm_mixed(h, "L", "L", "N", "N", 1.0, Ad, Bd, gemm=gemm, tol=1e-12, max_iter=30,
+                                          allow_not_converged=True))
+            t = _event_ms(torch, run, lambda: Bd.copy_(B0))
+            case[gemm] = {"ms": round(t, 3), "speedup_vs_fp64": round(t_plain / t, 3), "iters": info["iters"],
+                          "eta": info["eta"], "converged": info["converged"],
+                          "useful_tflops": round(m ** 3 / (t * 1e-3) / 1e12, 3)}
+        res["cases"].append(case)
     return res
 
 
@@ -309,11 +329,13 @@ def bench_serving(rt, count):
                 "factor_hits": st["factor_hits"], "factor_misses": st["factor_misses"],
                 "evictions": st["evictions"], "hbm_peak_GB": round(st["hbm_peak"] / 1e9, 2)}
     sat = run(None)
+    progress("serving saturation", sat["solves_per_s"], "solves/s")
     res["saturation"] = sat
     mu = sat["solves_per_s"]
     res["rates"] = {}
     for frac in (0.25, 0.5, 0.75, 0.9):
         res["rates"][str(frac)] = dict(run(frac * mu), rate_per_s=round(frac * mu, 1))
+        progress("serving rate", frac)
     return res
 
 

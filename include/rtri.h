@@ -70,8 +70,8 @@ enum {
 
 /* Tunable options (rtri_set_option / rtri_get_option). */
 enum {
-    RTRI_OPT_LEAF_F64 = 1,   /* leaf size for FP64 (16, 32 or 64; 0 = automatic) */
-    RTRI_OPT_LEAF_F32 = 2,   /* leaf size for FP32 (16, 32, 64 or 128; 0 = automatic) */
+    RTRI_OPT_LEAF_F64 = 1,   /* leaf size for FP64 (16, 32, 64, 128 or 256; 0 = automatic) */
+    RTRI_OPT_LEAF_F32 = 2,   /* leaf size for FP32 (16, 32, 64, 128 or 256; 0 = automatic) */
     RTRI_OPT_GEMM_TILE = 3   /* GEMM tile choice: 0 = automatic, 1 = 128x128, 2 = 64x64 */
 };
 

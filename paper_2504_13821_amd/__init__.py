@@ -159,7 +159,10 @@ _DIAG = {"N": NONUNIT, "U": UNIT}
 
 
 def codes(side: str, uplo: str, trans: str, diag: str):
-    return _SIDE[side.upper()], _UPLO[uplo.upper()], _TRANS[trans.upper()], _DIAG[diag.upper()]
+    """BLAS letters -> C ABI codes; an unknown letter maps to -1, which the
+    library rejects with the argument's error code."""
+    return (_SIDE.get(side.upper(), -1), _UPLO.get(uplo.upper(), -1), _TRANS.get(trans.upper(), -1),
+            _DIAG.get(diag.upper(), -1))
 
 
 class Handle:

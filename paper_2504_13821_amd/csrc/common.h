@@ -42,14 +42,14 @@ struct GemmDesc {
 // L(k+1,k) ...; ascending columns for a solve, descending for a multiply),
 // with L(i,k) = Mx(p(i), p(k)), p(i) = i (lower)
 // or nb-1-i (upper); rows past the block's end and a unit diagonal become the
-// identity.  Each packed block takes tri_elems(nbmax) = nbmax*(nbmax+1)/2 slots.
+// identity.  Each packed block takes pack_elems(nbmax) slots.
 // ---------------------------------------------------------------------------
 struct PackDesc {
     const void *A;      // A of the whole problem (element (0,0) of Mx)
     int64_t lda;
     int64_t ka;         // order of Mx
     bool mtrans, mlower, unit;
-    void *out;          // nblocks * tri_elems(nbmax) elements
+    void *out;          // nblocks * pack_elems(nbmax) elements
 };
 
 // Leaf kernel on one diagonal block against a panel of nvec independent
@@ -67,6 +67,10 @@ struct LeafDesc {
 };
 
 inline int64_t tri_elems(int nb) { return (int64_t)nb * (nb + 1) / 2; }
+// Leaves of 128 and 256 rows read a tiled packed form instead (see mleaf.hip):
+// the 16 x 16 tiles of the lower triangle, column block by column block.
+inline int64_t bpack_elems(int nbmax) { return (int64_t)128 * (nbmax / 16) * (nbmax / 16 + 1); }
+inline int64_t pack_elems(int nbmax) { return nbmax <= 64 ? tri_elems(nbmax) : bpack_elems(nbmax); }
 
 enum class DType { F64, F32 };
 // element types of matrices in memory
@@ -79,6 +83,9 @@ hipError_t launch_gemm16(bool bf16, bool p16, const GemmDesc &g, hipStream_t st)
 // pack diagonal blocks read from A of type src into packed triangles of type dst
 hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);
+// matrix-core leaves (nbmax = 128 or 256, mleaf.hip), called by launch_pack / launch_leaf
+hipError_t launch_bpack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
+hipError_t launch_bleaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);
 hipError_t launch_fill(DType t, void *B, int64_t m, int64_t n, int64_t ldb, double value, hipStream_t st);
 
 // ---- element-wise kernels (HBM-bound) ----

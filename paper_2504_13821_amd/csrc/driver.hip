@@ -69,7 +69,7 @@ struct Planner {
         op.gemm = false;
         LeafDesc &l = op.l;
         // offset of this block inside the packed workspace; rebased at launch
-        l.Lp = reinterpret_cast<const void *>((intptr_t)((d0 / p.leaf) * tri_elems(p.leaf) * (int64_t)es));
+        l.Lp = reinterpret_cast<const void *>((intptr_t)((d0 / p.leaf) * pack_elems(p.leaf) * (int64_t)es));
         l.nb = (int)h;
         l.unit = p.diag == RTRI_UNIT;
         l.alpha = alpha;
@@ -247,6 +247,8 @@ int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, co
     return 0;
 }
 
+bool valid_leaf(int64_t v) { return v == 0 || v == 16 || v == 32 || v == 64 || v == 128 || v == 256; }
+
 int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nvec)
 {
     int leaf = t == DType::F64 ? h->leaf_f64 : h->leaf_f32;
@@ -269,7 +271,7 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     // pack every diagonal block once into the canonical form the leaves read
     const int64_t nblk = (ka + p.leaf - 1) / p.leaf;
     if (!p.skip_pack) {
-        hipError_t e0 = ensure_ws(h, p.pack_slot, (size_t)(nblk * tri_elems(p.leaf)) * es);
+        hipError_t e0 = ensure_ws(h, p.pack_slot, (size_t)(nblk * pack_elems(p.leaf)) * es);
         if (e0 != hipSuccess)
             return hip_fail(h, e0);
         PackDesc pk{};
@@ -286,7 +288,7 @@ int run_plan(rtri_handle *h, const PlanIn &p)
         }
         pk.out = h->ws[p.pack_slot];
         e0 = timed(h, RTRI_KCLASS_OTHER, dtype_code(p.st), 0.0,
-                   (double)elem_size(p.st) * ka * (double)p.leaf + (double)es * nblk * tri_elems(p.leaf),
+                   (double)elem_size(p.st) * ka * (double)p.leaf + (double)es * nblk * pack_elems(p.leaf),
                    [&] { return launch_pack(p.st, bt, p.solve, p.leaf, pk, h->stream); });
         if (e0 != hipSuccess)
             return hip_fail(h, e0);
@@ -438,11 +440,11 @@ int rtri_set_option(rtri_handle *h, int option, int64_t value)
         return RTRI_ERR_HANDLE;
     switch (option) {
     case RTRI_OPT_LEAF_F64:
-        if (value != 0 && value != 16 && value != 32 && value != 64) return -3;
+        if (!valid_leaf(value)) return -3;
         h->leaf_f64 = (int)value;
         return RTRI_OK;
     case RTRI_OPT_LEAF_F32:
-        if (value != 0 && value != 16 && value != 32 && value != 64) return -3;
+        if (!valid_leaf(value)) return -3;
         h->leaf_f32 = (int)value;
         return RTRI_OK;
     case RTRI_OPT_GEMM_TILE:

@@ -80,6 +80,7 @@ bool handle_valid(const rtri_handle *h);
 int hip_fail(rtri_handle *h, hipError_t e);
 hipError_t ensure_ws(rtri_handle *h, int slot, size_t bytes);
 // leaf size: the handle's option, else the tuning database, else 64
+bool valid_leaf(int64_t v);   // 0 (automatic), 16, 32, 64, 128 or 256
 int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nvec);
 int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, const void *A, int64_t lda,
                const void *B, int64_t ldb, bool need_a);

@@ -110,6 +110,8 @@ hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDe
 {
     if (p.ka <= 0)
         return hipSuccess;
+    if (nbmax > 64)
+        return launch_bpack(src, dst, solve, nbmax, p, st);
     if (dst == DType::F64) {
         if (src != ElemT::F64)
             return hipErrorInvalidValue;
@@ -130,6 +132,8 @@ hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStr
         return hipSuccess;
     if (l.nb > nbmax)
         return hipErrorInvalidValue;
+    if (nbmax > 64)
+        return launch_bleaf(t, solve, nbmax, l, st);
     if (t == DType::F64) {
         switch (nbmax) {
         case 16: return launch_nb<double, 16>(solve, l, st);

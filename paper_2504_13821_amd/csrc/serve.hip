@@ -143,6 +143,7 @@ void complete_now(rtri_server *s, const Req &q, int status)
     s->st.completed += 1;
     s->st.failed += 1;
     s->outstanding -= 1;
+    s->cv.notify_all();   // drain() may be waiting for the last outstanding request
 }
 
 // Reserve what request q needs for slot `slot`; creates (and starts generating)

@@ -168,7 +168,7 @@ bool parse_db(const std::string &text, TuneDB &db)
             TuneDB::Leaf r{dtype_of(str_of(e, "dtype", ok)), str_of(e, "op", ok) == "trsm" ? 1 : 0,
                            (int64_t)num_of(e, "ka_max", ok), (int64_t)num_of(e, "n_max", ok),
                            (int)num_of(e, "leaf", ok)};
-            if (r.dtype < 0 || (r.leaf != 16 && r.leaf != 32 && r.leaf != 64))
+            if (r.dtype < 0 || r.leaf == 0 || !valid_leaf(r.leaf))
                 ok = false;
             db.leaf.push_back(r);
         }
@@ -335,7 +335,7 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
         return -3;
     const size_t es = dtype == RTRI_F64 ? 8 : 4;
     const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
-    const int64_t max_n = std::min<int64_t>(max_order, 4096);
+    const int64_t max_n = std::min<int64_t>(max_order, 16384);
     void *A = nullptr, *B = nullptr, *C = nullptr;
     hipError_t e = hipMalloc(&A, (size_t)max_order * max_order * es);
     if (e == hipSuccess)
@@ -364,13 +364,13 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
     // leaf size per (op, order, vector count)
     for (int64_t ka = 256; ka <= max_order && rc == RTRI_OK; ka *= 2) {
         rc = rtri_synth_fill(h, dtype, 1, 77, 5, (uint64_t)ka, ka, ka, (double)ka, A, max_order);
-        for (int64_t n : {64, 512, 4096}) {
+        for (int64_t n : {64, 512, 4096, 16384}) {
             if (n > max_n || rc != RTRI_OK)
                 continue;
             for (int solve = 1; solve >= 0; --solve) {
                 int best = 64;
                 float best_ms = 1e30f;
-                for (int leaf : {16, 32, 64}) {
+                for (int leaf : {16, 32, 64, 128, 256}) {
                     (dtype == RTRI_F64 ? h->leaf_f64 : h->leaf_f32) = leaf;
                     int rr = RTRI_OK;
                     const float ms = time_median(

@@ -87,6 +87,9 @@ def test_options(rt, handle):
     assert rt.rtri_set_option(handle, rt.OPT_LEAF_F64, 32) == rt.OK
     assert rt.rtri_get_option(handle, rt.OPT_LEAF_F64, ctypes.byref(v)) == rt.OK and v.value == 32
     assert rt.rtri_set_option(handle, rt.OPT_LEAF_F64, 48) == -3
+    for leaf in (16, 64, 128, 256, 0):
+        assert rt.rtri_set_option(handle, rt.OPT_LEAF_F32, leaf) == rt.OK
+    assert rt.rtri_set_option(handle, rt.OPT_LEAF_F32, 512) == -3
     assert rt.rtri_set_option(handle, 999, 1) == -2
 
 

@@ -121,10 +121,65 @@ def test_exact_bitwise(rt, h, orc, dt, op, diag, side, uplo, trans):
     assert np.array_equal(X, Xo)
 
 
+# ---- blocked leaves (128 / 256 rows: several wavefronts per panel) ---------------
+
+@pytest.mark.parametrize("leaf", [128, 256])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("op", ["trsm", "trmm"])
+@pytest.mark.parametrize("diag", "NU")
+@pytest.mark.parametrize("side,uplo,trans", [v for v in VARIANTS if v[2] != "C"])
+def test_blocked_leaf_variants(rt, h, orc, leaf, dt, op, diag, side, uplo, trans):
+    """Orders 600 (full blocks plus a ragged one of 88 rows) against 130
+    vectors (a ragged last workgroup of 2 vectors)."""
+    m, n = (600, 130) if side == "L" else (130, 600)
+    say("bleaf", leaf, op, dt, side, uplo, trans, diag, m, n)
+    A, B = _inputs(side, uplo, diag, m, n, dt, G(12, m))
+    h.set_option(rt.OPT_LEAF_F64 if dt == "f64" else rt.OPT_LEAF_F32, leaf)
+    X = run_op(rt, h, op, side, uplo, trans, diag, -1.5, A, B, dt)
+    e = eta(orc, op, side, uplo, trans, diag, -1.5, A, B, X)
+    assert e <= TOL[dt], (leaf, op, dt, side, uplo, trans, diag, e)
+
+
+@pytest.mark.parametrize("leaf", [128, 256])
+@pytest.mark.parametrize("op", ["trsm", "trmm"])
+@pytest.mark.parametrize("side,uplo,trans", [("L", "L", "N"), ("L", "U", "T"), ("R", "U", "N"), ("R", "L", "T")])
+def test_blocked_leaf_exact(rt, h, orc, leaf, op, side, uplo, trans):
+    """One partial block with exact small integers (power-of-two diagonal, so
+    the reciprocal is exact): bit for bit with the oracle."""
+    ka = 44 if op == "trsm" else 60
+    m, n = (ka, 70) if side == "L" else (70, ka)
+    say("bleaf exact", leaf, op, side, uplo, trans)
+    g = G(13, ka)
+    if op == "trsm":
+        A = synth.exact_tri(ka, uplo, g, offdiag=(-1, 0, 1), diag=(1.0, -1.0))
+    else:
+        A = synth.exact_tri(ka, uplo, g, offdiag=(-2, -1, 0, 1, 2), diag=(1.0, -1.0, 2.0, -2.0))
+    B = synth.exact_dense(m, n, g)
+    h.set_option(rt.OPT_LEAF_F64, leaf)
+    X = run_op(rt, h, op, side, uplo, trans, "N", 2.0, A, B, "f64")
+    assert np.array_equal(X, oracle_op(orc, op, side, uplo, trans, "N", 2.0, A, B))
+
+
+@pytest.mark.parametrize("op", ["trsm", "trmm"])
+def test_blocked_leaf_exact_full_blocks(rt, h, orc, op):
+    """Exact integers over two full 128-row blocks and a ragged one: unit
+    diagonal with off-diagonal entries in {-1, 0, 1} scaled so every
+    intermediate stays an exact integer."""
+    ka, n = 300, 65
+    say("bleaf exact full", op)
+    g = G(14, ka)
+    A = synth.exact_tri(ka, "L", g, offdiag=(0.0, 0.0, 0.0, 1.0), diag=(1.0,))
+    A[np.tril_indices(ka, -2)] = 0.0          # bidiagonal: solutions stay small integers
+    B = synth.exact_dense(ka, n, g, bound=3)
+    h.set_option(rt.OPT_LEAF_F64, 128)
+    X = run_op(rt, h, op, "L", "L", "N", "N", 1.0, A, B, "f64")
+    assert np.array_equal(X, oracle_op(orc, op, "L", "L", "N", "N", 1.0, A, B))
+
+
 # ---- leaf sizes, padding, alpha, sentinels, determinism --------------------------
 
-@pytest.mark.parametrize("dt,leaf", [("f64", 16), ("f64", 32), ("f64", 64), ("f32", 16), ("f32", 32),
-                                     ("f32", 64)])
+@pytest.mark.parametrize("dt,leaf", [("f64", 16), ("f64", 32), ("f64", 64), ("f64", 128), ("f64", 256),
+                                     ("f32", 16), ("f32", 32), ("f32", 64), ("f32", 128), ("f32", 256)])
 @pytest.mark.parametrize("op", ["trsm", "trmm"])
 def test_leaf_sizes(rt, h, orc, dt, leaf, op):
     m, n = 333, 130

@@ -119,10 +119,11 @@ def test_serving_alone_vs_mix(rt, h, orc):
 
 
 def test_serving_small_budget(rt, h):
-    """A 48 MB budget: factors (up to 8 MB each) are evicted and requests wait
-    for memory; every result is still the alone result."""
+    """A 48 MB budget against about 150 MB of distinct factors (up to 19 MB
+    each): factors are evicted and requests wait for memory; every result is
+    still the alone result."""
     g = synth.rng(synth.W_SERVE, 2)
-    reqs = _stream(150, g, m_hi=1024, n_hi=64, mixed_frac=0.0, n_factors=40)
+    reqs = _stream(150, g, m_hi=1536, n_hi=64, mixed_frac=0.0, n_factors=60)
     say("serving budget", len(reqs))
     results, comps, stats = _run_stream(rt, reqs, rate=2000.0, slots=3, hbm_budget=48 << 20, max_batch=16,
                                         small_max=512)
@@ -133,6 +134,7 @@ def test_serving_small_budget(rt, h):
         assert np.array_equal(res, _alone(rt, h, r)), r
 
 
+@pytest.mark.timeout(60)
 def test_serving_rejects(rt):
     srv = rt.Server(slots=1)
     with pytest.raises(rt.RtriError):
