@@ -30,6 +30,21 @@ sys.path.insert(0, ROOT)
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}   # MI355X dense MFMA, TFLOP/s
 HBM_PEAK = 8000.0                                                    # GB/s
 
+# HBM-side bytes per FP64 GEMM-update launch of this step, from two rocprofv3
+# PMC passes (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 2 GiB copy in the
+# same process; profiles/gemm_f64_16384_traffic.txt).  Valid only for the GEMM
+# sources they were taken on: reported as null once those change.
+GEMM_TRAFFIC = {"bytes_per_launch": 1.9018e9, "sources_sha256_16": "a186cf737dac46ba"}
+
+
+def gemm_sources_digest():
+    import hashlib
+    d = hashlib.sha256()
+    for f in ("gemm.hip", "gemm_core.h"):
+        with open(os.path.join(ROOT, "paper_2504_13821_amd", "csrc", f), "rb") as fh:
+            d.update(fh.read())
+    return d.hexdigest()[:16]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -116,6 +131,7 @@ def main():
     by = {(s["kclass"], s["dtype"]): s for s in stats}
     gem = by[("gemm", "f64")]
     gemm_avg_ms = gem["ms"] / gem["launches"]
+    traffic = GEMM_TRAFFIC["bytes_per_launch"] if gemm_sources_digest() == GEMM_TRAFFIC["sources_sha256_16"] else None
     achieved = gem["flops"] / (gem["ms"] * 1e-3) / 1e12
     prof_total_ms = sum(s["ms"] for s in stats) / args.steps
     kernels = {f"{s['kclass']}_{s['dtype']}": {"launches_per_step": s["launches"] / args.steps,
@@ -138,7 +154,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"FP64 TRSM + TRMM, side=L uplo=L trans=N diag=N, m=n={m}, alpha=1, "
                                "A: off-diagonal U(-1,1), diagonal m+U(0,1); B: U(-1,1)",
-                   "m": m, "n": n, "leaf": h.get_option(rt.OPT_LEAF_F64) or 64},
+                   "m": m, "n": n, "leaf": {"trsm": h.leaf("f64", "trsm", m, n), "trmm": h.leaf("f64", "trmm", m, n)}},
         "trsm_ms": round(t_trsm, 3), "trsm_tflops": round(m * m * n / (t_trsm * 1e-3) / 1e12, 3),
         "trmm_ms": round(t_trmm, 3), "trmm_tflops": round(m * m * n / (t_trmm * 1e-3) / 1e12, 3),
         "fraction_of_fp64_peak": round(value / PEAK["f64"], 4),
@@ -149,7 +165,10 @@ def main():
             "peak": PEAK["f64"],
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK["f64"], 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch (HBM side, PMC)",
+            "algorithmic_bytes_per_launch": round(gem["bytes"] / gem["launches"]),
+            "algorithmic_flops_per_launch": round(gem["flops"] / gem["launches"]),
             "avg_launch_ms": round(gemm_avg_ms, 5),
             "launches_per_step": gem["launches"] / args.steps,
         },
@@ -313,8 +332,10 @@ def bench_serving(rt, count):
             arr = np.full(count, t0)
         else:
             arr = t0 + np.cumsum(synth.rng(synth.W_SERVE, 2000, int(rate)).exponential(1.0 / rate, count))
+        ticket0 = None
         for r, ta in zip(reqs, arr):
-            srv.submit(t_arrival=float(ta), **r)
+            tk = srv.submit(t_arrival=float(ta), **r)
+            ticket0 = tk if ticket0 is None else ticket0
         srv.drain()
         comps = srv.poll(count + 16)
         st = srv.stats()
@@ -322,10 +343,22 @@ def bench_serving(rt, count):
         lat = np.array([c["t_done"] - c["t_arrival"] for c in comps])
         span = max(c["t_done"] for c in comps) - t0
         bad = sum(1 for c in comps if c["status"] not in (0,))
+        by_status = {}
+        failed = []
+        for c in comps:
+            if c["status"] != 0:
+                by_status[str(c["status"])] = by_status.get(str(c["status"]), 0) + 1
+                r = reqs[c["ticket"] - ticket0]
+                if len(failed) < 8:
+                    failed.append({"status": c["status"], "op": r["op"], "m": r["m"], "n": r["n"],
+                                   "precision": r["precision"], "trans": r["trans"], "uplo": r["uplo"],
+                                   "iters": c["iters"], "eta": c["eta"], "factor_id": r["factor_id"]})
         return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
                 "solves_per_s": round(count / span, 1), "busy_tflops": round(flops / span / 1e12, 3),
-                "errors": bad, "batched_requests": st["batched_requests"], "launches": st["launches"],
+                "errors": bad, "errors_by_status": by_status, "failed_sample": failed,
+                "batched_requests": st["batched_requests"],
+                "launches": st["launches"],
                 "factor_hits": st["factor_hits"], "factor_misses": st["factor_misses"],
                 "evictions": st["evictions"], "hbm_peak_GB": round(st["hbm_peak"] / 1e9, 2)}
     sat = run(None)

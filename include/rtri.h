@@ -213,10 +213,11 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
 int rtri_synth_fill(rtri_handle *h, int dtype, int kind, uint64_t seed, uint32_t stream, uint64_t id, int64_t m,
                     int64_t n, double param, void *X, int64_t ldx);
 
-/* Tuning: time leaf sizes (16 / 32 / 64) for TRSM and TRMM at factor orders
- * 256, 512, ... up to max_order and 64 / 512 / 4096 vectors, and the GEMM tile
- * (128x128 or 64x64) at M = K = 64 ... min(max_order / 2, 8192) and the same
- * vector counts, on synthetic inputs in device memory the call allocates and
+/* Tuning: time leaf sizes (16 / 32 / 64 / 128 / 256) for TRSM and TRMM at
+ * factor orders 256, 512, ... up to max_order and 64 / 512 / 4096 / 16384
+ * vectors (at most max_order), and the GEMM tile (128x128 or 64x64) at M = K =
+ * 64 ... min(max_order / 2, 8192) and the same vector counts, on synthetic
+ * inputs in device memory the call allocates and
  * frees; keep the winners in the handle (rules for the other dtype are kept)
  * and, if db_path != NULL, write them there as JSON.  Blocking.  Options set
  * with rtri_set_option still take precedence.  Codes: -2 dtype, -3 max_order
@@ -228,6 +229,13 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
  * names such a file loads it automatically.  RTRI_ERR_INVALID if the file is
  * missing or malformed. */
 int rtri_load_tuning(rtri_handle *h, const char *path);
+
+/* The leaf size the handle would use for a TRSM (op = 0) or TRMM (op = 1) of
+ * dtype RTRI_F64 / RTRI_F32 with a factor of order `order` against `nvec`
+ * vectors: the option if set, else the loaded tuning rules, else 64 for
+ * orders up to 1024 and 256 above.  Codes: -2 dtype, -3 op, -4 order or nvec
+ * negative, -6 leaf NULL. */
+int rtri_query_leaf(rtri_handle *h, int dtype, int op, int64_t order, int64_t nvec, int *leaf);
 
 /* ---- batched independent problems (one persistent launch) ----------------- */
 

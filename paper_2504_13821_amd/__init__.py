@@ -123,6 +123,7 @@ rtri_server_now = _sig("rtri_server_now", ctypes.c_double, _vp)
 rtri_server_destroy = _sig("rtri_server_destroy", _int, _vp)
 rtri_tune = _sig("rtri_tune", _int, _vp, _int, _i64, ctypes.c_char_p)
 rtri_load_tuning = _sig("rtri_load_tuning", _int, _vp, ctypes.c_char_p)
+rtri_query_leaf = _sig("rtri_query_leaf", _int, _vp, _int, _int, _i64, _i64, ctypes.POINTER(_int))
 TUNING_DB = os.path.join(_HERE, "tuning", "gfx950.json")
 rtri_gemm_update = _sig("rtri_gemm_update", _int, _vp, _int, _int, _int, _i64, _i64, _i64, ctypes.c_double, _vp,
                         _i64, _vp, _i64, ctypes.c_double, _vp, _i64)
@@ -199,6 +200,13 @@ class Handle:
 
     def load_tuning(self, path=TUNING_DB):
         check(rtri_load_tuning(self._h, path.encode()), "rtri_load_tuning")
+
+    def leaf(self, dtype="f64", op="trsm", order=1, nvec=1) -> int:
+        """The leaf size this handle would use for such a problem."""
+        v = _int()
+        check(rtri_query_leaf(self._h, {"f64": F64, "f32": F32}[dtype], {"trsm": 0, "trmm": 1}[op], order, nvec,
+                              ctypes.byref(v)), "rtri_query_leaf")
+        return v.value
 
     def profile_begin(self):
         check(rtri_profile_begin(self._h), "rtri_profile_begin")

@@ -254,7 +254,11 @@ int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nve
     int leaf = t == DType::F64 ? h->leaf_f64 : h->leaf_f32;
     if (leaf == 0)
         leaf = tuned_leaf(h->tune, t == DType::F64 ? RTRI_F64 : RTRI_F32, solve, ka, nvec);
-    return leaf == 0 ? 64 : leaf;
+    if (leaf != 0)
+        return leaf;
+    // untuned: the 64-row leaf (also the batched kernel's) for small factors,
+    // the matrix-core 256-row leaf above
+    return ka <= 1024 ? 64 : 256;
 }
 
 int run_plan(rtri_handle *h, const PlanIn &p)
@@ -370,6 +374,22 @@ int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int 
 }  // namespace
 
 extern "C" {
+
+int rtri_query_leaf(rtri_handle *h, int dtype, int op, int64_t order, int64_t nvec, int *leaf)
+{
+    if (!handle_valid(h))
+        return RTRI_ERR_HANDLE;
+    if (dtype != RTRI_F64 && dtype != RTRI_F32)
+        return -2;
+    if (op != 0 && op != 1)
+        return -3;
+    if (order < 0 || nvec < 0)
+        return -4;
+    if (leaf == nullptr)
+        return -6;
+    *leaf = pick_leaf(h, dtype == RTRI_F64 ? DType::F64 : DType::F32, op == 0, order, nvec);
+    return RTRI_OK;
+}
 
 int rtri_create(rtri_handle **out, void *stream)
 {

@@ -58,7 +58,8 @@ struct Factor {
 struct Work {
     std::vector<Req> reqs;
     bool batched = false;
-    size_t ws_extra = 0;
+    size_t ws_extra = 0;      // device memory reserved for the slot's workspace growth
+    size_t tables = 0;        // upper bound of the batch tables (batched work)
 };
 
 }  // namespace
@@ -99,14 +100,54 @@ size_t handle_ws_bytes(const rtri_handle *h)
     return b;
 }
 
-// workspace a request needs in its slot's handle (upper estimate)
-size_t ws_estimate(const rtri_request &r, int64_t ka)
+constexpr size_t WS_MIN = (size_t)1 << 16;   // smallest workspace block a handle allocates
+
+// upper bound of the workspace any handle may need for request r, whatever
+// its leaf size (the largest packed form is the 256-row one)
+size_t ws_bound(const rtri_request &r, int64_t ka)
 {
     const size_t mn = (size_t)r.m * (size_t)r.n;
-    const size_t pack = (size_t)((ka + 63) / 64) * 2080 * 8;
+    const size_t pack = (size_t)((ka + 255) / 256 + 1) * (size_t)pack_elems(256) + (size_t)ka * 136;
     if (r.precision == RTRI_PREC_F64)
-        return 2 * pack;
-    return (size_t)ka * ka * 4 + mn * (4 + 8 * 4) + 4 * pack + 64;
+        return 8 * pack + WS_MIN;
+    return (size_t)ka * ka * 4 + mn * (4 + 8 * 4) + 12 * pack + 9 * WS_MIN;
+}
+
+// device memory the slot's handle allocates to run q alone: for every
+// workspace slot the request uses, what ensure_ws() would add
+size_t alone_growth(const rtri_handle *h, const Req &q)
+{
+    const rtri_request &r = q.r;
+    const int64_t nvec = r.side == RTRI_LEFT ? r.n : r.m;
+    size_t need[WS_COUNT] = {};
+    auto pack_bytes = [&](DType t, bool solve) {
+        const int leaf = pick_leaf(h, t, solve, q.ka, nvec);
+        return (size_t)((q.ka + leaf - 1) / leaf) * (size_t)pack_elems(leaf) * (t == DType::F64 ? 8 : 4);
+    };
+    if (r.precision == RTRI_PREC_F64) {
+        need[WS_PACK] = pack_bytes(DType::F64, r.op == 0);
+    } else {
+        const size_t mn = (size_t)r.m * (size_t)r.n;
+        need[WS_ACOPY] = (size_t)q.ka * q.ka * (r.precision == RTRI_PREC_MIXED_BF16 ? 2 : 4);
+        need[WS_PANEL32] = mn * 4;
+        need[WS_X] = need[WS_R0] = need[WS_R] = need[WS_W] = mn * 8;
+        need[WS_SCALARS] = 64;
+        need[WS_PACK2] = pack_bytes(DType::F32, true);
+        need[WS_PACK] = pack_bytes(DType::F64, false);
+    }
+    size_t g = 0;
+    for (int i = 0; i < WS_COUNT; ++i)
+        if (need[i] > h->ws_bytes[i])
+            g += std::max(need[i], WS_MIN) - h->ws_bytes[i];
+    return g;
+}
+
+// upper bound of one request's share of the batch tables (instance record,
+// 64-vector work items, op list)
+size_t batch_entry_bound(const Req &q)
+{
+    const int64_t nvec = q.r.side == RTRI_LEFT ? q.r.n : q.r.m;
+    return 256 + 16 * (size_t)((nvec + 63) / 64) + 64 * (size_t)((q.ka + 31) / 32 + 2);
 }
 
 bool evict_one(rtri_server *s, hipStream_t st)
@@ -148,14 +189,21 @@ void complete_now(rtri_server *s, const Req &q, int status)
 
 // Reserve what request q needs for slot `slot`; creates (and starts generating)
 // a missing synthetic factor.  Returns false if it does not fit right now.
-bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w)
+bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool batched)
 {
     auto it = s->factors.find(q.r.factor_id);
     const bool have = it != s->factors.end();
     const size_t fbytes = have ? 0 : (size_t)q.ka * q.ka * 8;
-    size_t ws_extra = 0;
-    if (q.ws_bytes > slot.ws_held + w.ws_extra)
-        ws_extra = q.ws_bytes - (slot.ws_held + w.ws_extra);
+    // workspace growth: exact for the handle, bounded for the batch tables
+    // (the batched launch grows its scratch to twice the tables' size)
+    size_t ws_extra = 0, tables = w.tables;
+    if (batched) {
+        tables += batch_entry_bound(q) + (w.reqs.empty() ? 1024 : 0);
+        const size_t grow = 2 * tables > slot.sc.dev_bytes ? 2 * tables - slot.sc.dev_bytes : 0;
+        ws_extra = grow > w.ws_extra ? grow - w.ws_extra : 0;
+    } else {
+        ws_extra = alone_growth(slot.h, q);
+    }
     const int64_t need = (int64_t)(fbytes + q.rhs_bytes + ws_extra);
     while (s->used + need > s->cfg.hbm_budget)
         if (!evict_one(s, slot.stream))
@@ -191,6 +239,7 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w)
     f->last_use = ++s->use_clock;
     s->used += (int64_t)(q.rhs_bytes + ws_extra);
     w.ws_extra += ws_extra;
+    w.tables = tables;
     s->st.hbm_in_use = s->used;
     s->st.hbm_peak = std::max(s->st.hbm_peak, s->used);
     w.reqs.push_back(q);
@@ -225,7 +274,7 @@ void take_work(rtri_server *s, rtri_server::Slot &slot, Work &w)
     if (s->pending.empty() || s->pending.front().r.t_arrival > t)
         return;
     const Req head = s->pending.front();
-    if (!admit(s, slot, head, w))
+    if (!admit(s, slot, head, w, head.small))
         return;
     s->pending.pop_front();
     if (!head.small)
@@ -236,7 +285,7 @@ void take_work(rtri_server *s, rtri_server::Slot &slot, Work &w)
         const Req &q = s->pending.front();
         if (q.r.t_arrival > t || !q.small || !consistent(s, q))
             break;
-        if (!admit(s, slot, q, w))
+        if (!admit(s, slot, q, w, true))
             break;
         s->pending.pop_front();
     }
@@ -359,8 +408,8 @@ void worker(rtri_server *s, int idx)
                 else
                     s->st.failed += 1;
             }
-            // the slot's handle keeps its largest workspace: count what it holds now
-            const size_t held = handle_ws_bytes(slot.h);
+            // the slot keeps its largest workspace and batch scratch: count what it holds now
+            const size_t held = handle_ws_bytes(slot.h) + slot.sc.dev_bytes;
             s->used += (int64_t)held - (int64_t)(slot.ws_held + w.ws_extra);
             slot.ws_held = held;
             s->st.completed += (int64_t)w.reqs.size();
@@ -462,7 +511,7 @@ int rtri_server_submit(rtri_server *s, const rtri_request *r, uint64_t *ticket)
     q.r = *r;
     q.ka = r->side == RTRI_LEFT ? r->m : r->n;
     q.rhs_bytes = (size_t)std::max<int64_t>(1, r->m * r->n) * 8;
-    q.ws_bytes = ws_estimate(*r, q.ka);
+    q.ws_bytes = ws_bound(*r, q.ka);
     q.small = r->precision == RTRI_PREC_F64 && q.ka <= s->cfg.small_max && r->m > 0 && r->n > 0;
     {
         std::lock_guard<std::mutex> lk(s->mu);

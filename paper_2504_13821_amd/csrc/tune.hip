@@ -409,7 +409,7 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
     (dtype == RTRI_F64 ? h->leaf_f64 : h->leaf_f32) = dtype == RTRI_F64 ? saved_f64 : saved_f32;
     // GEMM tile per (M = K, N)
     for (int64_t mk = 64; mk <= std::min<int64_t>(max_order / 2, 8192) && rc == RTRI_OK; mk *= 2) {
-        for (int64_t n : {64, 512, 4096}) {
+        for (int64_t n : {64, 512, 4096, 16384}) {
             if (n > max_n)
                 continue;
             int best = 1;

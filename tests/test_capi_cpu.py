@@ -110,3 +110,39 @@ def test_tuning_db_load(rt, handle, tmp_path):
     assert rt.rtri_load_tuning(handle, str(tmp_path / "missing.json").encode()) == rt.ERR_INVALID
     (tmp_path / "trunc.json").write_text('{"leaf": [')
     assert rt.rtri_load_tuning(handle, str(tmp_path / "trunc.json").encode()) == rt.ERR_INVALID
+
+
+def _leaf(rt, handle, dt, op, order, nvec):
+    v = ctypes.c_int()
+    assert rt.rtri_query_leaf(handle, dt, op, order, nvec, ctypes.byref(v)) == rt.OK
+    return v.value
+
+
+def test_leaf_policy(rt, handle, tmp_path):
+    # untuned: 64-row leaves up to order 1024 (the batched kernel's size), 256 above
+    assert _leaf(rt, handle, rt.F64, 0, 1024, 100) == 64
+    assert _leaf(rt, handle, rt.F32, 1, 1025, 100) == 256
+    # rules: the smallest bucket that covers the order, then the vector count
+    db = tmp_path / "t.json"
+    db.write_text('{"leaf": [{"dtype": "f64", "op": "trsm", "ka_max": 1024, "n_max": 512, "leaf": 32},'
+                  '{"dtype": "f64", "op": "trsm", "ka_max": 1024, "n_max": 4096, "leaf": 128},'
+                  '{"dtype": "f64", "op": "trsm", "ka_max": 4096, "n_max": 512, "leaf": 256}]}')
+    assert rt.rtri_load_tuning(handle, str(db).encode()) == rt.OK
+    assert _leaf(rt, handle, rt.F64, 0, 700, 100) == 32
+    assert _leaf(rt, handle, rt.F64, 0, 700, 1000) == 128
+    assert _leaf(rt, handle, rt.F64, 0, 3000, 10) == 256
+    assert _leaf(rt, handle, rt.F64, 0, 99999, 10) == 256        # past the largest bucket: the largest
+    # an explicit option wins over the rules
+    assert rt.rtri_set_option(handle, rt.OPT_LEAF_F64, 16) == rt.OK
+    assert _leaf(rt, handle, rt.F64, 0, 3000, 10) == 16
+    v = ctypes.c_int()
+    assert rt.rtri_query_leaf(handle, 7, 0, 1, 1, ctypes.byref(v)) == -2
+    assert rt.rtri_query_leaf(handle, rt.F64, 2, 1, 1, ctypes.byref(v)) == -3
+    assert rt.rtri_query_leaf(handle, rt.F64, 0, -1, 1, ctypes.byref(v)) == -4
+
+
+def test_shipped_tuning_rules_load(rt, handle):
+    assert rt.rtri_load_tuning(handle, rt.TUNING_DB.encode()) == rt.OK
+    for dt in (rt.F64, rt.F32):
+        for op in (0, 1):
+            assert _leaf(rt, handle, dt, op, 16384, 16384) in (16, 32, 64, 128, 256)
