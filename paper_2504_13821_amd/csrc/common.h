@@ -93,6 +93,9 @@ hipError_t launch_fill(DType t, void *B, int64_t m, int64_t n, int64_t ldb, doub
 // is rounded once, not through FP32)
 hipError_t launch_convert(ElemT src, ElemT dst, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
                           int64_t n, double scale, hipStream_t st);
+// Y = fl_dst(X^T): X is m-by-n FP64, Y is n-by-m (rounded once, as launch_convert)
+hipError_t launch_transpose_convert(ElemT dst, const double *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
+                                    int64_t n, hipStream_t st);
 // X += s * D   (X FP64, D FP32)
 hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,
                              hipStream_t st);

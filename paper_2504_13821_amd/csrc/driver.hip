@@ -41,10 +41,14 @@ struct Op {
     LeafDesc l;
 };
 
+// whether op(A) reads the GEMM copy of A transposed: op(A)(r, c) is A(c, r)
+// for trans = T, and a copy that holds A^T swaps the two readings
+inline bool ag_tr(const PlanIn &p) { return (p.trans != RTRI_NOTRANS) != p.ag_trans; }
+
 // pointer to op(A)[r0.., c0..] inside the GEMM copy of A
 inline const char *tri_block(const PlanIn &p, int64_t r0, int64_t c0)
 {
-    const int64_t off = p.trans ? c0 + r0 * p.ldag : r0 + c0 * p.ldag;
+    const int64_t off = ag_tr(p) ? c0 + r0 * p.ldag : r0 + c0 * p.ldag;
     return p.Ag + off * (int64_t)elem_size(p.gt);
 }
 
@@ -100,7 +104,7 @@ struct Planner {
         g.beta = beta;
         g.s = s;
         g.K = sh;
-        const bool tr = p.trans != RTRI_NOTRANS;
+        const bool tr = ag_tr(p);
         if (p.side == RTRI_LEFT) {
             g.M = th;
             g.N = p.n;

@@ -63,8 +63,11 @@ template <> __device__ __forceinline__ float4_t mfma16<false>(u16x8 a, u16x8 b, 
 // Load one R x BK operand tile into LDS as Ls[row * SK + k] (16-bit).
 //   SRC16: source is 16-bit (P); else FP32 rounded with to16 (Q).
 //   KC:    element (row, k) at base[k + row*ld]; else at base[row + k*ld].
+//   VEC:   16-byte aligned base and ld (8 elements for 16-bit sources, 4 for
+//          FP32): a full tile moves each 8-element chunk (contiguous in memory
+//          in either layout) with 16-byte loads.
 // Each thread moves PER elements; out-of-range elements are zero.
-template <int R, bool SRC16, bool KC, bool BF>
+template <int R, bool SRC16, bool KC, bool BF, bool VEC>
 struct Loader16 {
     static constexpr int PER = R * BK / NT;   // 16 for R = 128
     static constexpr int W = 8;               // elements per chunk
@@ -85,6 +88,30 @@ struct Loader16 {
 
     __device__ inline void load(const void *base_, int64_t ld, int tid, int rlim, int klim, bool full)
     {
+        if (VEC && full) {
+#pragma unroll
+            for (int v = 0; v < NCH; ++v) {
+                int row, k;
+                coords(v, tid, row, k);
+                const int64_t off = KC ? k + (int64_t)row * ld : row + (int64_t)k * ld;
+                if (SRC16) {
+                    const u16x8 x = *reinterpret_cast<const u16x8 *>(static_cast<const unsigned short *>(base_) + off);
+#pragma unroll
+                    for (int w = 0; w < W; ++w)
+                        reg[v * W + w] = x[w];
+                } else {
+                    const float *fp = static_cast<const float *>(base_) + off;
+                    const float4_t x0 = *reinterpret_cast<const float4_t *>(fp);
+                    const float4_t x1 = *reinterpret_cast<const float4_t *>(fp + 4);
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) {
+                        reg[v * W + w] = to16<BF>(x0[w]);
+                        reg[v * W + 4 + w] = to16<BF>(x1[w]);
+                    }
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int v = 0; v < NCH; ++v) {
             int row, k;
@@ -112,6 +139,14 @@ struct Loader16 {
         for (int v = 0; v < NCH; ++v) {
             int row, k;
             coords(v, tid, row, k);
+            if (KC) {   // 8 consecutive k of one row: one 16-byte LDS write
+                u16x8 x;
+#pragma unroll
+                for (int w = 0; w < W; ++w)
+                    x[w] = reg[v * W + w];
+                *reinterpret_cast<u16x8 *>(lds + row * SK + k) = x;
+                continue;
+            }
 #pragma unroll
             for (int w = 0; w < W; ++w) {
                 const int rr = KC ? row : row + w;
@@ -122,7 +157,7 @@ struct Loader16 {
     }
 };
 
-template <int BM, int BN, bool TP, bool TQ, bool BF, bool P16>
+template <int BM, int BN, bool TP, bool TQ, bool BF, bool P16, bool VEC>
 __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, int tiles_n)
 {
     constexpr int FM = BM / 32, FN = BN / 32;
@@ -160,8 +195,8 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
     const int rlim_n = (int)min<int64_t>(BN, g.N - n0);
     const bool full_mn = rlim_m == BM && rlim_n == BN;
 
-    Loader16<BM, P16, TP, BF> la;
-    Loader16<BN, !P16, !TQ, BF> lb;
+    Loader16<BM, P16, TP, BF, VEC> la;
+    Loader16<BN, !P16, !TQ, BF, VEC> lb;
 
     float4_t acc[FM][FN];
 #pragma unroll
@@ -235,13 +270,22 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
     }
 }
 
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
 template <bool TP, bool TQ, bool BF, bool P16>
 hipError_t launch_t16(const GemmDesc &g, hipStream_t st)
 {
     constexpr int BM = 128, BN = 128;
     const int tm = (int)((g.M + BM - 1) / BM), tn = (int)((g.N + BN - 1) / BN);
-    hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16>), dim3((unsigned)(tm * tn)), dim3(NT), 0, st, g, tm,
-                       tn);
+    // 16-byte chunks: 8 elements of the 16-bit operand, 4 of the FP32 one
+    const int64_t lp = P16 ? 8 : 4, lq = P16 ? 4 : 8;
+    const bool vec = aligned16(g.P) && aligned16(g.Q) && g.ldp % lp == 0 && g.ldq % lq == 0;
+    if (vec)
+        hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16, true>), dim3((unsigned)(tm * tn)), dim3(NT), 0, st,
+                           g, tm, tn);
+    else
+        hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16, false>), dim3((unsigned)(tm * tn)), dim3(NT), 0,
+                           st, g, tm, tn);
     return hipGetLastError();
 }
 

@@ -50,6 +50,7 @@ struct PlanIn {
     ElemT gt;                      // type of the GEMM copy of A
     const char *Ag;
     int64_t ldag;
+    bool ag_trans;                 // Ag holds A^T (column-major, ld ldag) instead of A
     ElemT st;                      // type of A as read by the pack pass
     const void *As;
     int64_t ldas;

@@ -97,6 +97,28 @@ __global__ __launch_bounds__(NT) void convert_kernel(const void *X, int64_t ldx,
     }
 }
 
+// Y = fl_D(X^T): X m-by-n FP64, Y n-by-m.  32x32 tiles pass through LDS so
+// both the reads of X and the writes of Y are contiguous along columns.
+template <ElemT D>
+__global__ __launch_bounds__(NT) void transpose_convert_kernel(const double *X, int64_t ldx, void *Y, int64_t ldy,
+                                                               int64_t m, int64_t n)
+{
+    __shared__ double t[32][33];
+    const int64_t tiles_m = (m + 31) / 32;
+    const int64_t i0 = (blockIdx.x % tiles_m) * 32, j0 = (blockIdx.x / tiles_m) * 32;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;   // 8 rows of threads
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = i0 + tx, j = j0 + r;
+        t[r][tx] = (i < m && j < n) ? X[i + j * ldx] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t yi = j0 + tx, yj = i0 + r;   // Y(yi, yj) = X(yj, yi)
+        if (yi < n && yj < m)
+            store_from_f64<D>(Y, yi + yj * ldy, t[tx][r]);
+    }
+}
+
 template <ElemT S>
 hipError_t convert_from(ElemT dst, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m, int64_t n,
                         double scale, hipStream_t st)
@@ -264,6 +286,24 @@ hipError_t launch_convert(ElemT src, ElemT dst, const void *X, int64_t ldx, void
     case ElemT::F16: return convert_from<ElemT::F16>(dst, X, ldx, Y, ldy, m, n, scale, st);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_transpose_convert(ElemT dst, const double *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
+                                    int64_t n, hipStream_t st)
+{
+    if (m <= 0 || n <= 0)
+        return hipSuccess;
+    const int64_t tiles = ((m + 31) / 32) * ((n + 31) / 32);
+    if (tiles > INT32_MAX)
+        return hipErrorInvalidValue;
+    const dim3 g((unsigned)tiles);
+    switch (dst) {
+    case ElemT::F64: hipLaunchKernelGGL((transpose_convert_kernel<ElemT::F64>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n); break;
+    case ElemT::F32: hipLaunchKernelGGL((transpose_convert_kernel<ElemT::F32>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n); break;
+    case ElemT::BF16: hipLaunchKernelGGL((transpose_convert_kernel<ElemT::BF16>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n); break;
+    case ElemT::F16: hipLaunchKernelGGL((transpose_convert_kernel<ElemT::F16>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,

@@ -143,7 +143,14 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
 
     // once per call: the GEMM copy of A, |op(A)|, alpha B, X = 0, max |R|
     auto other = [&](double bytes, auto &&f) { return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, bytes, f); };
-    e = other(8.0 * ka * ka, [&] { return launch_convert(ElemT::F64, gt, A, lda, Acopy, ka, ka, ka, 1.0, st); });
+    // The 16-bit GEMM wants its triangle operand with k contiguous: for side L
+    // (operand op(A)) and trans N, or side R (operand op(A), k = rows) and
+    // trans T, the BF16 copy holds A^T.
+    const bool ag_trans = gt == ElemT::BF16 && (left ? tr == RTRI_NOTRANS : tr != RTRI_NOTRANS);
+    e = other(8.0 * ka * ka, [&] {
+        return ag_trans ? launch_transpose_convert(gt, A, lda, Acopy, ka, ka, ka, st)
+                        : launch_convert(ElemT::F64, gt, A, lda, Acopy, ka, ka, ka, 1.0, st);
+    });
     if (e == hipSuccess)
         e = launch_zero_u64(sc, 4, st);
     if (e == hipSuccess)
@@ -187,6 +194,7 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
     lo.gt = gt;
     lo.Ag = static_cast<const char *>(Acopy);
     lo.ldag = ka;
+    lo.ag_trans = ag_trans;
     lo.st = ElemT::F64;
     lo.As = A;
     lo.ldas = lda;

@@ -52,6 +52,7 @@ struct Factor {
     int refs = 0;
     uint64_t last_use = 0;
     bool registered = false;
+    int owner = -1;               // slot whose pool and stream hold a synthetic factor
     hipEvent_t ready = nullptr;   // recorded after generation (synthetic factors)
 };
 
@@ -80,7 +81,13 @@ struct rtri_server {
     Clock::time_point t0;
     struct Slot {
         std::thread th;
+        int idx = 0;
         hipStream_t stream = nullptr;
+        // Every device allocation of the slot (synthetic factors, right-hand
+        // sides) comes from its own pool and is freed on its own stream, so
+        // freed memory is only ever reused in that stream's order: no reuse
+        // across the slots' streams, whatever the runtime would allow.
+        hipMemPool_t pool = nullptr;
         rtri_handle *h = nullptr;
         BatchScratch sc;
         size_t ws_held = 0;   // workspace the slot's handle keeps allocated (counted in used)
@@ -163,8 +170,10 @@ bool evict_one(rtri_server *s, hipStream_t st)
     if (victim == s->factors.end())
         return false;
     Factor &f = victim->second;
-    // no request uses it and every earlier user has completed on the host side
-    (void)hipFreeAsync(f.ptr, st);
+    // no request uses it and every earlier user has completed on the host
+    // side; the memory goes back to its owner's pool in the owner's stream order
+    (void)st;
+    (void)hipFreeAsync(f.ptr, s->slots[f.owner].stream);
     if (f.ready != nullptr)
         (void)hipEventDestroy(f.ready);
     s->used -= (int64_t)f.bytes;
@@ -215,7 +224,8 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool 
         nf.lda = q.ka;
         nf.uplo = q.r.uplo;
         nf.bytes = fbytes;
-        hipError_t e = hipMallocAsync((void **)&nf.ptr, fbytes, slot.stream);
+        nf.owner = slot.idx;
+        hipError_t e = hipMallocFromPoolAsync((void **)&nf.ptr, fbytes, slot.pool, slot.stream);
         if (e == hipSuccess) {
             const int kind = q.r.uplo == RTRI_LOWER ? 1 : 2;
             int rc = rtri_synth_fill(slot.h, RTRI_F64, kind, s->cfg.synth_seed, 1u, q.r.factor_id, q.ka, q.ka,
@@ -311,7 +321,7 @@ void execute(rtri_server *s, rtri_server::Slot &slot, Work &w, std::vector<rtri_
         if (fac[i]->ready != nullptr)
             e = hipStreamWaitEvent(st, fac[i]->ready, 0);
         if (e == hipSuccess)
-            e = hipMallocAsync((void **)&rhs[i], w.reqs[i].rhs_bytes, st);
+            e = hipMallocFromPoolAsync((void **)&rhs[i], w.reqs[i].rhs_bytes, slot.pool, st);
         if (e == hipSuccess && rtri_synth_fill(h, RTRI_F64, 0, s->cfg.synth_seed, 2u, r.rhs_id, r.m, r.n, 0.0, rhs[i],
                                                r.m) != RTRI_OK)
             e = hipErrorUnknown;
@@ -448,16 +458,33 @@ int rtri_server_create(const rtri_server_cfg *cfg, rtri_server **out)
     s->t0 = Clock::now();
     hipError_t e = hipGetDevice(&s->device);
     s->slots.resize(cfg->slots);
-    for (auto &sl : s->slots) {
+    for (int i = 0; i < cfg->slots; ++i) {
+        auto &sl = s->slots[i];
+        sl.idx = i;
         if (e == hipSuccess)
             e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess && rtri_create(&sl.h, sl.stream) != RTRI_OK)
             e = hipErrorOutOfMemory;
+        if (e == hipSuccess) {
+            hipMemPoolProps props{};
+            props.allocType = hipMemAllocationTypePinned;
+            props.handleTypes = hipMemHandleTypeNone;
+            props.location.type = hipMemLocationTypeDevice;
+            props.location.id = s->device;
+            e = hipMemPoolCreate(&sl.pool, &props);
+        }
+        int off = 0;
+        if (e == hipSuccess)
+            e = hipMemPoolSetAttribute(sl.pool, hipMemPoolReuseAllowOpportunistic, &off);
+        if (e == hipSuccess)
+            e = hipMemPoolSetAttribute(sl.pool, hipMemPoolReuseAllowInternalDependencies, &off);
     }
     if (e != hipSuccess) {
         for (auto &sl : s->slots) {
             if (sl.h)
                 rtri_destroy(sl.h);
+            if (sl.pool)
+                (void)hipMemPoolDestroy(sl.pool);
             if (sl.stream)
                 (void)hipStreamDestroy(sl.stream);
         }
@@ -582,17 +609,18 @@ int rtri_server_destroy(rtri_server *s)
     for (auto &sl : s->slots)
         if (sl.th.joinable())
             sl.th.join();
-    for (auto &sl : s->slots)
-        (void)hipStreamSynchronize(sl.stream);
     for (auto &kv : s->factors) {
         if (!kv.second.registered && kv.second.ptr != nullptr)
-            (void)hipFree(kv.second.ptr);
+            (void)hipFreeAsync(kv.second.ptr, s->slots[kv.second.owner].stream);
         if (kv.second.ready != nullptr)
             (void)hipEventDestroy(kv.second.ready);
     }
+    for (auto &sl : s->slots)
+        (void)hipStreamSynchronize(sl.stream);
     for (auto &sl : s->slots) {
         batch_scratch_free(sl.sc);
         rtri_destroy(sl.h);
+        (void)hipMemPoolDestroy(sl.pool);
         (void)hipStreamDestroy(sl.stream);
     }
     delete s;

@@ -150,3 +150,24 @@ def test_serving_rejects(rt):
     comps = srv.poll()
     srv.close()
     assert sorted(c["status"] for c in comps) == [0, rt.ERR_INVALID]
+
+
+def test_serving_large_mix_alone_equal(rt, h):
+    """The bench's request mix at reduced orders: TRSM 80 % / TRMM 20 %, half of
+    the TRSMs refined from BF16, orders log-uniform up to 3072, right-hand
+    sides up to 512, factors shared; every request must succeed and equal its
+    alone result bit for bit."""
+    g = synth.rng(synth.W_SERVE, 3)
+    reqs = _stream(240, g, m_hi=3072, n_hi=512, mixed_frac=0.5, n_factors=40)
+    for r in reqs:
+        if r["precision"] == 2:
+            r["precision"] = 1
+    say("serving large mix", len(reqs))
+    results, comps, stats = _run_stream(rt, reqs, rate=3000.0, slots=4, max_batch=64, small_max=1024)
+    bad = [(c["status"], c["iters"], c["eta"], results[c["ticket"]][0]) for c in comps if c["status"] != 0]
+    assert not bad, bad[:4]
+    diff = []
+    for tk, (r, res) in results.items():
+        if not np.array_equal(res, _alone(rt, h, r)):
+            diff.append(r)
+    assert not diff, (len(diff), diff[:4])
