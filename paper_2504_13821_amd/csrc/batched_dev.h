@@ -5,6 +5,7 @@
 
 #include "gemm_core.h"
 #include "leaf_core.h"
+#include "mleaf_core.h"
 
 namespace rtri {
 namespace bk {
@@ -34,26 +35,140 @@ struct BItem {
 
 // ---- device ----
 
+// 64-row leaves run on the matrix cores (canonical staging + A-operand tiles),
+// 16/32-row leaves as one-lane-per-vector substitution in wavefront 0
 template <typename T, int NB>
 struct Smem {
     static constexpr int GEMM = 2 * gk::lds_elems<T, 64, true>() + 2 * gk::lds_elems<T, 64, false>() + 64;
-    static constexpr int LEAF = lk::tri_n<NB>() + lk::WAVE * (NB + 1);
+    static constexpr int LEAF = NB == 64 ? lk::tri_n<64>() + mk::ntiles<64>() * mk::TE
+                                         : lk::tri_n<NB>() + lk::WAVE * (NB + 1);
     static constexpr int N = GEMM > LEAF ? GEMM : LEAF;
 };
 
 template <typename T, bool TP, bool TQ>
-__device__ void run_gemm(const GemmDesc &g, T *smem)
+__device__ __forceinline__ void run_gemm(const GemmDesc &g, T *smem)
 {
     constexpr int EA = gk::lds_elems<T, 64, TP>();
     T *As = smem;
     T *Bs = smem + 2 * EA;
+    // an opaque copy of the thread index: the offsets derived from it are
+    // recomputed here instead of being hoisted out of the persistent loop and
+    // kept live for the whole kernel
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     for (int64_t m0 = 0; m0 < g.M; m0 += 64)
         for (int64_t n0 = 0; n0 < g.N; n0 += 64)
-            gk::gemm_tile<T, 64, 64, TP, TQ, false>(g, m0, n0, As, Bs);
+            gk::gemm_tile<T, 64, 64, TP, TQ, false>(g, m0, n0, As, Bs, tid);
+}
+
+// The chunk's vectors [v0, v0 + 64) against one diagonal block of 64 rows, on
+// the matrix cores: the same tiles (diagonal tiles inverted by the same FP64
+// substitution) and the same MFMA sequence as the single-call 64-row leaf, so
+// the results agree bit for bit.  Dg: 4 x 16 x 17 doubles of LDS.
+template <typename T, bool SOLVE>
+__device__ __forceinline__ void run_mleaf(const BInst &in, const BOp &op, int v0, T *smem, double *Dg)
+{
+    constexpr int NB = 64, NBK = NB / mk::RB;
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));   // see run_gemm
+    const int d0 = op.a0, h = op.a1;
+    T *Ls = smem;                        // canonical block, ascending stream order
+    T *Lt = smem + lk::tri_n<NB>();      // the 10 tiles in A-operand order
+    const bool mtrans = in.left ? in.tr != 0 : in.tr == 0;
+    const bool mlower = in.left ? in.low != 0 : in.low == 0;
+    lk::stage_block<sizeof(T) == 8 ? ElemT::F64 : ElemT::F32, T, NB, true, NT>(
+        in.A, (int64_t)d0 + (int64_t)d0 * in.lda, in.lda, h, mtrans, mlower, in.unit != 0, Ls, tid);
+    __syncthreads();
+    auto canon = [&](int i, int k) { return Ls[lk::colstart<NB, true>(k) + (i - k)]; };
+    if (tid < NBK * mk::RB) {
+        const int j = tid / mk::RB, k = tid % mk::RB;
+        double y[mk::RB];
+        mk::diag_column<SOLVE>(
+            k, [&](int m, int q) { return (double)canon(mk::RB * j + m, mk::RB * j + q); }, y);
+#pragma unroll
+        for (int m = 0; m < mk::RB; ++m)
+            Dg[(j * mk::RB + m) * (mk::RB + 1) + k] = y[m];
+    }
+    __syncthreads();
+    for (int e = tid; e < mk::ntiles<NB>() * mk::TE; e += NT) {
+        const int tile = e / mk::TE;
+        int m, kk;
+        mk::tile_entry<T>(e % mk::TE, m, kk);
+        int j = 0;
+        while (j + 1 < NBK && mk::cb_tile(NBK, j + 1) <= tile)
+            ++j;
+        const int i = j + (tile - mk::cb_tile(NBK, j));
+        T v;
+        if (i == j) {
+            v = (T)Dg[(j * mk::RB + m) * (mk::RB + 1) + kk];
+        } else {
+            v = canon(mk::RB * i + m, mk::RB * j + kk);
+            if (SOLVE)
+                v = -v;
+        }
+        Lt[e] = v;
+    }
+    __syncthreads();
+
+    using AccT = mk::Acc<T>;
+    const int lane = tid % 64;
+    const int w = __builtin_amdgcn_readfirstlane(tid / 64);
+    const int c = lane % 16, g = lane / 16;
+    int64_t sd, si, nvec;
+    T *B = static_cast<T *>(in.B);
+    if (in.left) {
+        B += d0;
+        sd = 1;
+        si = in.ldb;
+        nvec = in.n;
+    } else {
+        B += (int64_t)d0 * in.ldb;
+        sd = in.ldb;
+        si = 1;
+        nvec = in.m;
+    }
+    const int64_t vec = (int64_t)v0 + 16 * w + c;
+    const bool act = vec < nvec;
+    T *Bv = B + vec * si;
+    typename AccT::V acc[NBK];
+#pragma unroll
+    for (int i = 0; i < NBK; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = mk::RB * i + AccT::row(g, r);
+            const int dm = mlower ? row : h - 1 - row;
+            acc[i][r] = (act && row < h) ? Bv[(int64_t)dm * sd] : T(0);
+        }
+    const T alpha = T(op.use_alpha ? in.alpha : 1.0);
+    if (SOLVE)
+#pragma unroll
+        for (int i = 0; i < NBK; ++i)
+            acc[i] *= alpha;
+    mk::leaf_phases<T, NB, SOLVE>(
+        acc, lane,
+        [&](int s, int ti) -> const T * {
+            const int j = SOLVE ? s : NBK - 1 - s;
+            return Lt + (mk::cb_tile(NBK, j) + ti) * mk::TE;
+        },
+        [](int) {});
+    if (!SOLVE)
+#pragma unroll
+        for (int i = 0; i < NBK; ++i)
+            acc[i] *= alpha;
+#pragma unroll
+    for (int i = 0; i < NBK; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = mk::RB * i + AccT::row(g, r);
+            const int dm = mlower ? row : h - 1 - row;
+            if (act && row < h)
+                Bv[(int64_t)dm * sd] = acc[i][r];
+        }
+    __syncthreads();
 }
 
 template <typename T, int NB, bool SOLVE>
-__device__ void run_leaf(const BInst &in, const BOp &op, int v0, T *smem)
+__device__ __forceinline__ void run_leaf(const BInst &in, const BOp &op, int v0, T *smem)
 {
     const int tid = threadIdx.x;
     const int d0 = op.a0, h = op.a1;
@@ -62,8 +177,8 @@ __device__ void run_leaf(const BInst &in, const BOp &op, int v0, T *smem)
     // the block of op(A) (side L) or of op(A)^T (side R), see driver.hip
     const bool mtrans = in.left ? in.tr != 0 : in.tr == 0;
     const bool mlower = in.left ? in.low != 0 : in.low == 0;
-    lk::stage_block<sizeof(T) == 8 ? ElemT::F64 : ElemT::F32, T, NB, SOLVE>(
-        in.A, (int64_t)d0 + (int64_t)d0 * in.lda, in.lda, h, mtrans, mlower, in.unit != 0, Ls, tid, NT);
+    lk::stage_block<sizeof(T) == 8 ? ElemT::F64 : ElemT::F32, T, NB, SOLVE, NT>(
+        in.A, (int64_t)d0 + (int64_t)d0 * in.lda, in.lda, h, mtrans, mlower, in.unit != 0, Ls, tid);
     __syncthreads();
     if (tid < lk::WAVE) {
         LeafDesc d{};
@@ -97,13 +212,14 @@ __global__ __launch_bounds__(NT) void batched_kernel(const BInst *insts, const B
                                                      const BOp *ops, unsigned *counter)
 {
     __shared__ __attribute__((aligned(16))) T smem[Smem<T, NB>::N];
+    __shared__ double Dg[NB == 64 ? 4 * 16 * 17 : 1];
     __shared__ int s_item;
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0)
             s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
-        const int it = s_item;
+        const int it = __builtin_amdgcn_readfirstlane(s_item);   // uniform: scalar loads of the tables
         __syncthreads();
         if (it >= nitems)
             return;   // every wave of the workgroup leaves together
@@ -114,10 +230,17 @@ __global__ __launch_bounds__(NT) void batched_kernel(const BInst *insts, const B
         for (int o = in.op_begin; o < in.op_end; ++o) {
             const BOp op = ops[o];
             if (op.kind == 0) {
-                if (in.solve)
-                    run_leaf<T, NB, true>(in, op, item.v0, smem);
-                else
-                    run_leaf<T, NB, false>(in, op, item.v0, smem);
+                if constexpr (NB == 64) {
+                    if (in.solve)
+                        run_mleaf<T, true>(in, op, item.v0, smem, Dg);
+                    else
+                        run_mleaf<T, false>(in, op, item.v0, smem, Dg);
+                } else {
+                    if (in.solve)
+                        run_leaf<T, NB, true>(in, op, item.v0, smem);
+                    else
+                        run_leaf<T, NB, false>(in, op, item.v0, smem);
+                }
             } else if (op.kind == 1) {
                 GemmDesc g{};
                 const int t0 = op.a0, th = op.a1, s0 = op.a2, sh = op.a3;

@@ -67,10 +67,11 @@ struct LeafDesc {
 };
 
 inline int64_t tri_elems(int nb) { return (int64_t)nb * (nb + 1) / 2; }
-// Leaves of 128 and 256 rows read a tiled packed form instead (see mleaf.hip):
-// the 16 x 16 tiles of the lower triangle, column block by column block.
+// Leaves of 64, 128 and 256 rows read a tiled packed form instead (see
+// mleaf.hip): the 16 x 16 tiles of the lower triangle, column block by column
+// block.
 inline int64_t bpack_elems(int nbmax) { return (int64_t)128 * (nbmax / 16) * (nbmax / 16 + 1); }
-inline int64_t pack_elems(int nbmax) { return nbmax <= 64 ? tri_elems(nbmax) : bpack_elems(nbmax); }
+inline int64_t pack_elems(int nbmax) { return nbmax <= 32 ? tri_elems(nbmax) : bpack_elems(nbmax); }
 
 enum class DType { F64, F32 };
 // element types of matrices in memory
@@ -83,7 +84,7 @@ hipError_t launch_gemm16(bool bf16, bool p16, const GemmDesc &g, hipStream_t st)
 // pack diagonal blocks read from A of type src into packed triangles of type dst
 hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);
-// matrix-core leaves (nbmax = 128 or 256, mleaf.hip), called by launch_pack / launch_leaf
+// matrix-core leaves (nbmax = 64, 128 or 256, mleaf.hip), called by launch_pack / launch_leaf
 hipError_t launch_bpack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_bleaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);
 hipError_t launch_fill(DType t, void *B, int64_t m, int64_t n, int64_t ldb, double value, hipStream_t st);
@@ -96,9 +97,9 @@ hipError_t launch_convert(ElemT src, ElemT dst, const void *X, int64_t ldx, void
 // Y = fl_dst(X^T): X is m-by-n FP64, Y is n-by-m (rounded once, as launch_convert)
 hipError_t launch_transpose_convert(ElemT dst, const double *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
                                     int64_t n, hipStream_t st);
-// X += s * D   (X FP64, D FP32)
+// X += s * D   (X FP64, D FP32); then W = X when W != nullptr
 hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,
-                             hipStream_t st);
+                             double *W, int64_t ldw, hipStream_t st);
 // Refinement bookkeeping.  Vectors are columns (by_cols) or rows of the m-by-n
 // matrices.  R = R0 - W; per vector v: eta_v = |R_v|inf / (anorm |X_v|inf + |R0_v|inf);
 // out[0] = max_v eta_v, out[1] = max |R| (both as ordered bit patterns of

@@ -131,14 +131,14 @@ struct TileLoader {
 // workgroup.  As / Bs: two LDS slots each (lds_elems elements per slot).
 // Ends with a barrier, so the LDS slots may be reused right after it returns.
 template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC>
-__device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t n0, T *As, T *Bs)
+__device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t n0, T *As, T *Bs,
+                                          int tid = threadIdx.x)
 {
     constexpr int FM = BM / 32, FN = BN / 32;
     constexpr bool KCA = TP, KCB = !TQ;           // operand layouts (see lds_at)
     constexpr int EA = lds_elems<T, BM, KCA>(), EB = lds_elems<T, BN, KCB>();
     using AccT = Acc<T>;
     using V = typename AccT::V;
-    const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
     const int wm = wave & 1, wn = wave >> 1;
     const int lc = lane % 16, lg = lane / 16;

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackDesc p)
     const int64_t d0 = (int64_t)blockIdx.x * NB;
     const int nb = (int)min<int64_t>(NB, p.ka - d0);
     T *out = static_cast<T *>(p.out) + (int64_t)blockIdx.x * tri_n<NB>();
-    stage_block<S, T, NB, ASC>(p.A, d0 + d0 * p.lda, p.lda, nb, p.mtrans, p.mlower, p.unit, out, threadIdx.x, 256);
+    stage_block<S, T, NB, ASC, 256>(p.A, d0 + d0 * p.lda, p.lda, nb, p.mtrans, p.mlower, p.unit, out, threadIdx.x);
 }
 
 // One wavefront per 64 vectors of the panel.  The block's packed form is copied
@@ -99,7 +99,6 @@ hipError_t pack_t(bool solve, int nbmax, const PackDesc &p, hipStream_t st)
     switch (nbmax) {
     case 16: return pack_nb<S, T, 16>(solve, p, st);
     case 32: return pack_nb<S, T, 32>(solve, p, st);
-    case 64: return pack_nb<S, T, 64>(solve, p, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -110,7 +109,7 @@ hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDe
 {
     if (p.ka <= 0)
         return hipSuccess;
-    if (nbmax > 64)
+    if (nbmax >= 64)
         return launch_bpack(src, dst, solve, nbmax, p, st);
     if (dst == DType::F64) {
         if (src != ElemT::F64)
@@ -132,20 +131,18 @@ hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStr
         return hipSuccess;
     if (l.nb > nbmax)
         return hipErrorInvalidValue;
-    if (nbmax > 64)
+    if (nbmax >= 64)
         return launch_bleaf(t, solve, nbmax, l, st);
     if (t == DType::F64) {
         switch (nbmax) {
         case 16: return launch_nb<double, 16>(solve, l, st);
         case 32: return launch_nb<double, 32>(solve, l, st);
-        case 64: return launch_nb<double, 64>(solve, l, st);
         default: return hipErrorInvalidValue;
         }
     }
     switch (nbmax) {
     case 16: return launch_nb<float, 16>(solve, l, st);
     case 32: return launch_nb<float, 32>(solve, l, st);
-    case 64: return launch_nb<float, 64>(solve, l, st);
     default: return hipErrorInvalidValue;
     }
 }

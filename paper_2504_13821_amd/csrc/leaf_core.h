@@ -35,25 +35,36 @@ template <> __device__ __forceinline__ double ld_src<ElemT::F16>(const void *p, 
 }
 
 // Write one diagonal block (nb rows from element `base` of A) in canonical
-// packed stream order to `out` (global or LDS), using nthr threads from tid.
-// L(i,k) = Mx(p(i), p(k)), p(i) = i (lower) or nb-1-i (upper); rows past nb
-// and a unit diagonal become the identity.  The source may be narrower than T
-// (exact widening) or FP64 stored as FP32 (one rounding, to nearest).
-template <ElemT S, typename T, int NB, bool ASC>
+// packed stream order to `out` (global or LDS), using the NTHR threads of the
+// workgroup (tid = thread index).  L(i,k) = Mx(p(i), p(k)), p(i) = i (lower)
+// or nb-1-i (upper); rows past nb and a unit diagonal become the identity.
+// The source may be narrower than T (exact widening) or FP64 stored as FP32
+// (one rounding, to nearest).  All of a thread's loads are issued before its
+// first store, so one workgroup waits for one memory round trip, not one per
+// element.
+template <ElemT S, typename T, int NB, bool ASC, int NTHR>
 __device__ __forceinline__ void stage_block(const void *A, int64_t base, int64_t lda, int nb, bool mtrans,
-                                            bool mlower, bool unit, T *out, int tid, int nthr)
+                                            bool mlower, bool unit, T *out, int tid)
 {
-    for (int e = tid; e < NB * NB; e += nthr) {
+    constexpr int PER = (NB * NB + NTHR - 1) / NTHR;
+    T v[PER];
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = tid + t * NTHR;
         const int i = e % NB, k = e / NB;
-        if (i < k)
-            continue;
-        T v = (i == k) ? T(1) : T(0);
-        if (i < nb && (i > k || !unit)) {
+        v[t] = (i == k) ? T(1) : T(0);
+        if (e < NB * NB && i >= k && i < nb && (i > k || !unit)) {
             const int r = mlower ? i : nb - 1 - i;
             const int c = mlower ? k : nb - 1 - k;
-            v = (T)ld_src<S>(A, base + (mtrans ? c + (int64_t)r * lda : r + (int64_t)c * lda));
+            v[t] = (T)ld_src<S>(A, base + (mtrans ? c + (int64_t)r * lda : r + (int64_t)c * lda));
         }
-        out[colstart<NB, ASC>(k) + (i - k)] = v;
+    }
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int e = tid + t * NTHR;
+        const int i = e % NB, k = e / NB;
+        if (e < NB * NB && i >= k)
+            out[colstart<NB, ASC>(k) + (i - k)] = v[t];
     }
 }
 

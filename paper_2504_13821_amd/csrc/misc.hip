@@ -1,7 +1,9 @@
 // Element-wise kernels: fills, precision conversions, and the bookkeeping of
 // the mixed-precision refinement (correction update, residual, norms).  All of
-// them are bound by HBM bandwidth: grid-stride loops over 256-thread
-// workgroups, with consecutive threads on consecutive addresses.
+// them are bound by HBM bandwidth.  Matrix kernels use a 2-D grid (x: chunks of
+// 4 x 256 rows, y: columns, striding when there are more columns than grid
+// rows), so consecutive threads touch consecutive addresses and no thread
+// divides indices.
 #include "common.h"
 
 namespace rtri {
@@ -10,19 +12,30 @@ namespace {
 
 constexpr int NT = 256;
 
-unsigned grid_for(int64_t total)
+constexpr int RPT = 4;   // rows per thread of a matrix kernel
+
+dim3 grid2d(int64_t m, int64_t n)
 {
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + NT - 1) / NT, 8192));
+    return dim3((unsigned)((m + NT * RPT - 1) / (NT * RPT)), (unsigned)std::min<int64_t>(n, 65535));
+}
+
+// f(i, j) for every element of an m-by-n matrix (launched with grid2d)
+template <class F> __device__ __forceinline__ void for_each_2d(int64_t m, int64_t n, F &&f)
+{
+    const int64_t i0 = (int64_t)blockIdx.x * (NT * RPT) + threadIdx.x;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+            const int64_t i = i0 + t * NT;
+            if (i < m)
+                f(i, j);
+        }
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void fill_kernel(T *B, int64_t m, int64_t n, int64_t ldb, T value)
 {
-    const int64_t total = m * n;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-        const int64_t i = e % m, j = e / m;
-        B[i + j * ldb] = value;
-    }
+    for_each_2d(m, n, [&](int64_t i, int64_t j) { B[i + j * ldb] = value; });
 }
 
 // ---- conversions ----
@@ -89,12 +102,10 @@ template <ElemT S, ElemT D>
 __global__ __launch_bounds__(NT) void convert_kernel(const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
                                                      int64_t n, double scale)
 {
-    const int64_t total = m * n;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-        const int64_t i = e % m, j = e / m;
+    for_each_2d(m, n, [&](int64_t i, int64_t j) {
         const double v = load_as_f64<S>(X, i + j * ldx);
         store_from_f64<D>(Y, i + j * ldy, scale == 1.0 ? v : scale * v);
-    }
+    });
 }
 
 // Y = fl_D(X^T): X m-by-n FP64, Y n-by-m.  32x32 tiles pass through LDS so
@@ -123,7 +134,7 @@ template <ElemT S>
 hipError_t convert_from(ElemT dst, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m, int64_t n,
                         double scale, hipStream_t st)
 {
-    const dim3 g(grid_for(m * n));
+    const dim3 g = grid2d(m, n);
     switch (dst) {
     case ElemT::F64: hipLaunchKernelGGL((convert_kernel<S, ElemT::F64>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n, scale); break;
     case ElemT::F32: hipLaunchKernelGGL((convert_kernel<S, ElemT::F32>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n, scale); break;
@@ -153,14 +164,16 @@ __device__ __forceinline__ double wave_max(double v)
 
 __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
+// X += s * D, and W = X when W is given
 __global__ __launch_bounds__(NT) void add_scaled_kernel(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m,
-                                                        int64_t n, double s)
+                                                        int64_t n, double s, double *W, int64_t ldw)
 {
-    const int64_t total = m * n;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-        const int64_t i = e % m, j = e / m;
-        X[i + j * ldx] += s * (double)D[i + j * ldd];
-    }
+    for_each_2d(m, n, [&](int64_t i, int64_t j) {
+        const double x = X[i + j * ldx] + s * (double)D[i + j * ldd];
+        X[i + j * ldx] = x;
+        if (W != nullptr)
+            W[i + j * ldw] = x;
+    });
 }
 
 // vectors are columns: one wavefront per column, lanes run down the rows
@@ -243,12 +256,8 @@ __global__ __launch_bounds__(NT) void line_norm_kernel(const double *A, int64_t 
 __global__ __launch_bounds__(NT) void max_abs_kernel(const double *X, int64_t ldx, int64_t m, int64_t n,
                                                      unsigned long long *out)
 {
-    const int64_t total = m * n;
     double v = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
-        const int64_t i = e % m, j = e / m;
-        v = nmax(v, fabs(X[i + j * ldx]));
-    }
+    for_each_2d(m, n, [&](int64_t i, int64_t j) { v = nmax(v, fabs(X[i + j * ldx])); });
     v = wave_max(v);
     if (threadIdx.x % 64 == 0)
         atomicMax(out, ordered_bits(v));
@@ -266,7 +275,7 @@ hipError_t launch_fill(DType t, void *B, int64_t m, int64_t n, int64_t ldb, doub
 {
     if (m <= 0 || n <= 0)
         return hipSuccess;
-    const dim3 g(grid_for(m * n));
+    const dim3 g = grid2d(m, n);
     if (t == DType::F64)
         hipLaunchKernelGGL(fill_kernel<double>, g, dim3(NT), 0, st, static_cast<double *>(B), m, n, ldb, value);
     else
@@ -307,11 +316,11 @@ hipError_t launch_transpose_convert(ElemT dst, const double *X, int64_t ldx, voi
 }
 
 hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,
-                             hipStream_t st)
+                             double *W, int64_t ldw, hipStream_t st)
 {
     if (m <= 0 || n <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(add_scaled_kernel, dim3(grid_for(m * n)), dim3(NT), 0, st, X, ldx, D, ldd, m, n, s);
+    hipLaunchKernelGGL(add_scaled_kernel, grid2d(m, n), dim3(NT), 0, st, X, ldx, D, ldd, m, n, s, W, ldw);
     return hipGetLastError();
 }
 
@@ -345,7 +354,7 @@ hipError_t launch_max_abs(const double *X, int64_t ldx, int64_t m, int64_t n, un
 {
     if (m <= 0 || n <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(max_abs_kernel, dim3(grid_for(m * n)), dim3(NT), 0, st, X, ldx, m, n, out);
+    hipLaunchKernelGGL(max_abs_kernel, grid2d(m, n), dim3(NT), 0, st, X, ldx, m, n, out);
     return hipGetLastError();
 }
 

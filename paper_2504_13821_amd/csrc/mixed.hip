@@ -236,9 +236,8 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
         if (rc != RTRI_OK)
             return rc;
         lo.skip_pack = true;
-        e = other(20.0 * mn, [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, st); });
-        if (e == hipSuccess)
-            e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, X, ld, W, ld, m, n, 1.0, st); });
+        // X += s D, and W = X for the residual's product (one pass)
+        e = other(28.0 * mn, [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, W, ld, st); });
         if (e != hipSuccess)
             return hip_fail(h, e);
         rc = run_plan(h, mul);

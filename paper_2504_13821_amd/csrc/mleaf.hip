@@ -1,8 +1,8 @@
-// Matrix-core leaves for diagonal blocks of 128 or 256 rows (paper, Sec. 3.3:
+// Matrix-core leaves for diagonal blocks of 64, 128 or 256 rows (paper, Sec. 3.3:
 // the base case of the recursion handles one diagonal block against the panel
 // of right-hand sides; the leaf size is a tuning parameter).
 //
-// Why not one lane per vector, as in the 64-row leaf: with the triangle in LDS,
+// Why not one lane per vector, as in the 16/32-row leaves: with the triangle in LDS,
 // every lane-FMA pulls its (broadcast) triangle value through the LDS return
 // path, 8 bytes per lane for FP64, so several wavefronts on a CU saturate LDS
 // long before the FMA units.  Here the panel lives in MFMA accumulator tiles
@@ -32,27 +32,18 @@
 //
 // The packed triangle streams through a three-slot LDS ring one column block
 // (16 columns, tiles j..NB/16-1) at a time, two phases ahead of its use.
-#include "gemm_core.h"
 #include "leaf_core.h"
+#include "mleaf_core.h"
 
 namespace rtri {
 
 namespace {
 
-using gk::Acc;
 using lk::ld_src;
-
-constexpr int RB = 16;      // rows / columns of a tile
-constexpr int TE = 256;     // elements of a tile
-
-__host__ __device__ constexpr int cb_tile(int nbk, int c) { return c * nbk - c * (c - 1) / 2; }
-
-// element (slice t, lane) of a tile: 16-byte groups of W slices per lane
-template <typename T> __host__ __device__ constexpr int tile_pos(int t, int lane)
-{
-    constexpr int W = 16 / (int)sizeof(T);
-    return ((t / W) * 64 + lane) * W + t % W;
-}
+using mk::RB;
+using mk::TE;
+using mk::cb_tile;
+using mk::tile_pos;
 
 // Canonical block element L(i, k), i >= k, rounded to T (identity past nb and
 // on a unit diagonal).
@@ -88,23 +79,8 @@ __global__ __launch_bounds__(256) void mpack_kernel(PackDesc p)
     if (tid < NBK * RB) {
         const int j = tid / RB, k = tid % RB;
         double y[RB];
-#pragma unroll
-        for (int m = 0; m < RB; ++m) {
-            if (!SOLVE) {
-                y[m] = m >= k ? (double)canon<S, T>(p, base, nb, RB * j + m, RB * j + k) : 0.0;
-                continue;
-            }
-            if (m < k) {
-                y[m] = 0.0;
-                continue;
-            }
-            double s = m == k ? 1.0 : 0.0;
-#pragma unroll
-            for (int q = 0; q < m; ++q)
-                if (q >= k)
-                    s = __builtin_fma(-(double)canon<S, T>(p, base, nb, RB * j + m, RB * j + q), y[q], s);
-            y[m] = s / (double)canon<S, T>(p, base, nb, RB * j + m, RB * j + m);
-        }
+        mk::diag_column<SOLVE>(
+            k, [&](int m, int q) { return (double)canon<S, T>(p, base, nb, RB * j + m, RB * j + q); }, y);
 #pragma unroll
         for (int m = 0; m < RB; ++m)
             Dg[j][m][k] = y[m];
@@ -112,15 +88,13 @@ __global__ __launch_bounds__(256) void mpack_kernel(PackDesc p)
     __syncthreads();
 
     for (int e = tid; e < NTILE * TE; e += 256) {
-        const int tile = e / TE, pos = e % TE;
-        constexpr int W = 16 / (int)sizeof(T);
-        const int q = pos / W;
-        const int lane = q % 64, t = (q / 64) * W + pos % W;
+        const int tile = e / TE;
+        int m, kk;
+        mk::tile_entry<T>(e % TE, m, kk);
         int j = 0;
         while (j + 1 < NBK && cb_tile(NBK, j + 1) <= tile)
             ++j;
         const int i = j + (tile - cb_tile(NBK, j));
-        const int m = lane % 16, kk = Acc<T>::row(lane / 16, t);
         T v;
         if (i == j) {
             v = (T)Dg[j][m][kk];
@@ -146,7 +120,7 @@ __global__ __launch_bounds__(256, 1) void mleaf_kernel(LeafDesc d, const T *__re
     constexpr int NV = SLOT / (256 * W);          // 16-byte loads per thread per column block
     static_assert(NV * 256 * W == SLOT, "column block split");
     using V = typename Vec16<T>::V;
-    using AccT = Acc<T>;
+    using AccT = mk::Acc<T>;
     using A4 = typename AccT::V;
 
     __shared__ __attribute__((aligned(16))) T Lr[3 * SLOT];
@@ -210,37 +184,15 @@ __global__ __launch_bounds__(256, 1) void mleaf_kernel(LeafDesc d, const T *__re
         gload(2, pre0);
     __syncthreads();
 
-    // D = M * X + C for the tile M at tile index ti of the column block in slot sl
-    auto mm = [&](int sl, int ti, const A4 &X, A4 C) {
-        const T *Mt = Lr + sl * SLOT + ti * TE;
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            C = AccT::mfma(Mt[tile_pos<T>(t, lane)], X[t], C);
-        return C;
-    };
-
-#pragma unroll
-    for (int s = 0; s < NBK; ++s) {
-        const int j = cbk(s), sl = s % 3;
-        if (SOLVE) {
-            acc[j] = mm(sl, 0, acc[j], A4{0, 0, 0, 0});
-#pragma unroll
-            for (int i = j + 1; i < NBK; ++i)
-                acc[i] = mm(sl, i - j, acc[j], acc[i]);
-        } else {
-#pragma unroll
-            for (int i = j + 1; i < NBK; ++i)
-                acc[i] = mm(sl, i - j, acc[j], acc[i]);
-            acc[j] = mm(sl, 0, acc[j], A4{0, 0, 0, 0});
-        }
-        if (s + 1 < NBK) {
+    mk::leaf_phases<T, NB, SOLVE>(
+        acc, lane, [&](int s, int ti) -> const T * { return Lr + (s % 3) * SLOT + ti * TE; },
+        [&](int s) {
             if (s + 2 < NBK)
                 lstore(s + 2, pre0);
             if (s + 3 < NBK)
                 gload(s + 3, pre0);
             __syncthreads();
-        }
-    }
+        });
 
     if (!SOLVE)
 #pragma unroll
@@ -283,7 +235,9 @@ void mpack_nb(bool solve, const PackDesc &p, hipStream_t st)
 template <ElemT S, typename T>
 hipError_t mpack_t(bool solve, int nbmax, const PackDesc &p, hipStream_t st)
 {
-    if (nbmax == 128)
+    if (nbmax == 64)
+        mpack_nb<S, T, 64>(solve, p, st);
+    else if (nbmax == 128)
         mpack_nb<S, T, 128>(solve, p, st);
     else if (nbmax == 256)
         mpack_nb<S, T, 256>(solve, p, st);
@@ -294,7 +248,8 @@ hipError_t mpack_t(bool solve, int nbmax, const PackDesc &p, hipStream_t st)
 
 }  // namespace
 
-static_assert(TE * (8 * 9 / 2) == 9216 && TE * (16 * 17 / 2) == 34816, "packed sizes match bpack_elems");
+static_assert(TE * mk::ntiles<64>() == 2560 && TE * mk::ntiles<128>() == 9216 && TE * mk::ntiles<256>() == 34816,
+              "packed sizes match bpack_elems");
 
 hipError_t launch_bpack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st)
 {
@@ -320,11 +275,20 @@ hipError_t launch_bleaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipSt
         return hipSuccess;
     if (l.nb > nbmax)
         return hipErrorInvalidValue;
-    if (t == DType::F64)
-        return nbmax == 128 ? mleaf_nb<double, 128>(solve, l, st)
-                            : nbmax == 256 ? mleaf_nb<double, 256>(solve, l, st) : hipErrorInvalidValue;
-    return nbmax == 128 ? mleaf_nb<float, 128>(solve, l, st)
-                        : nbmax == 256 ? mleaf_nb<float, 256>(solve, l, st) : hipErrorInvalidValue;
+    if (t == DType::F64) {
+        switch (nbmax) {
+        case 64: return mleaf_nb<double, 64>(solve, l, st);
+        case 128: return mleaf_nb<double, 128>(solve, l, st);
+        case 256: return mleaf_nb<double, 256>(solve, l, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    switch (nbmax) {
+    case 64: return mleaf_nb<float, 64>(solve, l, st);
+    case 128: return mleaf_nb<float, 128>(solve, l, st);
+    case 256: return mleaf_nb<float, 256>(solve, l, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace rtri
