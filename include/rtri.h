@@ -72,7 +72,8 @@ enum {
 enum {
     RTRI_OPT_LEAF_F64 = 1,   /* leaf size for FP64 (16, 32, 64, 128 or 256; 0 = automatic) */
     RTRI_OPT_LEAF_F32 = 2,   /* leaf size for FP32 (16, 32, 64, 128 or 256; 0 = automatic) */
-    RTRI_OPT_GEMM_TILE = 3   /* GEMM tile choice: 0 = automatic, 1 = 128x128, 2 = 64x64 */
+    RTRI_OPT_GEMM_TILE = 3   /* GEMM tile choice: 0 = automatic, 1 = 128x128 (4 wavefronts), 2 = 64x64,
+                                3 = 128x128 (8 wavefronts) */
 };
 
 typedef struct rtri_handle rtri_handle;

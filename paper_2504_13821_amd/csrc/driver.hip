@@ -472,7 +472,7 @@ int rtri_set_option(rtri_handle *h, int option, int64_t value)
         h->leaf_f32 = (int)value;
         return RTRI_OK;
     case RTRI_OPT_GEMM_TILE:
-        if (value < 0 || value > 2) return -3;
+        if (value < 0 || value > 3) return -3;
         h->gemm_tile = (int)value;
         return RTRI_OK;
     default:

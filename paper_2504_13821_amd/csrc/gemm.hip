@@ -24,9 +24,13 @@ namespace {
 
 using namespace gk;
 
-// Workgroup tile BM x BN; wavefront tile (BM/2) x (BN/2) made of FM x FN MFMA blocks.
-template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC>
-__global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmDesc g, int tiles_m, int tiles_n)
+// Workgroup tile BM x BN; WM x WN wavefronts, each a (BM/WM) x (BN/WN) block
+// made of 16 x 16 MFMA blocks.
+// Two workgroups per CU: 2 wavefronts per SIMD with 4-wavefront tiles, 4 with
+// 8-wavefront tiles (at most 128 registers each).
+template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(WM * WN / 2))) void
+gemm_kernel(GemmDesc g, int tiles_m, int tiles_n)
 {
     constexpr bool KCA = TP, KCB = !TQ;
     __shared__ __attribute__((aligned(16))) T As[2 * lds_elems<T, BM, KCA>()];
@@ -48,35 +52,36 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmDesc g, int tiles_m, in
     const int in_band = bid - band * GROUP * tiles_n;
     const int tm = first_m + in_band % gsize;
     const int tn = in_band / gsize;
-    gemm_tile<T, BM, BN, TP, TQ, VEC>(g, (int64_t)tm * BM, (int64_t)tn * BN, As, Bs);
+    gemm_tile<T, BM, BN, TP, TQ, VEC, WM, WN>(g, (int64_t)tm * BM, (int64_t)tn * BN, As, Bs);
 }
 
-template <typename T, int BM, int BN, bool TP, bool TQ>
+template <typename T, int BM, int BN, int WM, int WN, bool TP, bool TQ>
 hipError_t launch_t(const GemmDesc &g, bool vec, hipStream_t st)
 {
     const int tm = (int)((g.M + BM - 1) / BM), tn = (int)((g.N + BN - 1) / BN);
-    const dim3 grid((unsigned)(tm * tn));
+    const dim3 grid((unsigned)(tm * tn)), block(64 * WM * WN);
     if (vec)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TP, TQ, true>), grid, dim3(NT), 0, st, g, tm, tn);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TP, TQ, true, WM, WN>), grid, block, 0, st, g, tm, tn);
     else
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TP, TQ, false>), grid, dim3(NT), 0, st, g, tm, tn);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TP, TQ, false, WM, WN>), grid, block, 0, st, g, tm, tn);
     return hipGetLastError();
 }
 
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, int WM = 2, int WN = 2>
 hipError_t launch_tile(const GemmDesc &g, bool vec, hipStream_t st)
 {
-    if (!g.tp && !g.tq) return launch_t<T, BM, BN, false, false>(g, vec, st);
-    if (g.tp && !g.tq) return launch_t<T, BM, BN, true, false>(g, vec, st);
-    if (!g.tp && g.tq) return launch_t<T, BM, BN, false, true>(g, vec, st);
-    return launch_t<T, BM, BN, true, true>(g, vec, st);
+    if (!g.tp && !g.tq) return launch_t<T, BM, BN, WM, WN, false, false>(g, vec, st);
+    if (g.tp && !g.tq) return launch_t<T, BM, BN, WM, WN, true, false>(g, vec, st);
+    if (!g.tp && g.tq) return launch_t<T, BM, BN, WM, WN, false, true>(g, vec, st);
+    return launch_t<T, BM, BN, WM, WN, true, true>(g, vec, st);
 }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 }  // namespace
 
-// tile: 1 = 128x128, 2 = 64x64, 0 = pick by problem size
+// tile: 1 = 128x128 (4 wavefronts), 2 = 64x64, 3 = 128x128 (8 wavefronts of
+// 64x32), 0 = pick by problem size
 hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st)
 {
     if (g.M <= 0 || g.N <= 0)
@@ -84,14 +89,19 @@ hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st)
     const int64_t w = t == DType::F64 ? 2 : 4;
     const bool vec = aligned16(g.P) && aligned16(g.Q) && g.ldp % w == 0 && g.ldq % w == 0;
     if (tile == 0) {
-        // 128x128 tiles once they fill the chip (2 workgroups on each of the
-        // 256 CUs) at least twice over; smaller problems run 64x64 tiles
+        // 128x128 tiles of 8 wavefronts (4 per SIMD with 2 workgroups per CU)
+        // once they fill the chip's 512 workgroup slots; smaller problems run
+        // 64x64 tiles (measured faster up to M = 256 at N = 16384)
         const int64_t big = ((g.M + 127) / 128) * ((g.N + 127) / 128);
-        tile = big >= 1024 ? 1 : 2;
+        tile = big >= 512 ? 3 : 2;
     }
     if (t == DType::F64)
-        return tile == 1 ? launch_tile<double, 128, 128>(g, vec, st) : launch_tile<double, 64, 64>(g, vec, st);
-    return tile == 1 ? launch_tile<float, 128, 128>(g, vec, st) : launch_tile<float, 64, 64>(g, vec, st);
+        return tile == 1   ? launch_tile<double, 128, 128>(g, vec, st)
+               : tile == 3 ? launch_tile<double, 128, 128, 2, 4>(g, vec, st)
+                           : launch_tile<double, 64, 64>(g, vec, st);
+    return tile == 1   ? launch_tile<float, 128, 128>(g, vec, st)
+           : tile == 3 ? launch_tile<float, 128, 128, 2, 4>(g, vec, st)
+                       : launch_tile<float, 64, 64>(g, vec, st);
 }
 
 }  // namespace rtri

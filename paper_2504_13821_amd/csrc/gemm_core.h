@@ -51,17 +51,17 @@ __device__ __forceinline__ T lds_at(const T *ls, int row, int k)
 // registers, then into LDS as Ls[row][k] (k contiguous, padded rows).
 //   KC = true : element (row, k) at base[k + row*ld]   (k contiguous in memory)
 //   KC = false: element (row, k) at base[row + k*ld]   (rows contiguous in memory)
-template <typename T, int R, bool KC, bool VEC>
+template <typename T, int R, bool KC, bool VEC, int NTH = NT>
 struct TileLoader {
     static constexpr int W = 16 / sizeof(T);               // elements per 16-byte load
-    static constexpr int PER = R * BK / NT;                 // elements per thread
+    static constexpr int PER = R * BK / NTH;                // elements per thread
     static constexpr int NV = PER / W;                      // 16-byte loads per thread
     static_assert(PER % W == 0, "tile too small");
     T reg[PER];
 
     __device__ inline void coords(int v, int tid, int &row, int &k) const
     {
-        const int e = v * NT + tid;                          // index of the W-vector
+        const int e = v * NTH + tid;                         // index of the W-vector
         if (KC) {
             k = (e % (BK / W)) * W;
             row = e / (BK / W);
@@ -127,20 +127,22 @@ struct TileLoader {
     }
 };
 
-// One BM x BN tile of C at (m0, n0), computed by the NT threads of the
-// workgroup.  As / Bs: two LDS slots each (lds_elems elements per slot).
-// Ends with a barrier, so the LDS slots may be reused right after it returns.
-template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC>
+// One BM x BN tile of C at (m0, n0), computed by the 64*WM*WN threads of the
+// workgroup, wavefronts in a WM x WN grid of (BM/WM) x (BN/WN) blocks.  As / Bs:
+// two LDS slots each (lds_elems elements per slot).  Ends with a barrier, so
+// the LDS slots may be reused right after it returns.
+template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC, int WM = 2, int WN = 2>
 __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t n0, T *As, T *Bs,
                                           int tid = threadIdx.x)
 {
-    constexpr int FM = BM / 32, FN = BN / 32;
+    constexpr int NTH = 64 * WM * WN;
+    constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
     constexpr bool KCA = TP, KCB = !TQ;           // operand layouts (see lds_at)
     constexpr int EA = lds_elems<T, BM, KCA>(), EB = lds_elems<T, BN, KCB>();
     using AccT = Acc<T>;
     using V = typename AccT::V;
     const int wave = tid / 64, lane = tid % 64;
-    const int wm = wave & 1, wn = wave >> 1;
+    const int wm = wave % WM, wn = wave / WM;
     const int lc = lane % 16, lg = lane / 16;
 
     const T *P = static_cast<const T *>(g.P);
@@ -153,8 +155,8 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
     const int rlim_n = (int)min<int64_t>(BN, g.N - n0);
     const bool full_mn = rlim_m == BM && rlim_n == BN;
 
-    TileLoader<T, BM, TP, VEC> la;
-    TileLoader<T, BN, !TQ, VEC> lb;
+    TileLoader<T, BM, TP, VEC, NTH> la;
+    TileLoader<T, BN, !TQ, VEC, NTH> lb;
 
     V acc[FM][FN];
 #pragma unroll
@@ -194,7 +196,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
 
         // fragments: lane (lc, lg) reads row (block*16 + lc), k = 4*lg .. 4*lg+3,
         // two k values at a time (one 16-byte read for FP64)
-        const int ra = wm * (BM / 2) + lc, rbq = wn * (BN / 2) + lc;
+        const int ra = wm * (BM / WM) + lc, rbq = wn * (BN / WN) + lc;
 #pragma unroll
         for (int t2 = 0; t2 < 4; t2 += 2) {
             T fa[FM][2], fb[FN][2];
@@ -232,8 +234,8 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int rb = wm * (BM / 2) + i * 16;              // local row of the block
-            const int cl = wn * (BN / 2) + j * 16 + lc;        // local column
+            const int rb = wm * (BM / WM) + i * 16;             // local row of the block
+            const int cl = wn * (BN / WN) + j * 16 + lc;       // local column
             if (cl >= rlim_n)
                 continue;
             T *cp = C + (m0 + rb) + (n0 + cl) * ldc;

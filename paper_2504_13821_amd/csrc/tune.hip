@@ -177,7 +177,7 @@ bool parse_db(const std::string &text, TuneDB &db)
         for (const JVal &e : tr->second.arr) {
             TuneDB::Tile r{dtype_of(str_of(e, "dtype", ok)), (int64_t)num_of(e, "m_max", ok),
                            (int64_t)num_of(e, "n_max", ok), (int)num_of(e, "tile", ok)};
-            if (r.dtype < 0 || (r.tile != 1 && r.tile != 2))
+            if (r.dtype < 0 || r.tile < 1 || r.tile > 3)
                 ok = false;
             db.tile.push_back(r);
         }
@@ -414,7 +414,7 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
                 continue;
             int best = 1;
             float best_ms = 1e30f;
-            for (int tile : {1, 2}) {
+            for (int tile : {1, 2, 3}) {
                 h->gemm_tile = tile;
                 int rr = RTRI_OK;
                 const float ms = time_median(

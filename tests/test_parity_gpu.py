@@ -45,7 +45,7 @@ GEMM_SHAPES = [(1, 1, 1), (37, 50, 19), (64, 64, 16), (128, 128, 16), (200, 300,
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 @pytest.mark.parametrize("tp,tq", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
 @pytest.mark.parametrize("shape", GEMM_SHAPES)
-@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_gemm_update(rt, h, orc, dt, tp, tq, shape, tile):
     M, N, K = shape
     say("gemm", dt, tp, tq, shape, tile)
