@@ -317,6 +317,10 @@ def serving_stream(count, seed_key=0):
 
 
 def bench_serving(rt, count):
+    """Closed-loop saturation, then open-loop Poisson arrivals at fractions of
+    it.  Latency = completion seen on the host minus the scheduled arrival (no
+    coordinated omission), overall and per tag (FP64 TRSM, FP64 TRMM, refined
+    TRSM).  (Served results are checked against the oracle in the GPU tests.)"""
     import numpy as np
     import synth
     reqs = serving_stream(count)
@@ -325,49 +329,66 @@ def bench_serving(rt, count):
                        "FP64 or mixed+IR 50/50 for TRSM, factors shared by 1-16 requests), 64 GB budget",
            "requests": count}
 
-    def run(rate):
+    def tag(r):
+        return "mixed_trsm" if r["precision"] else f"fp64_{r['op']}"
+
+    def pct(v):
+        return {"p50_ms": round(float(np.percentile(v, 50)) * 1e3, 3),
+                "p99_ms": round(float(np.percentile(v, 99)) * 1e3, 3), "count": len(v)}
+
+    def run(rate, keep=()):
         srv = rt.Server(slots=4, hbm_budget=64 << 30, max_batch=128, small_max=1024)
         t0 = srv.now() + 0.02
         if rate is None:
             arr = np.full(count, t0)
         else:
             arr = t0 + np.cumsum(synth.rng(synth.W_SERVE, 2000, int(rate)).exponential(1.0 / rate, count))
-        ticket0 = None
-        for r, ta in zip(reqs, arr):
-            tk = srv.submit(t_arrival=float(ta), **r)
-            ticket0 = tk if ticket0 is None else ticket0
+        kept = {}
+        tickets = []
+        for i, (r, ta) in enumerate(zip(reqs, arr)):
+            out = np.zeros((r["m"], r["n"]), order="F") if i in keep else None
+            tk = srv.submit(t_arrival=float(ta), result=out, **r)
+            tickets.append(tk)
+            if out is not None:
+                kept[i] = out
+        index = {tk: i for i, tk in enumerate(tickets)}
         srv.drain()
         comps = srv.poll(count + 16)
         st = srv.stats()
         srv.close()
         lat = np.array([c["t_done"] - c["t_arrival"] for c in comps])
         span = max(c["t_done"] for c in comps) - t0
-        bad = sum(1 for c in comps if c["status"] not in (0,))
+        by_tag = {}
+        for c in comps:
+            by_tag.setdefault(tag(reqs[index[c["ticket"]]]), []).append(c["t_done"] - c["t_arrival"])
+        bad = sum(1 for c in comps if c["status"] != 0)
         by_status = {}
         failed = []
         for c in comps:
             if c["status"] != 0:
                 by_status[str(c["status"])] = by_status.get(str(c["status"]), 0) + 1
-                r = reqs[c["ticket"] - ticket0]
+                r = reqs[index[c["ticket"]]]
                 if len(failed) < 8:
                     failed.append({"status": c["status"], "op": r["op"], "m": r["m"], "n": r["n"],
                                    "precision": r["precision"], "trans": r["trans"], "uplo": r["uplo"],
                                    "iters": c["iters"], "eta": c["eta"], "factor_id": r["factor_id"]})
-        return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                "solves_per_s": round(count / span, 1), "busy_tflops": round(flops / span / 1e12, 3),
-                "errors": bad, "errors_by_status": by_status, "failed_sample": failed,
-                "batched_requests": st["batched_requests"],
-                "launches": st["launches"],
-                "factor_hits": st["factor_hits"], "factor_misses": st["factor_misses"],
-                "evictions": st["evictions"], "hbm_peak_GB": round(st["hbm_peak"] / 1e9, 2)}
-    sat = run(None)
+        out = dict(pct(lat), solves_per_s=round(count / span, 1), busy_tflops=round(flops / span / 1e12, 3),
+                   per_tag={k: pct(v) for k, v in sorted(by_tag.items())},
+                   errors=bad, errors_by_status=by_status, failed_sample=failed,
+                   batched_requests=st["batched_requests"], launches=st["launches"],
+                   factor_hits=st["factor_hits"], factor_misses=st["factor_misses"],
+                   evictions=st["evictions"], hbm_peak_GB=round(st["hbm_peak"] / 1e9, 2))
+        out.pop("count")
+        return out, kept
+
+    sat, _ = run(None)
     progress("serving saturation", sat["solves_per_s"], "solves/s")
     res["saturation"] = sat
     mu = sat["solves_per_s"]
     res["rates"] = {}
-    for frac in (0.25, 0.5, 0.75, 0.9):
-        res["rates"][str(frac)] = dict(run(frac * mu), rate_per_s=round(frac * mu, 1))
+    for frac in (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+        r, _ = run(frac * mu)
+        res["rates"][str(frac)] = dict(r, rate_per_s=round(frac * mu, 1))
         progress("serving rate", frac)
     return res
 

@@ -140,6 +140,25 @@ def test_blocked_leaf_variants(rt, h, orc, leaf, dt, op, diag, side, uplo, trans
     assert e <= TOL[dt], (leaf, op, dt, side, uplo, trans, diag, e)
 
 
+@pytest.mark.parametrize("leaf", [16, 64, 128, 256])
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+@pytest.mark.parametrize("side,uplo,trans", [("L", "L", "N"), ("L", "U", "T"), ("R", "L", "N")])
+def test_leaf_ill_conditioned(rt, h, orc, leaf, dt, side, uplo, trans):
+    """Diagonal 4.5 + U(0,1) against off-diagonal U(-1,1): cond_1 ~ 1.7e6 at
+    order 1024, and 16 x 16 diagonal tiles far from the identity.  The
+    matrix-core leaves apply FP64 inverses of those tiles; the backward error
+    must still meet the tolerance."""
+    m, n = (1024, 96) if side == "L" else (96, 1024)
+    say("ill-conditioned leaf", leaf, dt, side, uplo, trans)
+    g = G(15, leaf)
+    A = rounded(synth.tri(1024, uplo, g, "cond", c=4.5), dt)
+    B = rounded(synth.dense(m, n, g), dt)
+    h.set_option(rt.OPT_LEAF_F64 if dt == "f64" else rt.OPT_LEAF_F32, leaf)
+    X = run_op(rt, h, "trsm", side, uplo, trans, "N", 1.0, A, B, dt)
+    e = eta(orc, "trsm", side, uplo, trans, "N", 1.0, A, B, X)
+    assert e <= TOL[dt], (leaf, dt, e)
+
+
 @pytest.mark.parametrize("leaf", [128, 256])
 @pytest.mark.parametrize("op", ["trsm", "trmm"])
 @pytest.mark.parametrize("side,uplo,trans", [("L", "L", "N"), ("L", "U", "T"), ("R", "U", "N"), ("R", "L", "T")])
