@@ -72,45 +72,11 @@ __device__ __forceinline__ void run_mleaf(const BInst &in, const BOp &op, int v0
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));   // see run_gemm
     const int d0 = op.a0, h = op.a1;
-    T *Ls = smem;                        // canonical block, ascending stream order
-    T *Lt = smem + lk::tri_n<NB>();      // the 10 tiles in A-operand order
+    // the chunk's panel first (lane = vector, MFMA accumulator layout), so its
+    // loads are in flight while the block is staged
+    using AccT = mk::Acc<T>;
     const bool mtrans = in.left ? in.tr != 0 : in.tr == 0;
     const bool mlower = in.left ? in.low != 0 : in.low == 0;
-    lk::stage_block<sizeof(T) == 8 ? ElemT::F64 : ElemT::F32, T, NB, true, NT>(
-        in.A, (int64_t)d0 + (int64_t)d0 * in.lda, in.lda, h, mtrans, mlower, in.unit != 0, Ls, tid);
-    __syncthreads();
-    auto canon = [&](int i, int k) { return Ls[lk::colstart<NB, true>(k) + (i - k)]; };
-    if (tid < NBK * mk::RB) {
-        const int j = tid / mk::RB, k = tid % mk::RB;
-        double y[mk::RB];
-        mk::diag_column<SOLVE>(
-            k, [&](int m, int q) { return (double)canon(mk::RB * j + m, mk::RB * j + q); }, y);
-#pragma unroll
-        for (int m = 0; m < mk::RB; ++m)
-            Dg[(j * mk::RB + m) * (mk::RB + 1) + k] = y[m];
-    }
-    __syncthreads();
-    for (int e = tid; e < mk::ntiles<NB>() * mk::TE; e += NT) {
-        const int tile = e / mk::TE;
-        int m, kk;
-        mk::tile_entry<T>(e % mk::TE, m, kk);
-        int j = 0;
-        while (j + 1 < NBK && mk::cb_tile(NBK, j + 1) <= tile)
-            ++j;
-        const int i = j + (tile - mk::cb_tile(NBK, j));
-        T v;
-        if (i == j) {
-            v = (T)Dg[(j * mk::RB + m) * (mk::RB + 1) + kk];
-        } else {
-            v = canon(mk::RB * i + m, mk::RB * j + kk);
-            if (SOLVE)
-                v = -v;
-        }
-        Lt[e] = v;
-    }
-    __syncthreads();
-
-    using AccT = mk::Acc<T>;
     const int lane = tid % 64;
     const int w = __builtin_amdgcn_readfirstlane(tid / 64);
     const int c = lane % 16, g = lane / 16;
@@ -139,6 +105,42 @@ __device__ __forceinline__ void run_mleaf(const BInst &in, const BOp &op, int v0
             const int dm = mlower ? row : h - 1 - row;
             acc[i][r] = (act && row < h) ? Bv[(int64_t)dm * sd] : T(0);
         }
+    T *Ls = smem;                        // canonical block, ascending stream order
+    T *Lt = smem + lk::tri_n<NB>();      // the 10 tiles in A-operand order
+    lk::stage_block<sizeof(T) == 8 ? ElemT::F64 : ElemT::F32, T, NB, true, NT>(
+        in.A, (int64_t)d0 + (int64_t)d0 * in.lda, in.lda, h, mtrans, mlower, in.unit != 0, Ls, tid);
+    __syncthreads();
+    auto canon = [&](int i, int k) { return Ls[lk::colstart<NB, true>(k) + (i - k)]; };
+    if (tid < NBK * mk::RB) {
+        const int j = tid / mk::RB, k = tid % mk::RB;
+        double y[mk::RB];
+        mk::diag_column<SOLVE>(
+            k, [&](int m, int q) { return (double)canon(mk::RB * j + m, mk::RB * j + q); }, y);
+#pragma unroll
+        for (int m = 0; m < mk::RB; ++m)
+            Dg[(j * mk::RB + m) * (mk::RB + 1) + k] = y[m];
+    }
+    __syncthreads();
+    // a tile has NT = 256 entries: thread tid writes entry tid of every tile
+    static_assert(mk::TE == NT, "one tile entry per thread");
+    int m, kk;
+    mk::tile_entry<T>(tid, m, kk);
+#pragma unroll
+    for (int j = 0, tile = 0; j < NBK; ++j)
+#pragma unroll
+        for (int i = j; i < NBK; ++i, ++tile) {
+            T v;
+            if (i == j) {
+                v = (T)Dg[(j * mk::RB + m) * (mk::RB + 1) + kk];
+            } else {
+                v = canon(mk::RB * i + m, mk::RB * j + kk);
+                if (SOLVE)
+                    v = -v;
+            }
+            Lt[tile * mk::TE + tid] = v;
+        }
+    __syncthreads();
+
     const T alpha = T(op.use_alpha ? in.alpha : 1.0);
     if (SOLVE)
 #pragma unroll
