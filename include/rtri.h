@@ -70,8 +70,10 @@ enum {
 
 /* Tunable options (rtri_set_option / rtri_get_option). */
 enum {
-    RTRI_OPT_LEAF_F64 = 1,   /* leaf size for FP64 (16, 32, 64, 128 or 256; 0 = automatic) */
-    RTRI_OPT_LEAF_F32 = 2,   /* leaf size for FP32 (16, 32, 64, 128 or 256; 0 = automatic) */
+    RTRI_OPT_LEAF_F64 = 1,   /* leaf size for FP64 (16, 32, 64, 128 or 256; 0 = automatic).
+                                16 and 32: substitution leaves; 64 and up: matrix-core leaves
+                                that apply FP64 inverses of their 16 x 16 diagonal tiles */
+    RTRI_OPT_LEAF_F32 = 2,   /* leaf size for FP32 (same values) */
     RTRI_OPT_GEMM_TILE = 3   /* GEMM tile choice: 0 = automatic, 1 = 128x128 (4 wavefronts), 2 = 64x64,
                                 3 = 128x128 (8 wavefronts) */
 };
@@ -258,8 +260,11 @@ typedef struct rtri_batch_plan rtri_batch_plan;
 
 /* Build a reusable plan for `count` problems of one element type (dtype
  * RTRI_F64 or RTRI_F32): every problem's recursion is laid out as an op list
- * (the same splits, leaf size and order as the single-call path, so each
- * result is bitwise the one rtri_?trsm / rtri_?trmm would give), its
+ * (the splits and order of the single-call path with 64-row leaves, or 32-row
+ * leaves when the handle would pick a leaf of at most 32 for an order-1024,
+ * 64-vector problem (option or tuning rule); each result
+ * is then bitwise what rtri_?trsm / rtri_?trmm give with the same leaf size,
+ * which is their untuned choice for factor orders up to 1024), its
  * independent right-hand-side vectors are cut into chunks of 64, and the
  * chunks are queued longest first.  The plan owns device copies of these
  * tables and a captured hipGraph of the launch (a queue reset and one

@@ -1,5 +1,7 @@
-// Leaf kernels: triangular solve / multiply of one diagonal block against a
-// panel of independent vectors (paper, Sec. 3.3).
+// Substitution leaf kernels (diagonal blocks of 16 or 32 rows): triangular
+// solve / multiply of one diagonal block against a panel of independent vectors
+// (paper, Sec. 3.3).  Blocks of 64 rows and more run on the matrix cores
+// (mleaf.hip); launch_pack / launch_leaf dispatch by block size.
 //
 // The paper's base TRSM gives each thread a row of one right-hand-side column
 // and synchronises after every row.  On CDNA4 a wavefront is 64 lanes wide and
