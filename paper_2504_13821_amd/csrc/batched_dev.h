@@ -101,7 +101,7 @@ __device__ __forceinline__ void run_mleaf(const BInst &in, const BOp &op, int v0
     for (int i = 0; i < NBK; ++i)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = mk::RB * i + AccT::row(g, r);
+            const int row = mk::RB * i + 4 * g + r;
             const int dm = mlower ? row : h - 1 - row;
             acc[i][r] = (act && row < h) ? Bv[(int64_t)dm * sd] : T(0);
         }
@@ -125,19 +125,21 @@ __device__ __forceinline__ void run_mleaf(const BInst &in, const BOp &op, int v0
     static_assert(mk::TE == NT, "one tile entry per thread");
     int m, kk;
     mk::tile_entry<T>(tid, m, kk);
+    m = mk::lrow<T>(m);
+    kk = mk::lrow<T>(kk);
 #pragma unroll
-    for (int j = 0, tile = 0; j < NBK; ++j)
+    for (int p = 0; p < NBK; ++p)
 #pragma unroll
-        for (int i = j; i < NBK; ++i, ++tile) {
+        for (int k = 0; k <= p; ++k) {
             T v;
-            if (i == j) {
-                v = (T)Dg[(j * mk::RB + m) * (mk::RB + 1) + kk];
+            if (k == p) {
+                v = (T)Dg[(p * mk::RB + m) * (mk::RB + 1) + kk];
             } else {
-                v = canon(mk::RB * i + m, mk::RB * j + kk);
+                v = canon(mk::RB * p + m, mk::RB * k + kk);
                 if (SOLVE)
                     v = -v;
             }
-            Lt[tile * mk::TE + tid] = v;
+            Lt[mk::rb_tile(p, k) * mk::TE + tid] = v;
         }
     __syncthreads();
 
@@ -146,26 +148,20 @@ __device__ __forceinline__ void run_mleaf(const BInst &in, const BOp &op, int v0
 #pragma unroll
         for (int i = 0; i < NBK; ++i)
             acc[i] *= alpha;
-    mk::leaf_phases<T, NB, SOLVE>(
-        acc, lane,
-        [&](int s, int ti) -> const T * {
-            const int j = SOLVE ? s : NBK - 1 - s;
-            return Lt + (mk::cb_tile(NBK, j) + ti) * mk::TE;
+    mk::leaf_rows<T, NB, SOLVE>(
+        acc, lane, [&](int p, int k) -> const T * { return Lt + mk::rb_tile(p, k) * mk::TE; }, [](int) {},
+        [&](int p, typename AccT::V x) {
+            if (!SOLVE)
+                x *= alpha;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = mk::RB * p + 4 * g + r;
+                const int dm = mlower ? row : h - 1 - row;
+                if (act && row < h)
+                    Bv[(int64_t)dm * sd] = x[r];
+            }
         },
-        [](int) {});
-    if (!SOLVE)
-#pragma unroll
-        for (int i = 0; i < NBK; ++i)
-            acc[i] *= alpha;
-#pragma unroll
-    for (int i = 0; i < NBK; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = mk::RB * i + AccT::row(g, r);
-            const int dm = mlower ? row : h - 1 - row;
-            if (act && row < h)
-                Bv[(int64_t)dm * sd] = acc[i][r];
-        }
+        [](auto, auto) {});
     __syncthreads();
 }
 

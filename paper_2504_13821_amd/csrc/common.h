@@ -68,7 +68,7 @@ struct LeafDesc {
 
 inline int64_t tri_elems(int nb) { return (int64_t)nb * (nb + 1) / 2; }
 // Leaves of 64, 128 and 256 rows read a tiled packed form instead (see
-// mleaf.hip): the 16 x 16 tiles of the lower triangle, column block by column
+// mleaf.hip): the 16 x 16 tiles of the lower triangle, row block by row
 // block.
 inline int64_t bpack_elems(int nbmax) { return (int64_t)128 * (nbmax / 16) * (nbmax / 16 + 1); }
 inline int64_t pack_elems(int nbmax) { return nbmax <= 32 ? tri_elems(nbmax) : bpack_elems(nbmax); }
@@ -87,6 +87,11 @@ hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStr
 // matrix-core leaves (nbmax = 64, 128 or 256, mleaf.hip), called by launch_pack / launch_leaf
 hipError_t launch_bpack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_bleaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);
+// the leaf variants behind launch_bleaf, one translation unit each
+hipError_t mleaf_launch_f64_solve(int nbmax, const LeafDesc &l, hipStream_t st);
+hipError_t mleaf_launch_f64_mult(int nbmax, const LeafDesc &l, hipStream_t st);
+hipError_t mleaf_launch_f32_solve(int nbmax, const LeafDesc &l, hipStream_t st);
+hipError_t mleaf_launch_f32_mult(int nbmax, const LeafDesc &l, hipStream_t st);
 hipError_t launch_fill(DType t, void *B, int64_t m, int64_t n, int64_t ldb, double value, hipStream_t st);
 
 // ---- element-wise kernels (HBM-bound) ----

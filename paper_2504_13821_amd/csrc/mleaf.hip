@@ -12,26 +12,31 @@
 // Layout.  A workgroup of 4 wavefronts takes 64 vectors; wavefront w owns
 // vectors 16w .. 16w+15 for all NB rows, as NB/16 accumulator tiles of 16
 // rows x 16 vectors (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).  Lane
-// (c, g) = (lane % 16, lane / 16) holds vector c, rows Acc::row(g, r) of a
+// (c, g) = (lane % 16, lane / 16) holds vector c, tile rows Acc::row(g, r) of a
 // tile in slot r.  For K slice t an MFMA reads B[k = g][c] from lane (c, g);
-// slot t of a tile holds exactly the rows {Acc::row(g, t)}, so a tile is the B
-// operand of the next MFMA as it stands, with K index g of slice t labelled by
-// row Acc::row(g, t).  The A operand (16 x 16 triangle tile M) then carries
-// M[m][Acc::row(g, t)] in lane (m, g) for slice t; the pack pass writes every
-// tile in that order.  No data moves between lanes, and the four wavefronts
-// never wait on each other.
+// slot t of a tile holds exactly the tile rows {Acc::row(g, t)}, so a tile is
+// the B operand of the next MFMA as it stands, with K index g of slice t
+// labelled by tile row Acc::row(g, t).  The A operand (16 x 16 triangle tile
+// M) then carries M[m][Acc::row(g, t)] in lane (m, g) for slice t; the pack
+// pass writes every tile in that order.  Tile rows are a relabelling of the
+// block's rows (mk::lrow) under which slot r of group g is block row 4g + r,
+// so a lane's slots are consecutive rows of its vector.  No data moves between
+// lanes, and the four wavefronts never wait on each other's results.
 //
-// Solve, row blocks j ascending:  X_j = inv(T_jj) B_j;  B_i += (-L_ij) X_j, i > j.
-// Multiply, j descending:         B_i += L_ij B_j (i > j);  B_j = T_jj B_j.
-// inv(T_jj) is the exact-arithmetic inverse of the 16 x 16 diagonal tile,
+// Phases, one row block p of 16 rows each, ascending (mk::leaf_rows):
+//   solve:     X_p = inv(T_pp) (B_p - sum_{k<p} L_pk X_k)
+//   multiply:  B_p := T_pp B_p + sum_{k<p} L_pk B_k   (from the original B)
+// inv(T_pp) is the exact-arithmetic inverse of the 16 x 16 diagonal tile,
 // formed in FP64 by substitution in the pack pass and rounded once to the
 // panel type; applying it as a product instead of 16 dependent divisions is
 // the one difference from a substitution leaf (its error is bounded by
-// cond(T_jj) u instead of a small multiple of u; the diagonal tiles of a
-// triangle with a dominant diagonal have cond(T_jj) close to 1).
-//
-// The packed triangle streams through a three-slot LDS ring one column block
-// (16 columns, tiles j..NB/16-1) at a time, two phases ahead of its use.
+// cond(T_pp) u instead of a small multiple of u; the diagonal tiles of a
+// triangle with a dominant diagonal have cond(T_pp) close to 1).  Row block p
+// needs only the panel's row blocks 0..p, so the panel streams in behind the
+// first phases and each finished row block is stored while later ones are
+// computed; the packed triangle streams through LDS, its tiles numbered row
+// block by row block (mk::rb_tile).  The kernel and its memory schedule are in
+// mleaf_kernel.h; this file holds the pack pass and the dispatch.
 #include "leaf_core.h"
 #include "mleaf_core.h"
 
@@ -42,7 +47,6 @@ namespace {
 using lk::ld_src;
 using mk::RB;
 using mk::TE;
-using mk::cb_tile;
 using mk::tile_pos;
 
 // Canonical block element L(i, k), i >= k, rounded to T (identity past nb and
@@ -59,7 +63,8 @@ __device__ __forceinline__ T canon(const PackDesc &p, int64_t base, int nb, int 
     return (T)ld_src<S>(p.A, base + (p.mtrans ? c + (int64_t)r * p.lda : r + (int64_t)c * p.lda));
 }
 
-// One workgroup per diagonal block: every tile in A-operand order.
+// One workgroup per diagonal block: every tile in A-operand order, tiles
+// numbered by row block (mk::rb_tile).
 //   solve:    diagonal tiles inv(T_jj), off-diagonal tiles -L_ij
 //   multiply: diagonal tiles T_jj,      off-diagonal tiles  L_ij
 template <ElemT S, typename T, int NB, bool SOLVE>
@@ -91,135 +96,18 @@ __global__ __launch_bounds__(256) void mpack_kernel(PackDesc p)
         const int tile = e / TE;
         int m, kk;
         mk::tile_entry<T>(e % TE, m, kk);
-        int j = 0;
-        while (j + 1 < NBK && cb_tile(NBK, j + 1) <= tile)
-            ++j;
-        const int i = j + (tile - cb_tile(NBK, j));
+        const int i = mk::tile_row(tile), j = tile - mk::rb_tile(i, 0);
+        const int bm = mk::lrow<T>(m), bk = mk::lrow<T>(kk);
         T v;
         if (i == j) {
-            v = (T)Dg[j][m][kk];
+            v = (T)Dg[j][bm][bk];
         } else {
-            v = canon<S, T>(p, base, nb, RB * i + m, RB * j + kk);
+            v = canon<S, T>(p, base, nb, RB * i + bm, RB * j + bk);
             if (SOLVE)
                 v = -v;
         }
         out[e] = v;
     }
-}
-
-template <typename T> struct Vec16;
-template <> struct Vec16<double> { using V = double __attribute__((ext_vector_type(2))); };
-template <> struct Vec16<float> { using V = float __attribute__((ext_vector_type(4))); };
-
-template <typename T, int NB, bool SOLVE>
-__global__ __launch_bounds__(256, 1) void mleaf_kernel(LeafDesc d, const T *__restrict__ Lp, T *__restrict__ B)
-{
-    constexpr int NBK = NB / RB;
-    constexpr int SLOT = NBK * TE;                // elements of the largest column block
-    constexpr int W = 16 / (int)sizeof(T);
-    constexpr int NV = SLOT / (256 * W);          // 16-byte loads per thread per column block
-    static_assert(NV * 256 * W == SLOT, "column block split");
-    using V = typename Vec16<T>::V;
-    using AccT = mk::Acc<T>;
-    using A4 = typename AccT::V;
-
-    __shared__ __attribute__((aligned(16))) T Lr[3 * SLOT];
-
-    const int tid = threadIdx.x, lane = tid % 64;
-    const int w = __builtin_amdgcn_readfirstlane(tid / 64);
-    const int c = lane % 16, g = lane / 16;
-    const int64_t vec = (int64_t)blockIdx.x * 64 + 16 * w + c;
-    const bool act = vec < d.nvec;
-    const int nb = d.nb;
-    T *Bv = B + vec * d.si;
-
-    auto cbk = [](int s) { return SOLVE ? s : NBK - 1 - s; };
-    V pre0[NV], pre1[NV];
-    auto gload = [&](int s, V(&dst)[NV]) {
-        const int cc = cbk(s);
-        const int cnt = (NBK - cc) * TE;
-        const T *src = Lp + (int64_t)cb_tile(NBK, cc) * TE;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int e = (v * 256 + tid) * W;
-            if (e < cnt)
-                dst[v] = *reinterpret_cast<const V *>(src + e);
-        }
-    };
-    auto lstore = [&](int s, const V(&src)[NV]) {
-        const int cc = cbk(s);
-        const int cnt = (NBK - cc) * TE;
-        T *dst = Lr + (s % 3) * SLOT;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const int e = (v * 256 + tid) * W;
-            if (e < cnt)
-                *reinterpret_cast<V *>(dst + e) = src[v];
-        }
-    };
-
-    gload(0, pre0);
-    if (NBK > 1)
-        gload(1, pre1);
-
-    A4 acc[NBK];
-#pragma unroll
-    for (int i = 0; i < NBK; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = RB * i + AccT::row(g, r);
-            const int dm = d.mlower ? row : nb - 1 - row;
-            acc[i][r] = (act && row < nb) ? Bv[(int64_t)dm * d.sd] : T(0);
-        }
-    const T alpha = T(d.alpha);
-    if (SOLVE)
-#pragma unroll
-        for (int i = 0; i < NBK; ++i)
-            acc[i] *= alpha;
-
-    lstore(0, pre0);
-    if (NBK > 1)
-        lstore(1, pre1);
-    if (NBK > 2)
-        gload(2, pre0);
-    __syncthreads();
-
-    mk::leaf_phases<T, NB, SOLVE>(
-        acc, lane, [&](int s, int ti) -> const T * { return Lr + (s % 3) * SLOT + ti * TE; },
-        [&](int s) {
-            if (s + 2 < NBK)
-                lstore(s + 2, pre0);
-            if (s + 3 < NBK)
-                gload(s + 3, pre0);
-            __syncthreads();
-        });
-
-    if (!SOLVE)
-#pragma unroll
-        for (int i = 0; i < NBK; ++i)
-            acc[i] *= alpha;
-#pragma unroll
-    for (int i = 0; i < NBK; ++i)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = RB * i + AccT::row(g, r);
-            const int dm = d.mlower ? row : nb - 1 - row;
-            if (act && row < nb)
-                Bv[(int64_t)dm * d.sd] = acc[i][r];
-        }
-}
-
-template <typename T, int NB>
-hipError_t mleaf_nb(bool solve, const LeafDesc &l, hipStream_t st)
-{
-    const dim3 grid((unsigned)((l.nvec + 63) / 64));
-    const T *L = static_cast<const T *>(l.Lp);
-    T *B = static_cast<T *>(l.B);
-    if (solve)
-        hipLaunchKernelGGL((mleaf_kernel<T, NB, true>), grid, dim3(256), 0, st, l, L, B);
-    else
-        hipLaunchKernelGGL((mleaf_kernel<T, NB, false>), grid, dim3(256), 0, st, l, L, B);
-    return hipGetLastError();
 }
 
 template <ElemT S, typename T, int NB>
@@ -275,20 +163,9 @@ hipError_t launch_bleaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipSt
         return hipSuccess;
     if (l.nb > nbmax)
         return hipErrorInvalidValue;
-    if (t == DType::F64) {
-        switch (nbmax) {
-        case 64: return mleaf_nb<double, 64>(solve, l, st);
-        case 128: return mleaf_nb<double, 128>(solve, l, st);
-        case 256: return mleaf_nb<double, 256>(solve, l, st);
-        default: return hipErrorInvalidValue;
-        }
-    }
-    switch (nbmax) {
-    case 64: return mleaf_nb<float, 64>(solve, l, st);
-    case 128: return mleaf_nb<float, 128>(solve, l, st);
-    case 256: return mleaf_nb<float, 256>(solve, l, st);
-    default: return hipErrorInvalidValue;
-    }
+    if (t == DType::F64)
+        return solve ? mleaf_launch_f64_solve(nbmax, l, st) : mleaf_launch_f64_mult(nbmax, l, st);
+    return solve ? mleaf_launch_f32_solve(nbmax, l, st) : mleaf_launch_f32_mult(nbmax, l, st);
 }
 
 }  // namespace rtri

@@ -3,6 +3,8 @@
 // operations in the same order.
 #pragma once
 
+#include <type_traits>
+
 #include "gemm_core.h"
 
 namespace rtri {
@@ -10,12 +12,47 @@ namespace mk {
 
 using gk::Acc;
 
+// f(std::integral_constant<int, i>) for i = B .. E-1, in order: the index is a
+// constant in every call whatever the unroller decides
+template <int B, int E, class F> __device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
 constexpr int RB = 16;    // rows / columns of a tile
 constexpr int TE = 256;   // elements of a tile
 
-// first tile of column block c (tiles c..nbk-1 of that block follow in order)
-__host__ __device__ constexpr int cb_tile(int nbk, int c) { return c * nbk - c * (c - 1) / 2; }
+// 16 bytes of T
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using V = double __attribute__((ext_vector_type(2))); };
+template <> struct Vec16<float> { using V = float __attribute__((ext_vector_type(4))); };
+
+// Tiles are numbered by row block: tile (p, k), k <= p, of row block p is
+// number p (p + 1) / 2 + k (k == p: the diagonal tile).
+__host__ __device__ constexpr int rb_tile(int p, int k) { return p * (p + 1) / 2 + k; }
 template <int NB> __host__ __device__ constexpr int ntiles() { return (NB / RB) * (NB / RB + 1) / 2; }
+// row block of tile t
+__host__ __device__ constexpr int tile_row(int t)
+{
+    int p = 0;
+    while (rb_tile(p + 1, 0) <= t)
+        ++p;
+    return p;
+}
+
+// Rows inside a 16-row block are relabelled: tile row tau holds block row
+// lrow(tau).  Slot r of lane group g of an accumulator tile is tile row
+// Acc::row(g, r), so with this labelling it holds block row 4g + r for both
+// element types: a lane's four slots are four consecutive rows of its vector,
+// which side-L panels read and write with 16-byte accesses.  Triangle tiles
+// carry the same labelling on both indices, so the products are unchanged.
+template <typename T> __host__ __device__ constexpr int lrow(int tau)
+{
+    return sizeof(T) == 8 ? 4 * (tau % 4) + tau / 4 : tau;
+}
 
 // element (K slice t, lane) of a tile in A-operand order: 16-byte groups of W
 // slices per lane
@@ -24,7 +61,8 @@ template <typename T> __host__ __device__ constexpr int tile_pos(int t, int lane
     constexpr int W = 16 / (int)sizeof(T);
     return ((t / W) * 64 + lane) * W + t % W;
 }
-// inverse of tile_pos: the tile entry M[m][kk] that position pos holds
+// inverse of tile_pos: the tile entry M[m][kk] (tile rows / columns) that
+// position pos holds
 template <typename T> __device__ __forceinline__ void tile_entry(int pos, int &m, int &kk)
 {
     constexpr int W = 16 / (int)sizeof(T);
@@ -62,46 +100,66 @@ template <bool SOLVE, class TV> __device__ __forceinline__ void diag_column(int 
     }
 }
 
-// D = M * X + C for the tile M (A-operand order) at Mt; X in accumulator
-// layout serves as the B operand, K index g of slice t labelled by row
-// Acc::row(g, t)
-template <typename T>
-__device__ __forceinline__ typename Acc<T>::V tile_mm(const T *Mt, int lane, const typename Acc<T>::V &X,
-                                                      typename Acc<T>::V C)
-{
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-        C = Acc<T>::mfma(Mt[tile_pos<T>(t, lane)], X[t], C);
-    return C;
-}
-
 // The phases of one leaf over the accumulator tiles acc[0..NB/16) of a
-// wavefront.  tile(s, ti) returns the LDS address of tile ti (0 = diagonal) of
-// the column block used in phase s; sync(s) runs after phase s (s < NBK - 1).
-//   solve, blocks ascending:   X_j = inv(T_jj) B_j;  B_i += (-L_ij) X_j  (i > j)
-//   multiply, descending:      B_i += L_ij B_j  (i > j);  B_j = T_jj B_j
-template <typename T, int NB, bool SOLVE, class Tile, class Sync>
-__device__ __forceinline__ void leaf_phases(typename Acc<T>::V (&acc)[NB / RB], int lane, Tile &&tile, Sync &&sync)
+// wavefront, one row block of 16 rows per phase, ascending.  tile(p, k)
+// returns the LDS address of tile (p, k); sync(P) runs before phase p (P: p as
+// a std::integral_constant); done(P, R) receives row block p of the result;
+// mid(P, S) runs after MFMA s of phase p (S: s as an integral constant), so a
+// caller can thread other work between the matrix instructions.
+//   solve:     X_p = inv(T_pp) (B_p + sum_{k<p} (-L_pk) X_k), k ascending;
+//              acc[p] becomes X_p
+//   multiply:  R_p = T_pp B_p + sum_{k<p} L_pk B_k, k descending; acc keeps B
+// Each result entry sees the same operations in the same order as in the
+// column-oriented forms (solve: B_i += (-L_ij) X_j, j ascending, then
+// X_i = inv(T_ii) B_i; multiply: B_i = T_ii B_i, then B_i += L_ij B_j, j
+// descending), so the two agree bit for bit.  Row block p needs only B_0..B_p,
+// so the panel can stream in while the first phases run, and each finished
+// row block can be stored while the later ones are computed.
+template <typename T, int NB, bool SOLVE, class Tile, class Sync, class Done, class Mid>
+__device__ __forceinline__ void leaf_rows(typename Acc<T>::V (&acc)[NB / RB], int lane, Tile &&tile, Sync &&sync,
+                                          Done &&done, Mid &&mid)
 {
     constexpr int NBK = NB / RB;
     using A4 = typename Acc<T>::V;
+    static_for<0, NBK>([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        sync(P);
+        // C + M X for the tile M (A-operand order) at Mt, one MFMA per K slice t;
+        // X in accumulator layout serves as the B operand, K index g of slice t
+        // labelled by tile row Acc::row(g, t).  S0: index of the first MFMA in the phase.
+        auto mm = [&](const T *Mt, const A4 &X, A4 C, auto S0) {
+            constexpr int W = 16 / (int)sizeof(T);
+            T a[4];   // the lane's four A operands, read as 16-byte groups
+            static_for<0, 4 / W>([&](auto J) {
+                const auto v = *reinterpret_cast<const typename Vec16<T>::V *>(
+                    Mt + tile_pos<T>(W * decltype(J)::value, lane));
 #pragma unroll
-    for (int s = 0; s < NBK; ++s) {
-        const int j = SOLVE ? s : NBK - 1 - s;
-        if (SOLVE) {
-            acc[j] = tile_mm<T>(tile(s, 0), lane, acc[j], A4{0, 0, 0, 0});
-#pragma unroll
-            for (int i = j + 1; i < NBK; ++i)
-                acc[i] = tile_mm<T>(tile(s, i - j), lane, acc[j], acc[i]);
+                for (int e = 0; e < W; ++e)
+                    a[W * decltype(J)::value + e] = v[e];
+            });
+            static_for<0, 4>([&](auto Tt) {
+                constexpr int t = decltype(Tt)::value;
+                C = Acc<T>::mfma(a[t], X[t], C);
+                mid(P, std::integral_constant<int, decltype(S0)::value + t>{});
+            });
+            return C;
+        };
+        if constexpr (SOLVE) {
+            static_for<0, p>([&](auto Kk) {
+                constexpr int k = decltype(Kk)::value;
+                acc[p] = mm(tile(p, k), acc[k], acc[p], std::integral_constant<int, 4 * k>{});
+            });
+            acc[p] = mm(tile(p, p), acc[p], A4{0, 0, 0, 0}, std::integral_constant<int, 4 * p>{});
+            done(P, acc[p]);
         } else {
-#pragma unroll
-            for (int i = j + 1; i < NBK; ++i)
-                acc[i] = tile_mm<T>(tile(s, i - j), lane, acc[j], acc[i]);
-            acc[j] = tile_mm<T>(tile(s, 0), lane, acc[j], A4{0, 0, 0, 0});
+            A4 r = mm(tile(p, p), acc[p], A4{0, 0, 0, 0}, std::integral_constant<int, 0>{});
+            static_for<0, p>([&](auto Jj) {
+                constexpr int k = p - 1 - decltype(Jj)::value;
+                r = mm(tile(p, k), acc[k], r, std::integral_constant<int, 4 * (p - k)>{});
+            });
+            done(P, r);
         }
-        if (s + 1 < NBK)
-            sync(s);
-    }
+    });
 }
 
 }  // namespace mk

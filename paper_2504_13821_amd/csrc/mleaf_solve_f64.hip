@@ -1,0 +1,11 @@
+// Matrix-core leaf, solve in F64 (kernel in mleaf_kernel.h).
+#include "mleaf_kernel.h"
+
+namespace rtri {
+
+hipError_t mleaf_launch_f64_solve(int nbmax, const LeafDesc &l, hipStream_t st)
+{
+    return mleaf::launch<double, true>(nbmax, l, st);
+}
+
+}  // namespace rtri

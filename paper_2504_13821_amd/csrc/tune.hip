@@ -334,7 +334,6 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
     if (max_order < 256)
         return -3;
     const size_t es = dtype == RTRI_F64 ? 8 : 4;
-    const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
     const int64_t max_n = std::min<int64_t>(max_order, 16384);
     void *A = nullptr, *B = nullptr, *C = nullptr;
     hipError_t e = hipMalloc(&A, (size_t)max_order * max_order * es);
