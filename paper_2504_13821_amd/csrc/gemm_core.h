@@ -30,6 +30,36 @@ template <> struct Acc<float> {
     static __device__ inline int row(int g, int r) { return 4 * g + r; }
 };
 
+// Rows inside a 16-row block are relabelled: the row that the MFMA calls m
+// (tile row) is block row lrow(m).  Slot r of lane group g holds tile row
+// Acc::row(g, r), hence block row 4g + r for both element types: a lane's four
+// slots are four consecutive rows, which column-major data moves with 16-byte
+// accesses.  Only the lane that supplies (or receives) a row changes, not the
+// arithmetic of any entry.
+template <typename T> __host__ __device__ constexpr int lrow(int m)
+{
+    return sizeof(T) == 8 ? 4 * (m % 4) + m / 4 : m;
+}
+
+// 16 bytes of T, and four consecutive elements from 16-byte aligned addresses
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using V = double __attribute__((ext_vector_type(2))); };
+template <> struct Vec16<float> { using V = float __attribute__((ext_vector_type(4))); };
+__device__ __forceinline__ double4_t ld4(const double *p)
+{
+    const auto *q = reinterpret_cast<const Vec16<double>::V *>(p);
+    const auto a = q[0], b = q[1];
+    return double4_t{a.x, a.y, b.x, b.y};
+}
+__device__ __forceinline__ float4_t ld4(const float *p) { return *reinterpret_cast<const float4_t *>(p); }
+__device__ __forceinline__ void st4(double *p, double4_t v)
+{
+    auto *q = reinterpret_cast<Vec16<double>::V *>(p);
+    q[0] = Vec16<double>::V{v.x, v.y};
+    q[1] = Vec16<double>::V{v.z, v.w};
+}
+__device__ __forceinline__ void st4(float *p, float4_t v) { *reinterpret_cast<float4_t *>(p) = v; }
+
 // LDS layout of an operand tile (R rows of M or N, BK along K) follows its
 // layout in global memory, so the global -> LDS copy never transposes:
 //   KC (k contiguous in memory):    Ls[row * SK + k],  SK = BK + pad
@@ -194,9 +224,10 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
         if (kt + 1 < nk)
             load_step(kt + 1);
 
-        // fragments: lane (lc, lg) reads row (block*16 + lc), k = 4*lg .. 4*lg+3,
-        // two k values at a time (one 16-byte read for FP64)
-        const int ra = wm * (BM / WM) + lc, rbq = wn * (BN / WN) + lc;
+        // fragments: lane (lc, lg) reads row (block*16 + lrow(lc)) of op(P), row
+        // (block*16 + lc) of op(Q)^T, k = 4*lg .. 4*lg+3, two k values at a time
+        // (one 16-byte read for FP64)
+        const int ra = wm * (BM / WM) + lrow<T>(lc), rbq = wn * (BN / WN) + lc;
 #pragma unroll
         for (int t2 = 0; t2 < 4; t2 += 2) {
             T fa[FM][2], fb[FN][2];
@@ -226,25 +257,38 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
         __syncthreads();
     }
 
-    // epilogue: slot r of lane (lc, lg) holds row AccT::row(lg, r), column lc of every 16x16 block
+    // epilogue: slot r of lane (lc, lg) holds row 4*lg + r, column lc of every
+    // 16x16 block; C moves as one or two 16-byte accesses per lane and block when
+    // aligned, else element by element (the same arithmetic either way)
     T *C = static_cast<T *>(g.C);
     const int64_t ldc = g.ldc;
     const T beta = T(g.beta), s = T(g.s);
+    const bool cvec = reinterpret_cast<uintptr_t>(C) % 16 == 0 && (ldc * (int64_t)sizeof(T)) % 16 == 0;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int rb = wm * (BM / WM) + i * 16;             // local row of the block
+            const int r0 = wm * (BM / WM) + i * 16 + 4 * lg;    // local row of slot 0
             const int cl = wn * (BN / WN) + j * 16 + lc;       // local column
             if (cl >= rlim_n)
                 continue;
-            T *cp = C + (m0 + rb) + (n0 + cl) * ldc;
+            T *cp = C + (m0 + r0) + (n0 + cl) * ldc;
+            if (cvec && r0 + 4 <= rlim_m) {
+                V v = s * acc[i][j];
+                if (g.beta != 0.0) {
+                    const V c = ld4(cp);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int rr = AccT::row(lg, r);
-                if (rb + rr < rlim_m) {
-                    const T v = s * acc[i][j][r];
-                    cp[rr] = (g.beta == 0.0) ? v : fmat(beta, cp[rr], v);
+                    for (int r = 0; r < 4; ++r)
+                        v[r] = fmat(beta, c[r], v[r]);
+                }
+                st4(cp, v);
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (r0 + r < rlim_m) {
+                        const T v = s * acc[i][j][r];
+                        cp[r] = (g.beta == 0.0) ? v : fmat(beta, cp[r], v);
+                    }
                 }
             }
         }

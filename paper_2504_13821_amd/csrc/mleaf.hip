@@ -63,61 +63,54 @@ __device__ __forceinline__ T canon(const PackDesc &p, int64_t base, int nb, int 
     return (T)ld_src<S>(p.A, base + (p.mtrans ? c + (int64_t)r * p.lda : r + (int64_t)c * p.lda));
 }
 
-// One workgroup per diagonal block: every tile in A-operand order, tiles
-// numbered by row block (mk::rb_tile).
-//   solve:    diagonal tiles inv(T_jj), off-diagonal tiles -L_ij
-//   multiply: diagonal tiles T_jj,      off-diagonal tiles  L_ij
+// One workgroup per row block i (blockIdx.y) of a diagonal block
+// (blockIdx.x): the tiles (i, 0..i) in A-operand order, tiles numbered by row
+// block (mk::rb_tile).
+//   solve:    diagonal tile inv(T_ii), off-diagonal tiles -L_ij
+//   multiply: diagonal tile T_ii,      off-diagonal tiles  L_ij
 template <ElemT S, typename T, int NB, bool SOLVE>
 __global__ __launch_bounds__(256) void mpack_kernel(PackDesc p)
 {
-    constexpr int NBK = NB / RB;
-    constexpr int NTILE = NBK * (NBK + 1) / 2;
-    __shared__ double Dg[NBK][RB][RB + 1];    // diagonal tiles (inverted for a solve), FP64
+    constexpr int NTILE = mk::ntiles<NB>();
+    static_assert(TE == 256, "one tile entry per thread");
+    __shared__ double Dg[RB][RB + 1];    // the diagonal tile (inverted for a solve), FP64
+    const int i = blockIdx.y;
     const int64_t d0 = (int64_t)blockIdx.x * NB;
     const int nb = (int)min<int64_t>(NB, p.ka - d0);
     const int64_t base = d0 + d0 * p.lda;
-    T *out = static_cast<T *>(p.out) + (int64_t)blockIdx.x * NTILE * TE;
+    T *out = static_cast<T *>(p.out) + ((int64_t)blockIdx.x * NTILE + mk::rb_tile(i, 0)) * TE;
     const int tid = threadIdx.x;
 
-    // thread (j, k): column k of diagonal tile j, inverted by forward
+    // thread k < 16: column k of the diagonal tile, inverted by forward
     // substitution for a solve (values rounded to T first, FP64 arithmetic)
-    if (tid < NBK * RB) {
-        const int j = tid / RB, k = tid % RB;
+    if (tid < RB) {
         double y[RB];
         mk::diag_column<SOLVE>(
-            k, [&](int m, int q) { return (double)canon<S, T>(p, base, nb, RB * j + m, RB * j + q); }, y);
+            tid, [&](int m, int q) { return (double)canon<S, T>(p, base, nb, RB * i + m, RB * i + q); }, y);
 #pragma unroll
         for (int m = 0; m < RB; ++m)
-            Dg[j][m][k] = y[m];
+            Dg[m][tid] = y[m];
+    }
+    // the off-diagonal entries of this thread (tile entry tid of each tile) meanwhile
+    int m, kk;
+    mk::tile_entry<T>(tid, m, kk);
+    const int bm = mk::lrow<T>(m), bk = mk::lrow<T>(kk);
+    for (int j = 0; j < i; ++j) {
+        T v = canon<S, T>(p, base, nb, RB * i + bm, RB * j + bk);
+        out[j * TE + tid] = SOLVE ? -v : v;
     }
     __syncthreads();
-
-    for (int e = tid; e < NTILE * TE; e += 256) {
-        const int tile = e / TE;
-        int m, kk;
-        mk::tile_entry<T>(e % TE, m, kk);
-        const int i = mk::tile_row(tile), j = tile - mk::rb_tile(i, 0);
-        const int bm = mk::lrow<T>(m), bk = mk::lrow<T>(kk);
-        T v;
-        if (i == j) {
-            v = (T)Dg[j][bm][bk];
-        } else {
-            v = canon<S, T>(p, base, nb, RB * i + bm, RB * j + bk);
-            if (SOLVE)
-                v = -v;
-        }
-        out[e] = v;
-    }
+    out[i * TE + tid] = (T)Dg[bm][bk];
 }
 
 template <ElemT S, typename T, int NB>
 void mpack_nb(bool solve, const PackDesc &p, hipStream_t st)
 {
-    const unsigned nblk = (unsigned)((p.ka + NB - 1) / NB);
+    const dim3 grid((unsigned)((p.ka + NB - 1) / NB), NB / RB);
     if (solve)
-        hipLaunchKernelGGL((mpack_kernel<S, T, NB, true>), dim3(nblk), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((mpack_kernel<S, T, NB, true>), grid, dim3(256), 0, st, p);
     else
-        hipLaunchKernelGGL((mpack_kernel<S, T, NB, false>), dim3(nblk), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((mpack_kernel<S, T, NB, false>), grid, dim3(256), 0, st, p);
 }
 
 template <ElemT S, typename T>

@@ -25,10 +25,7 @@ template <int B, int E, class F> __device__ __forceinline__ void static_for(F &&
 constexpr int RB = 16;    // rows / columns of a tile
 constexpr int TE = 256;   // elements of a tile
 
-// 16 bytes of T
-template <typename T> struct Vec16;
-template <> struct Vec16<double> { using V = double __attribute__((ext_vector_type(2))); };
-template <> struct Vec16<float> { using V = float __attribute__((ext_vector_type(4))); };
+using gk::Vec16;
 
 // Tiles are numbered by row block: tile (p, k), k <= p, of row block p is
 // number p (p + 1) / 2 + k (k == p: the diagonal tile).
@@ -43,16 +40,11 @@ __host__ __device__ constexpr int tile_row(int t)
     return p;
 }
 
-// Rows inside a 16-row block are relabelled: tile row tau holds block row
-// lrow(tau).  Slot r of lane group g of an accumulator tile is tile row
-// Acc::row(g, r), so with this labelling it holds block row 4g + r for both
-// element types: a lane's four slots are four consecutive rows of its vector,
-// which side-L panels read and write with 16-byte accesses.  Triangle tiles
-// carry the same labelling on both indices, so the products are unchanged.
-template <typename T> __host__ __device__ constexpr int lrow(int tau)
-{
-    return sizeof(T) == 8 ? 4 * (tau % 4) + tau / 4 : tau;
-}
+// Block rows are relabelled as in the GEMM (gk::lrow): slot r of lane group g
+// of an accumulator tile holds block row 4g + r, so side-L panels move with
+// 16-byte accesses.  Triangle tiles carry the same labelling on both indices,
+// so the products are unchanged.
+using gk::lrow;
 
 // element (K slice t, lane) of a tile in A-operand order: 16-byte groups of W
 // slices per lane

@@ -13,21 +13,8 @@ using mk::RB;
 using mk::TE;
 using mk::Vec16;
 
-// four consecutive elements (16-byte aligned pairs / quads)
-__device__ __forceinline__ double4_t ld4(const double *p)
-{
-    const auto *q = reinterpret_cast<const Vec16<double>::V *>(p);
-    const auto a = q[0], b = q[1];
-    return double4_t{a.x, a.y, b.x, b.y};
-}
-__device__ __forceinline__ float4_t ld4(const float *p) { return *reinterpret_cast<const float4_t *>(p); }
-__device__ __forceinline__ void st4(double *p, double4_t v)
-{
-    auto *q = reinterpret_cast<Vec16<double>::V *>(p);
-    q[0] = Vec16<double>::V{v.x, v.y};
-    q[1] = Vec16<double>::V{v.z, v.w};
-}
-__device__ __forceinline__ void st4(float *p, float4_t v) { *reinterpret_cast<float4_t *>(p) = v; }
+using gk::ld4;
+using gk::st4;
 
 // Memory schedule.  The packed triangle reaches LDS in rounds of one 16-byte
 // load per thread (512 FP64 / 1024 FP32 consecutive packed elements, 2 or 4
