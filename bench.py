@@ -422,10 +422,23 @@ def cpu_baseline(rt, torch, h, A, B0, B0d, Ad, Bd, m, n):
            "trmm": oracle.trmm_eta("L", "L", "N", "N", 1.0, A, Bs, Cg),
            "trsm_max_abs_diff_vs_oracle": float(np.max(np.abs(Xg - Xo))),
            "columns": int(ns)}
+    # one core, a whole small problem: FP64 TRSM L/L/N/N at m = n = 1024
+    g1 = synth.rng(synth.W_SWEEP, 1024, 0)
+    A1 = synth.tri(1024, "L", g1, "base", fill=0.0)
+    B1 = synth.dense(1024, 1024, g1)
+    oracle.set_threads(1)
+    try:
+        t3 = time.perf_counter()
+        oracle.trsm("L", "L", "N", "N", 1.0, A1, B1)
+        t4 = time.perf_counter()
+    finally:
+        oracle.set_threads(threads)
     base = {"value": round(rate, 6), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{ns} seeded columns of the m=n={m} FP64 TRSM and TRMM (same A), "
                       f"{t2 - t0:.1f} s of CPU time, scaled to TFLOP/s with m^2 flops per column",
-            "seconds": round(t2 - t0, 2)}
+            "seconds": round(t2 - t0, 2),
+            "one_core_trsm_1024": {"seconds": round(t4 - t3, 3),
+                                   "gflops": round(1024.0 ** 3 / (t4 - t3) / 1e9, 3)}}
     return base, eta
 
 

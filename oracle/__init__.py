@@ -66,6 +66,8 @@ def lib():
             f.restype = ctypes.c_double
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -190,3 +192,8 @@ def cond_one(uplo, diag, A) -> float:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Thread count of later oracle calls (timing only: results do not depend on it)."""
+    lib().oracle_set_threads(int(n))

@@ -390,6 +390,17 @@ double oracle_trmm_eta(int side, int uplo, int trans, int diag, int64_t m, int64
     return worst;
 }
 
+/* set the number of OpenMP threads for later calls (no effect without OpenMP) */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* number of OpenMP threads the oracle runs with (1 if built without OpenMP) */
 int oracle_num_threads(void)
 {
