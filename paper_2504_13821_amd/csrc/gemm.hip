@@ -52,7 +52,9 @@ gemm_kernel(GemmDesc g, int tiles_m, int tiles_n)
     const int in_band = bid - band * GROUP * tiles_n;
     const int tm = first_m + in_band % gsize;
     const int tn = in_band / gsize;
-    gemm_tile<T, BM, BN, TP, TQ, VEC, WM, WN>(g, (int64_t)tm * BM, (int64_t)tn * BN, As, Bs);
+    // the 64x64 tile serves the short-K updates: FP64 reads C during the K loop
+    gemm_tile<T, BM, BN, TP, TQ, VEC, WM, WN, BM == 64 && sizeof(T) == 8>(g, (int64_t)tm * BM, (int64_t)tn * BN,
+                                                                           As, Bs);
 }
 
 template <typename T, int BM, int BN, int WM, int WN, bool TP, bool TQ>

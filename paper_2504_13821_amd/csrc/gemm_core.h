@@ -161,7 +161,11 @@ struct TileLoader {
 // workgroup, wavefronts in a WM x WN grid of (BM/WM) x (BN/WN) blocks.  As / Bs:
 // two LDS slots each (lds_elems elements per slot).  Ends with a barrier, so
 // the LDS slots may be reused right after it returns.
-template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC, int WM = 2, int WN = 2>
+// CPF: read C during the K loop (one accumulator block per k-step, right after
+// that step's operand loads) instead of in the epilogue, for short K where the
+// epilogue's reads would otherwise follow all the MFMA work (FP64: the FP32
+// k-step is too short to cover the read, measured slower there).
+template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC, int WM = 2, int WN = 2, bool CPF = false>
 __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t n0, T *As, T *Bs,
                                           int tid = threadIdx.x)
 {
@@ -198,6 +202,17 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
     const int64_t K = g.K;
     const int nk = (int)((K + BK - 1) / BK);
 
+    // C block (i, j) of this lane: rows 4*lg .. 4*lg+3 of its 16-row block
+    T *C = static_cast<T *>(g.C);
+    const int64_t ldc = g.ldc;
+    const bool cvec = reinterpret_cast<uintptr_t>(C) % 16 == 0 && (ldc * (int64_t)sizeof(T)) % 16 == 0;
+    auto cptr = [&](int i, int j, int wm_, int wn_, int lc_, int lg_) {
+        return C + (m0 + wm_ * (BM / WM) + i * 16 + 4 * lg_) + (n0 + wn_ * (BN / WN) + j * 16 + lc_) * ldc;
+    };
+    // prefetched C blocks: block t = i * FN + j is requested during k-step t
+    const bool pre = CPF && cvec && full_mn && g.beta != 0.0 && nk > FM * FN;
+    V cpre[CPF ? FM : 1][CPF ? FN : 1];
+
     auto load_step = [&](int kt) {
         const int64_t k0 = (int64_t)kt * BK;
         const T *pa = TP ? Pt + k0 : Pt + k0 * ldp;
@@ -223,6 +238,12 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
         const int cur = kt & 1;
         if (kt + 1 < nk)
             load_step(kt + 1);
+        if (CPF && pre) {
+#pragma unroll
+            for (int t = 0; t < FM * FN; ++t)
+                if (kt == t)
+                    cpre[CPF ? t / FN : 0][CPF ? t % FN : 0] = ld4(cptr(t / FN, t % FN, wm, wn, lc, lg));
+        }
 
         // fragments: lane (lc, lg) reads row (block*16 + lrow(lc)) of op(P), row
         // (block*16 + lc) of op(Q)^T, k = 4*lg .. 4*lg+3, two k values at a time
@@ -251,32 +272,43 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
         }
 
         if (kt + 1 < nk) {
-            la.store(As + (cur ^ 1) * EA, tid);
-            lb.store(Bs + (cur ^ 1) * EB, tid);
+            int ts = tid;
+            // The FP64 8-wavefront tile with both operands transposed sits one
+            // register over its 128-register budget: there, recompute the LDS
+            // offsets each step from an opaque copy of the thread index instead
+            // of spilling one.  Elsewhere that recomputation costs more than it
+            // saves (measured 3% at 8192x16384x8192), so the offsets stay live.
+            if constexpr (sizeof(T) == 8 && WM * WN == 8 && TP && TQ)
+                asm volatile("" : "+v"(ts));
+            la.store(As + (cur ^ 1) * EA, ts);
+            lb.store(Bs + (cur ^ 1) * EB, ts);
         }
         __syncthreads();
     }
 
     // epilogue: slot r of lane (lc, lg) holds row 4*lg + r, column lc of every
     // 16x16 block; C moves as one or two 16-byte accesses per lane and block when
-    // aligned, else element by element (the same arithmetic either way)
-    T *C = static_cast<T *>(g.C);
-    const int64_t ldc = g.ldc;
+    // aligned, else element by element (the same arithmetic either way).  The
+    // lane's offsets are recomputed from an opaque copy of the thread index, so
+    // none of them is kept live (or spilled) across the K loop.
+    int te = tid;
+    asm volatile("" : "+v"(te));
+    const int lane_e = te % 64, wave_e = te / 64;
+    const int wm_e = wave_e % WM, wn_e = wave_e / WM, lc_e = lane_e % 16, lg_e = lane_e / 16;
     const T beta = T(g.beta), s = T(g.s);
-    const bool cvec = reinterpret_cast<uintptr_t>(C) % 16 == 0 && (ldc * (int64_t)sizeof(T)) % 16 == 0;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-            const int r0 = wm * (BM / WM) + i * 16 + 4 * lg;    // local row of slot 0
-            const int cl = wn * (BN / WN) + j * 16 + lc;       // local column
+            const int r0 = wm_e * (BM / WM) + i * 16 + 4 * lg_e;    // local row of slot 0
+            const int cl = wn_e * (BN / WN) + j * 16 + lc_e;       // local column
             if (cl >= rlim_n)
                 continue;
-            T *cp = C + (m0 + r0) + (n0 + cl) * ldc;
+            T *cp = cptr(i, j, wm_e, wn_e, lc_e, lg_e);
             if (cvec && r0 + 4 <= rlim_m) {
                 V v = s * acc[i][j];
                 if (g.beta != 0.0) {
-                    const V c = ld4(cp);
+                    const V c = (CPF && pre) ? cpre[CPF ? i : 0][CPF ? j : 0] : ld4(cp);
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         v[r] = fmat(beta, c[r], v[r]);

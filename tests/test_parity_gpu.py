@@ -221,6 +221,27 @@ def test_leading_dimension_padding(rt, h, orc, dt, side):
         assert eta(orc, op, side, "L", "N", "N", 0.5, A, B, X) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt,leaf", [("f64", 64), ("f64", 128), ("f64", 256), ("f32", 64), ("f32", 256)])
+@pytest.mark.parametrize("op", ["trsm", "trmm"])
+@pytest.mark.parametrize("uplo", "LU")
+@pytest.mark.parametrize("m", [600, 601])
+def test_vector_and_element_paths_agree(rt, h, orc, dt, leaf, op, uplo, m):
+    """Side L with ldb = m (16-byte panel and C accesses where the alignment
+    allows) and ldb = m + 1 (element by element, every vector misaligned):
+    the same arithmetic, so the results agree bit for bit, and both pass the
+    oracle's bound.  m = 600 ends in a ragged leaf of a multiple of 4 rows,
+    m = 601 in one that is not."""
+    n = 130
+    say("vec/elem", dt, leaf, op, uplo, m)
+    A, B = _inputs("L", uplo, "N", m, n, dt, G(16, m))
+    h.set_option(rt.OPT_LEAF_F64 if dt == "f64" else rt.OPT_LEAF_F32, leaf)
+    ld_vec = m + (-m) % 4
+    X1 = run_op(rt, h, op, "L", uplo, "N", "N", 0.75, A, B, dt, ldb=ld_vec)
+    X2 = run_op(rt, h, op, "L", uplo, "N", "N", 0.75, A, B, dt, ldb=ld_vec + 1)
+    assert np.array_equal(X1, X2), (dt, leaf, op, uplo, m)
+    assert eta(orc, op, "L", uplo, "N", "N", 0.75, A, B, X1) <= TOL[dt]
+
+
 @pytest.mark.parametrize("op", ["trsm", "trmm"])
 def test_alpha_zero_reads_nothing(rt, h, op):
     m, n = 70, 33
