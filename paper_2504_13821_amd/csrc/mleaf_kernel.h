@@ -19,12 +19,14 @@ using gk::st4;
 // Memory schedule.  The packed triangle reaches LDS in rounds of one 16-byte
 // load per thread (512 FP64 / 1024 FP32 consecutive packed elements, 2 or 4
 // tiles).  A short prologue loads the rounds of row blocks 0..K and panel
-// blocks 0..DB.  Every later round is fetched into registers during phase
-// need - 1 - D and written to LDS during phase need - 1 (need: the first row
-// block it holds); panel block q is requested during phase q - 1 - DB; row
-// block p of the result is stored during phase p + 1.  Tile t sits in LDS slot
-// t mod CAP; every write lands on a slot whose previous tile belongs to a row
-// block that all wavefronts have finished (checked at compile time).
+// blocks 0..DB.  Every later round is written to LDS during the even phase
+// before the barrier that precedes its row block (barriers stand before phase 0
+// and before every odd phase, so one barrier covers two row blocks) and
+// fetched into registers D phases before that; panel block q is requested
+// during phase q - 1 - DB; row block p of the result is stored during phase
+// p + 1.  Tile t sits in LDS slot t mod CAP; every write lands on a slot whose
+// previous tile belongs to a row block that all wavefronts finished before
+// the last barrier (checked at compile time).
 //
 // A wavefront issues in order, and a memory instruction that cannot issue
 // stalls it; with one wavefront per SIMD that idles the matrix core.  So the
@@ -54,8 +56,20 @@ template <typename T, int NB> struct LeafSched {
     static constexpr bool STREAM = K < NBK - 1;
     static constexpr int need(int u) { return mk::tile_row(u * TPR); }
     static constexpr bool pro(int u) { return need(u) <= K; }
-    static constexpr int wphase(int u) { return pro(u) ? -1 : need(u) - 1; }       // -1: prologue
-    static constexpr int fphase(int u) { return pro(u) ? -1 : need(u) - 1 - D; }
+    // a barrier before phase 0 and, when streaming, before every odd phase:
+    // rounds are written during even phases, for the next two row blocks
+    static constexpr bool barrier_at(int p) { return p == 0 || (STREAM && p % 2 == 1); }
+    static constexpr int wrow(int q) { return q % 2 == 1 ? q - 1 : q - 2; }        // write phase of row block q
+    static constexpr int wphase(int u) { return pro(u) ? -1 : wrow(need(u)); }     // -1: prologue
+    static constexpr int fphase(int u) { return pro(u) ? -1 : wrow(need(u)) - D; }
+    // the last barrier at or before phase w (every wavefront has finished the
+    // phases before it)
+    static constexpr int last_barrier(int w)
+    {
+        while (w > 0 && !barrier_at(w))
+            --w;
+        return w;
+    }
     static constexpr int bphase(int q) { return q - 1 - DB; }                     // < 0: prologue
 
     // operations of phase p, in issue order: fetches, the panel block, LDS
@@ -101,12 +115,20 @@ template <typename T, int NB> struct LeafSched {
                 if (pro(u)) {
                     if (t >= CAP)
                         return false;
-                } else if (t >= CAP && mk::tile_row(t - CAP) > wphase(u) - 1) {
-                    // slot still read by a wavefront in the current phase
+                } else if (t >= CAP && mk::tile_row(t - CAP) > last_barrier(wphase(u)) - 1) {
+                    // slot still read by a wavefront that has not passed the last barrier
                     return false;
                 }
                 if (!pro(u) && fphase(u) < 0)
                     return false;
+                if (!pro(u)) {
+                    // a barrier between the write and the first phase that reads it
+                    bool ok = false;
+                    for (int b = wphase(u) + 1; b <= need(u); ++b)
+                        ok = ok || barrier_at(b);
+                    if (!ok)
+                        return false;
+                }
             }
         return true;
     }
@@ -208,7 +230,7 @@ __global__ __launch_bounds__(256, 1) void mleaf_kernel(LeafDesc d, const T *__re
     mk::leaf_rows<T, NB, SOLVE>(
         acc, lane, [&](int p, int k) -> const T * { return Lr + (mk::rb_tile(p, k) % CAP) * TE; },
         [&](auto P) {
-            if constexpr (decltype(P)::value == 0 || S::STREAM)
+            if constexpr (S::barrier_at(decltype(P)::value))
                 __syncthreads();
             if (SOLVE)
                 acc[decltype(P)::value] *= alpha;
