@@ -189,6 +189,8 @@ def main():
         progress("batched done")
         out["serving"] = bench_serving(rt, args.serve_requests)
         progress("serving done")
+        out["vendor_context"] = bench_vendor(rt, torch, h, m)
+        progress("vendor context done")
     print(json.dumps(out), flush=True)
 
 
@@ -204,6 +206,111 @@ def _event_ms(torch, fn, prep=None, reps=3):
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
     return min(ts)
+
+
+class _RocBlas:
+    """rocBLAS trsm / trmm through its C API (context only: the paper compares
+    its recursive kernels against the vendor library on the same hardware)."""
+    SIDE_L, FILL_L, OP_N, DIAG_N = 141, 122, 111, 131
+
+    def __init__(self, torch):
+        import ctypes
+        self.ct = ctypes
+        self.lib = ctypes.CDLL(os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib", "librocblas.so"))
+        self.h = ctypes.c_void_p()
+        self._ok(self.lib.rocblas_create_handle(ctypes.byref(self.h)), "create_handle")
+        self._ok(self.lib.rocblas_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)),
+                 "set_stream")
+
+    def _ok(self, st, what):
+        if st != 0:
+            raise RuntimeError(f"rocblas_{what} returned {st}")
+
+    def trsm(self, A, B):
+        ct = self.ct
+        f64 = A.dtype.itemsize == 8
+        al = (ct.c_double if f64 else ct.c_float)(1.0)
+        fn = self.lib.rocblas_dtrsm if f64 else self.lib.rocblas_strsm
+        m, n = B.shape
+        self._ok(fn(self.h, self.SIDE_L, self.FILL_L, self.OP_N, self.DIAG_N, ct.c_int(m), ct.c_int(n), ct.byref(al),
+                    ct.c_void_p(A.data_ptr()), ct.c_int(A.stride(1)), ct.c_void_p(B.data_ptr()),
+                    ct.c_int(B.stride(1))), "trsm")
+
+    def trmm(self, A, B, C):
+        ct = self.ct
+        f64 = A.dtype.itemsize == 8
+        al = (ct.c_double if f64 else ct.c_float)(1.0)
+        fn = self.lib.rocblas_dtrmm if f64 else self.lib.rocblas_strmm
+        m, n = B.shape
+        self._ok(fn(self.h, self.SIDE_L, self.FILL_L, self.OP_N, self.DIAG_N, ct.c_int(m), ct.c_int(n), ct.byref(al),
+                    ct.c_void_p(A.data_ptr()), ct.c_int(A.stride(1)), ct.c_void_p(B.data_ptr()),
+                    ct.c_int(B.stride(1)), ct.c_void_p(C.data_ptr()), ct.c_int(C.stride(1))), "trmm")
+
+    def close(self):
+        self.lib.rocblas_destroy_handle(self.h)
+
+
+def bench_vendor(rt, torch, h, m):
+    """rocBLAS beside this library on the same device-drawn inputs, side=L
+    uplo=L trans=N diag=N, alpha = 1: FP64 at m = n = 16384, and the paper's
+    FP32 shapes (B m x 256 and m x m).  ratio = rocBLAS time / this library's time, the paper's
+    convention (above 1: this library is faster).  Context, not a target."""
+    import synth
+    try:
+        rb = _RocBlas(torch)
+    except (OSError, RuntimeError) as e:
+        return {"skipped": f"rocBLAS not usable: {e}"}
+    res = {"library": "rocBLAS (ROCm install)", "convention": "ratio = rocBLAS time / this library's time"}
+    try:
+        A = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
+        B0 = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
+        rt.synth_fill(h, 1, synth.SEED, synth.W_SWEEP, 1, A, param=float(m))
+        rt.synth_fill(h, 0, synth.SEED, synth.W_SWEEP, 2, B0)
+        B = B0.clone()
+        C = torch.empty_like(B0)
+        o_s = _event_ms(torch, lambda: rt.trsm(h, "L", "L", "N", "N", 1.0, A, B), lambda: B.copy_(B0), reps=2)
+        o_m = _event_ms(torch, lambda: rt.trmm(h, "L", "L", "N", "N", 1.0, A, B), lambda: B.copy_(B0), reps=2)
+        v_s = _event_ms(torch, lambda: rb.trsm(A, B), lambda: B.copy_(B0), reps=2)
+        v_m = _event_ms(torch, lambda: rb.trmm(A, B0, C), reps=2)
+        fl = float(m) ** 3
+        res["f64_square"] = {"m": m, "n": m,
+                             "trsm": {"ours_ms": round(o_s, 3), "rocblas_ms": round(v_s, 3),
+                                      "ours_tflops": round(fl / (o_s * 1e-3) / 1e12, 3),
+                                      "rocblas_tflops": round(fl / (v_s * 1e-3) / 1e12, 3),
+                                      "ratio": round(v_s / o_s, 3)},
+                             "trmm": {"ours_ms": round(o_m, 3), "rocblas_ms": round(v_m, 3),
+                                      "ours_tflops": round(fl / (o_m * 1e-3) / 1e12, 3),
+                                      "rocblas_tflops": round(fl / (v_m * 1e-3) / 1e12, 3),
+                                      "ratio": round(v_m / o_m, 3)}}
+        del A, B0, B, C
+        torch.cuda.empty_cache()
+        rows = []
+        for shape in ("rect256", "square"):
+            for mm in (1024, 2048, 4096, 8192, 16384):
+                n = 256 if shape == "rect256" else mm
+                A = torch.empty((mm, mm), dtype=torch.float32, device="cuda").t()
+                B0 = torch.empty((n, mm), dtype=torch.float32, device="cuda").t()
+                rt.synth_fill(h, 1, synth.SEED, synth.W_SWEEP, 3, A, param=float(mm))
+                rt.synth_fill(h, 0, synth.SEED, synth.W_SWEEP, 4, B0)
+                B = B0.clone()
+                C = torch.empty_like(B0)
+                reps = 5 if mm * mm * n < 1e12 else 2
+                o_s = _event_ms(torch, lambda: rt.trsm(h, "L", "L", "N", "N", 1.0, A, B), lambda: B.copy_(B0), reps)
+                o_m = _event_ms(torch, lambda: rt.trmm(h, "L", "L", "N", "N", 1.0, A, B), lambda: B.copy_(B0), reps)
+                v_s = _event_ms(torch, lambda: rb.trsm(A, B), lambda: B.copy_(B0), reps)
+                v_m = _event_ms(torch, lambda: rb.trmm(A, B0, C), reps=reps)
+                fl = mm * mm * n
+                rows.append({"shape": shape, "m": mm, "n": n,
+                             "trsm_ms": [round(o_s, 3), round(v_s, 3)], "trsm_ratio": round(v_s / o_s, 3),
+                             "trsm_tflops": [round(fl / (o_s * 1e-3) / 1e12, 2), round(fl / (v_s * 1e-3) / 1e12, 2)],
+                             "trmm_ms": [round(o_m, 3), round(v_m, 3)], "trmm_ratio": round(v_m / o_m, 3),
+                             "trmm_tflops": [round(fl / (o_m * 1e-3) / 1e12, 2), round(fl / (v_m * 1e-3) / 1e12, 2)]})
+                del A, B0, B, C
+                torch.cuda.empty_cache()
+        res["f32_paper_shapes"] = {"columns": "ms / tflops pairs are [this library, rocBLAS]", "rows": rows}
+    finally:
+        rb.close()
+    return res
 
 
 # diagonal offset c of the m = 8192 mixed-precision factor (diagonal c + U(0,1),

@@ -74,8 +74,12 @@ enum {
                                 16 and 32: substitution leaves; 64 and up: matrix-core leaves
                                 that apply FP64 inverses of their 16 x 16 diagonal tiles */
     RTRI_OPT_LEAF_F32 = 2,   /* leaf size for FP32 (same values) */
-    RTRI_OPT_GEMM_TILE = 3   /* GEMM tile choice: 0 = automatic, 1 = 128x128 (4 wavefronts), 2 = 64x64,
+    RTRI_OPT_GEMM_TILE = 3,  /* GEMM tile choice: 0 = automatic, 1 = 128x128 (4 wavefronts), 2 = 64x64,
                                 3 = 128x128 (8 wavefronts) */
+    RTRI_OPT_TRMM_LEAVES = 4 /* TRMM leaf schedule (leaves of 64 rows and more): 0 = automatic (all in one
+                                launch below 8192 vectors), 1 = one launch per leaf, in recursion order,
+                                2 = the panel is copied to workspace, all leaves run in one launch, then the
+                                GEMM updates read the copy.  Both give bit-identical results. */
 };
 
 typedef struct rtri_handle rtri_handle;

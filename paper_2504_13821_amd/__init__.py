@@ -36,7 +36,7 @@ NOTRANS, TRANS, CONJTRANS = 0, 1, 2
 NONUNIT, UNIT = 0, 1
 F64, F32, BF16, F16 = 0, 1, 2, 3
 OK, ERR_HANDLE, ERR_HIP, ERR_NOMEM, ERR_UNSUPPORTED, NOT_CONVERGED, ERR_INVALID = range(7)
-OPT_LEAF_F64, OPT_LEAF_F32, OPT_GEMM_TILE = 1, 2, 3
+OPT_LEAF_F64, OPT_LEAF_F32, OPT_GEMM_TILE, OPT_TRMM_LEAVES = 1, 2, 3, 4
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64

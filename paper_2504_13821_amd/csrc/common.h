@@ -64,6 +64,10 @@ struct LeafDesc {
     int64_t nvec;
     bool mlower, unit;
     double alpha;
+    // ka > 0: every diagonal block of an order-ka factor in one launch
+    // (matrix-core leaves only): block y covers elements [y nbmax, min((y+1)
+    // nbmax, ka)); Lp and B then address block 0 and nb is ignored
+    int64_t ka;
 };
 
 inline int64_t tri_elems(int nb) { return (int64_t)nb * (nb + 1) / 2; }

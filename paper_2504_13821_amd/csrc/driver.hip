@@ -58,10 +58,17 @@ struct Planner {
     bool low;       // op(A) lower
     bool forward;   // block 1 before block 2
     std::vector<Op> ops;
+    // where the GEMM updates of a TRMM read the original values of the other
+    // block: the panel itself (one launch per leaf), or a copy of it taken
+    // before all leaves run in one launch
+    const char *src = nullptr;
+    int64_t ldsrc = 0;
 
     explicit Planner(const PlanIn &pr) : p(pr)
     {
         es = p.bt == DType::F64 ? 8 : 4;
+        src = p.B;
+        ldsrc = p.ldb;
         low = (p.uplo == RTRI_LOWER) != (p.trans != RTRI_NOTRANS);
         const bool fwd_solve = p.side == RTRI_LEFT ? low : !low;
         forward = p.solve ? fwd_solve : !fwd_solve;
@@ -111,15 +118,15 @@ struct Planner {
             g.P = tri_block(p, t0, s0);
             g.ldp = p.ldag;
             g.tp = tr;
-            g.Q = p.B + s0 * (int64_t)es;
-            g.ldq = p.ldb;
+            g.Q = (p.solve ? p.B : src) + s0 * (int64_t)es;
+            g.ldq = p.solve ? p.ldb : ldsrc;
             g.tq = false;
             g.C = p.B + t0 * (int64_t)es;
         } else {
             g.M = p.m;
             g.N = th;
-            g.P = p.B + s0 * p.ldb * (int64_t)es;
-            g.ldp = p.ldb;
+            g.P = p.solve ? p.B + s0 * p.ldb * (int64_t)es : src + s0 * ldsrc * (int64_t)es;
+            g.ldp = p.solve ? p.ldb : ldsrc;
             g.tp = false;
             g.Q = tri_block(p, s0, t0);
             g.ldq = p.ldag;
@@ -265,6 +272,17 @@ int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nve
     return ka <= 1024 ? 64 : 256;
 }
 
+bool trmm_one_launch(const rtri_handle *h, int leaf, int64_t ka, int64_t nvec)
+{
+    if (leaf < 64 || ka <= leaf)   // matrix-core leaves; a single leaf has no schedule to choose
+        return false;
+    if (h->trmm_leaves != 0)
+        return h->trmm_leaves == 2;
+    // one launch per leaf fills the chip from 8192 vectors on (128 workgroups
+    // of 64 vectors); below that the leaves run on a few CUs one after another
+    return nvec < 8192;
+}
+
 int run_plan(rtri_handle *h, const PlanIn &p)
 {
     const int64_t ka = p.side == RTRI_LEFT ? p.m : p.n;
@@ -274,6 +292,18 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     const size_t es = bt == DType::F64 ? 8 : 4;
     const int pcode = bt == DType::F64 ? RTRI_F64 : RTRI_F32;
     Planner pl(p);
+    // TRMM with every leaf in one launch: the GEMM updates read the original
+    // panel from a copy (m x n, leading dimension m), so the leaves may all run
+    // first; every update sees the same operands as in recursion order
+    const int64_t nvec_all = p.side == RTRI_LEFT ? p.n : p.m;
+    const bool one = !p.solve && trmm_one_launch(h, p.leaf, ka, nvec_all);
+    if (one) {
+        hipError_t e0 = ensure_ws(h, WS_SAVE, (size_t)p.m * (size_t)p.n * es);
+        if (e0 != hipSuccess)
+            return hip_fail(h, e0);
+        pl.src = static_cast<const char *>(h->ws[WS_SAVE]);
+        pl.ldsrc = p.m;
+    }
     pl.rec(0, ka, p.alpha);
 
     // pack every diagonal block once into the canonical form the leaves read
@@ -307,8 +337,35 @@ int run_plan(rtri_handle *h, const PlanIn &p)
 
     const bool g16 = p.gt == ElemT::BF16 || p.gt == ElemT::F16;
     const size_t ges = elem_size(p.gt);
+    if (one) {
+        hipError_t e = timed(h, RTRI_KCLASS_OTHER, pcode, 0.0, 2.0 * es * p.m * p.n, [&] {
+            return hipMemcpy2DAsync(h->ws[WS_SAVE], p.m * es, p.B, p.ldb * es, p.m * es, p.n,
+                                    hipMemcpyDeviceToDevice, h->stream);
+        });
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        LeafDesc all{};
+        double fl = 0.0, by = 0.0;
+        for (const Op &op : pl.ops)
+            if (!op.gemm) {
+                if (all.nvec == 0) {
+                    all = op.l;
+                    all.B = p.B;   // block 0 starts at element 0 of the panel
+                    all.Lp = h->ws[p.pack_slot];
+                    all.nb = p.leaf;
+                    all.ka = ka;
+                }
+                fl += leaf_flops(op.l);
+                by += leaf_bytes(op.l, es);
+            }
+        e = timed(h, RTRI_KCLASS_LEAF_MULT, pcode, fl, by, [&] { return launch_leaf(bt, false, p.leaf, all, h->stream); });
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+    }
     for (const Op &op : pl.ops) {
         hipError_t e;
+        if (one && !op.gemm)
+            continue;
         if (op.gemm) {
             const bool left = p.side == RTRI_LEFT;
             const double bytes = gemm_bytes(op.g, left ? ges : es, left ? es : ges, es);
@@ -407,6 +464,7 @@ int rtri_create(rtri_handle **out, void *stream)
     h->leaf_f64 = 0;
     h->leaf_f32 = 0;
     h->gemm_tile = 0;
+    h->trmm_leaves = 0;
     h->tune = nullptr;
     h->last = hipSuccess;
     for (int i = 0; i < WS_COUNT; ++i) {
@@ -475,6 +533,10 @@ int rtri_set_option(rtri_handle *h, int option, int64_t value)
         if (value < 0 || value > 3) return -3;
         h->gemm_tile = (int)value;
         return RTRI_OK;
+    case RTRI_OPT_TRMM_LEAVES:
+        if (value < 0 || value > 2) return -3;
+        h->trmm_leaves = (int)value;
+        return RTRI_OK;
     default:
         return -2;
     }
@@ -490,6 +552,7 @@ int rtri_get_option(rtri_handle *h, int option, int64_t *value)
     case RTRI_OPT_LEAF_F64: *value = h->leaf_f64; return RTRI_OK;
     case RTRI_OPT_LEAF_F32: *value = h->leaf_f32; return RTRI_OK;
     case RTRI_OPT_GEMM_TILE: *value = h->gemm_tile; return RTRI_OK;
+    case RTRI_OPT_TRMM_LEAVES: *value = h->trmm_leaves; return RTRI_OK;
     default: return -2;
     }
 }

@@ -33,6 +33,7 @@ enum WsSlot {
     WS_R,            // FP64 residual
     WS_W,            // FP64 op(A) * X
     WS_SCALARS,      // small reduction results
+    WS_SAVE,         // copy of a TRMM panel's original values (all leaves in one launch)
     WS_COUNT
 };
 
@@ -65,6 +66,7 @@ struct rtri_handle {
     uint32_t magic;
     hipStream_t stream;
     int leaf_f64, leaf_f32, gemm_tile;
+    int trmm_leaves;   // RTRI_OPT_TRMM_LEAVES: 0 automatic, 1 one launch per leaf, 2 all leaves in one launch
     rtri::TuneDB *tune;
     hipError_t last;
     void *ws[rtri::WS_COUNT];
@@ -83,6 +85,9 @@ hipError_t ensure_ws(rtri_handle *h, int slot, size_t bytes);
 // leaf size: the handle's option, else the tuning database, else 64
 bool valid_leaf(int64_t v);   // 0 (automatic), 16, 32, 64, 128 or 256
 int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nvec);
+// whether a TRMM with this leaf size runs all its leaves in one launch after
+// saving the panel (workspace WS_SAVE, m x n elements)
+bool trmm_one_launch(const rtri_handle *h, int leaf, int64_t ka, int64_t nvec);
 int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, const void *A, int64_t lda,
                const void *B, int64_t ldb, bool need_a);
 // enqueue a whole plan on the handle's stream (returns an RTRI_* status)

@@ -129,6 +129,8 @@ hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDe
 
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st)
 {
+    if (l.ka > 0)   // all diagonal blocks in one launch: matrix-core leaves only
+        return nbmax >= 64 ? launch_bleaf(t, solve, nbmax, l, st) : hipErrorInvalidValue;
     if (l.nvec <= 0 || l.nb <= 0)
         return hipSuccess;
     if (l.nb > nbmax)

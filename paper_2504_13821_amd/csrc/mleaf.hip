@@ -152,9 +152,9 @@ hipError_t launch_bpack(ElemT src, DType dst, bool solve, int nbmax, const PackD
 
 hipError_t launch_bleaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st)
 {
-    if (l.nvec <= 0 || l.nb <= 0)
+    if (l.nvec <= 0 || (l.ka > 0 ? l.ka : (int64_t)l.nb) <= 0)
         return hipSuccess;
-    if (l.nb > nbmax)
+    if (l.ka <= 0 && l.nb > nbmax)
         return hipErrorInvalidValue;
     if (t == DType::F64)
         return solve ? mleaf_launch_f64_solve(nbmax, l, st) : mleaf_launch_f64_mult(nbmax, l, st);

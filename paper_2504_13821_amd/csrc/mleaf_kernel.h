@@ -154,7 +154,14 @@ __global__ __launch_bounds__(256, 1) void mleaf_kernel(LeafDesc d, const T *__re
     const int c = lane % 16, g = lane / 16;
     const int64_t vec = (int64_t)blockIdx.x * 64 + 16 * w + c;
     const bool act = vec < d.nvec;
-    const int nb = d.nb;
+    int nb = d.nb;
+    if (d.ka > 0) {
+        // one of all the diagonal blocks (blockIdx.y)
+        const int64_t d0 = (int64_t)blockIdx.y * NB;
+        nb = (int)min<int64_t>(NB, d.ka - d0);
+        B += d0 * d.sd;
+        Lp += (int64_t)blockIdx.y * TOT;
+    }
     const bool mlower = d.mlower;
     T *Bv = B + vec * d.si;
     const T alpha = T(d.alpha);
@@ -259,11 +266,11 @@ __global__ __launch_bounds__(256, 1) void mleaf_kernel(LeafDesc d, const T *__re
 template <typename T, bool SOLVE, int NB>
 hipError_t launch_nb(const LeafDesc &l, hipStream_t st)
 {
-    const dim3 grid((unsigned)((l.nvec + 63) / 64));
+    const dim3 grid((unsigned)((l.nvec + 63) / 64), l.ka > 0 ? (unsigned)((l.ka + NB - 1) / NB) : 1u);
     const T *L = static_cast<const T *>(l.Lp);
     T *B = static_cast<T *>(l.B);
-    const bool vec = l.sd == 1 && l.nb % 4 == 0 && reinterpret_cast<uintptr_t>(B) % 16 == 0 &&
-                     (l.si * (int64_t)sizeof(T)) % 16 == 0;
+    const bool vec = l.sd == 1 && (l.ka > 0 ? l.ka : (int64_t)l.nb) % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(B) % 16 == 0 && (l.si * (int64_t)sizeof(T)) % 16 == 0;
     if (vec)
         hipLaunchKernelGGL((mleaf_kernel<T, NB, SOLVE, true>), grid, dim3(256), 0, st, l, L, B);
     else

@@ -115,9 +115,10 @@ size_t ws_bound(const rtri_request &r, int64_t ka)
 {
     const size_t mn = (size_t)r.m * (size_t)r.n;
     const size_t pack = (size_t)((ka + 255) / 256 + 1) * (size_t)pack_elems(256) + (size_t)ka * 136;
+    // a TRMM (and the residual product of a mixed solve) may save its panel (mn * 8)
     if (r.precision == RTRI_PREC_F64)
-        return 8 * pack + WS_MIN;
-    return (size_t)ka * ka * 4 + mn * (4 + 8 * 4) + 12 * pack + 9 * WS_MIN;
+        return 8 * pack + WS_MIN + (r.op == 1 ? mn * 8 + WS_MIN : 0);
+    return (size_t)ka * ka * 4 + mn * (4 + 8 * 5) + 12 * pack + 10 * WS_MIN;
 }
 
 // device memory the slot's handle allocates to run q alone: for every
@@ -131,8 +132,15 @@ size_t alone_growth(const rtri_handle *h, const Req &q)
         const int leaf = pick_leaf(h, t, solve, q.ka, nvec);
         return (size_t)((q.ka + leaf - 1) / leaf) * (size_t)pack_elems(leaf) * (t == DType::F64 ? 8 : 4);
     };
+    // the panel copy of a TRMM that runs all its leaves in one launch
+    auto save_bytes = [&] {
+        const int leaf = pick_leaf(h, DType::F64, false, q.ka, nvec);
+        return trmm_one_launch(h, leaf, q.ka, nvec) ? (size_t)r.m * (size_t)r.n * 8 : (size_t)0;
+    };
     if (r.precision == RTRI_PREC_F64) {
         need[WS_PACK] = pack_bytes(DType::F64, r.op == 0);
+        if (r.op == 1)
+            need[WS_SAVE] = save_bytes();
     } else {
         const size_t mn = (size_t)r.m * (size_t)r.n;
         need[WS_ACOPY] = (size_t)q.ka * q.ka * (r.precision == RTRI_PREC_MIXED_BF16 ? 2 : 4);
@@ -141,6 +149,7 @@ size_t alone_growth(const rtri_handle *h, const Req &q)
         need[WS_SCALARS] = 64;
         need[WS_PACK2] = pack_bytes(DType::F32, true);
         need[WS_PACK] = pack_bytes(DType::F64, false);
+        need[WS_SAVE] = save_bytes();
     }
     size_t g = 0;
     for (int i = 0; i < WS_COUNT; ++i)

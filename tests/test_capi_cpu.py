@@ -90,6 +90,10 @@ def test_options(rt, handle):
     for leaf in (16, 64, 128, 256, 0):
         assert rt.rtri_set_option(handle, rt.OPT_LEAF_F32, leaf) == rt.OK
     assert rt.rtri_set_option(handle, rt.OPT_LEAF_F32, 512) == -3
+    for mode in (0, 1, 2):
+        assert rt.rtri_set_option(handle, rt.OPT_TRMM_LEAVES, mode) == rt.OK
+        assert rt.rtri_get_option(handle, rt.OPT_TRMM_LEAVES, ctypes.byref(v)) == rt.OK and v.value == mode
+    assert rt.rtri_set_option(handle, rt.OPT_TRMM_LEAVES, 3) == -3
     assert rt.rtri_set_option(handle, 999, 1) == -2
 
 

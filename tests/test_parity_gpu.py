@@ -242,6 +242,27 @@ def test_vector_and_element_paths_agree(rt, h, orc, dt, leaf, op, uplo, m):
     assert eta(orc, op, "L", uplo, "N", "N", 0.75, A, B, X1) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt,leaf", [("f64", 64), ("f64", 256), ("f32", 128)])
+@pytest.mark.parametrize("side,uplo,trans", [("L", "L", "N"), ("L", "U", "T"), ("L", "U", "N"), ("R", "L", "N"),
+                                             ("R", "U", "T")])
+@pytest.mark.parametrize("shape", [(600, 130), (1000, 257), (301, 70)])
+def test_trmm_leaf_schedules_agree(rt, h, orc, dt, leaf, side, uplo, trans, shape):
+    """TRMM with one launch per leaf (recursion order) and with every leaf in
+    one launch after saving the panel: the GEMM updates see the same operands,
+    so the results agree bit for bit; both pass the oracle's bound."""
+    m, n = shape if side == "L" else shape[::-1]
+    say("trmm schedules", dt, leaf, side, uplo, trans, m, n)
+    A, B = _inputs(side, uplo, "N", m, n, dt, G(17, m, n))
+    h.set_option(rt.OPT_LEAF_F64 if dt == "f64" else rt.OPT_LEAF_F32, leaf)
+    out = []
+    for mode in (1, 2):
+        h.set_option(rt.OPT_TRMM_LEAVES, mode)
+        out.append(run_op(rt, h, "trmm", side, uplo, trans, "N", -1.25, A, B, dt))
+    h.set_option(rt.OPT_TRMM_LEAVES, 0)
+    assert np.array_equal(out[0], out[1]), (dt, leaf, side, uplo, trans, shape)
+    assert eta(orc, "trmm", side, uplo, trans, "N", -1.25, A, B, out[1]) <= TOL[dt]
+
+
 @pytest.mark.parametrize("op", ["trsm", "trmm"])
 def test_alpha_zero_reads_nothing(rt, h, op):
     m, n = 70, 33
