@@ -37,6 +37,7 @@ constexpr uint32_t MAGIC = 0x72747269u;  // 'rtri'
 
 struct Op {
     bool gemm;
+    int depth;   // recursion depth of the node that issued it
     GemmDesc g;
     LeafDesc l;
 };
@@ -103,10 +104,11 @@ struct Planner {
     }
 
     // B[t] = beta * B[t] + s * (off-diagonal block) x B[src]
-    void update(int64_t t0, int64_t th, int64_t s0, int64_t sh, double beta, double s)
+    void update(int64_t t0, int64_t th, int64_t s0, int64_t sh, double beta, double s, int depth)
     {
         Op op{};
         op.gemm = true;
+        op.depth = depth;
         GemmDesc &g = op.g;
         g.beta = beta;
         g.s = s;
@@ -137,7 +139,7 @@ struct Planner {
         ops.push_back(op);
     }
 
-    void rec(int64_t d0, int64_t h, double alpha)
+    void rec(int64_t d0, int64_t h, double alpha, int depth = 0)
     {
         if (h <= p.leaf) {
             leaf(d0, h, alpha);
@@ -148,13 +150,13 @@ struct Planner {
         const int64_t b1 = d0, h1 = k, b2 = d0 + k, h2 = h - k;
         const int64_t f0 = forward ? b1 : b2, fh = forward ? h1 : h2;   // first block
         const int64_t g0 = forward ? b2 : b1, gh = forward ? h2 : h1;   // second block
-        rec(f0, fh, alpha);
+        rec(f0, fh, alpha, depth + 1);
         if (p.solve) {
-            update(g0, gh, f0, fh, alpha, -1.0);   // B_second = alpha B_second - off * X_first
-            rec(g0, gh, 1.0);
+            update(g0, gh, f0, fh, alpha, -1.0, depth);   // B_second = alpha B_second - off * X_first
+            rec(g0, gh, 1.0, depth + 1);
         } else {
-            update(f0, fh, g0, gh, 1.0, alpha);    // B_first += alpha * off * B_second (original)
-            rec(g0, gh, alpha);
+            update(f0, fh, g0, gh, 1.0, alpha, depth);    // B_first += alpha * off * B_second (original)
+            rec(g0, gh, alpha, depth + 1);
         }
     }
 };
@@ -272,6 +274,48 @@ int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nve
     return ka <= 1024 ? 64 : 256;
 }
 
+// GEMM updates with disjoint outputs and no mutual dependence, spread over
+// the handle's auxiliary streams (one stays on the handle's stream);
+// launch(g, stream) enqueues one update
+template <class Launch>
+hipError_t run_gemms_concurrent(rtri_handle *h, const std::vector<const GemmDesc *> &gs, Launch &&launch)
+{
+    // a fork / join across streams costs tens of microseconds: a few small
+    // updates stay on the handle's stream, one after another (concurrent from
+    // 8 updates, or from 2 of at least 1 GFLOP each)
+    const bool big = !gs.empty() && 2.0 * (double)gs[0]->M * (double)gs[0]->N * (double)gs[0]->K >= 1e9;
+    if (gs.size() < 2 || (gs.size() < 8 && !big)) {
+        for (const GemmDesc *g : gs) {
+            const hipError_t e = launch(*g, h->stream);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t e = hipSuccess;
+    if (!h->aux_ready) {
+        for (int i = 0; i < 4 && e == hipSuccess; ++i)
+            e = hipStreamCreateWithFlags(&h->aux[i], hipStreamNonBlocking);
+        for (int i = 0; i < 5 && e == hipSuccess; ++i)
+            e = hipEventCreateWithFlags(&h->aux_ev[i], hipEventDisableTiming);
+        if (e != hipSuccess)
+            return e;
+        h->aux_ready = true;
+    }
+    const int na = (int)std::min<size_t>(4, gs.size() - 1);
+    e = hipEventRecord(h->aux_ev[4], h->stream);
+    for (int i = 0; i < na && e == hipSuccess; ++i)
+        e = hipStreamWaitEvent(h->aux[i], h->aux_ev[4], 0);
+    for (size_t j = 0; j < gs.size() && e == hipSuccess; ++j)
+        e = launch(*gs[j], j == 0 ? h->stream : h->aux[(j - 1) % na]);
+    for (int i = 0; i < na && e == hipSuccess; ++i) {
+        e = hipEventRecord(h->aux_ev[i], h->aux[i]);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(h->stream, h->aux_ev[i], 0);
+    }
+    return e;
+}
+
 bool trmm_one_launch(const rtri_handle *h, int leaf, int64_t ka, int64_t nvec)
 {
     if (leaf < 64 || ka <= leaf)   // matrix-core leaves; a single leaf has no schedule to choose
@@ -337,6 +381,13 @@ int run_plan(rtri_handle *h, const PlanIn &p)
 
     const bool g16 = p.gt == ElemT::BF16 || p.gt == ElemT::F16;
     const size_t ges = elem_size(p.gt);
+    // one GEMM update on a stream: 16-bit factor copy or panel-type MFMA tiles
+    auto launch_update = [&](const GemmDesc &g, hipStream_t st) {
+        if (g16)
+            return launch_gemm16(p.gt == ElemT::BF16, p.side == RTRI_LEFT, g, st);
+        const int tile = h->gemm_tile ? h->gemm_tile : tuned_tile(h->tune, pcode, g.M, g.N);
+        return launch_gemm(bt, g, tile, st);
+    };
     if (one) {
         hipError_t e = timed(h, RTRI_KCLASS_OTHER, pcode, 0.0, 2.0 * es * p.m * p.n, [&] {
             return hipMemcpy2DAsync(h->ws[WS_SAVE], p.m * es, p.B, p.ldb * es, p.m * es, p.n,
@@ -362,6 +413,26 @@ int run_plan(rtri_handle *h, const PlanIn &p)
         if (e != hipSuccess)
             return hip_fail(h, e);
     }
+    if (one && !h->profiling) {
+        // The updates read only the saved panel and each writes one row block,
+        // which gets one update per depth, deepest first in recursion order: so
+        // run the depths deepest first, the updates of one depth concurrently
+        // on the auxiliary streams.
+        int maxd = 0;
+        for (const Op &op : pl.ops)
+            if (op.gemm)
+                maxd = std::max(maxd, op.depth);
+        for (int d = maxd; d >= 0; --d) {
+            std::vector<const GemmDesc *> gs;
+            for (const Op &op : pl.ops)
+                if (op.gemm && op.depth == d)
+                    gs.push_back(&op.g);
+            hipError_t e = run_gemms_concurrent(h, gs, launch_update);
+            if (e != hipSuccess)
+                return hip_fail(h, e);
+        }
+        return RTRI_OK;
+    }
     for (const Op &op : pl.ops) {
         hipError_t e;
         if (one && !op.gemm)
@@ -369,14 +440,8 @@ int run_plan(rtri_handle *h, const PlanIn &p)
         if (op.gemm) {
             const bool left = p.side == RTRI_LEFT;
             const double bytes = gemm_bytes(op.g, left ? ges : es, left ? es : ges, es);
-            if (g16)
-                e = timed(h, RTRI_KCLASS_GEMM, dtype_code(p.gt), gemm_flops(op.g), bytes,
-                          [&] { return launch_gemm16(p.gt == ElemT::BF16, left, op.g, h->stream); });
-            else
-                e = timed(h, RTRI_KCLASS_GEMM, pcode, gemm_flops(op.g), bytes, [&] {
-                    const int tile = h->gemm_tile ? h->gemm_tile : tuned_tile(h->tune, pcode, op.g.M, op.g.N);
-                    return launch_gemm(bt, op.g, tile, h->stream);
-                });
+            e = timed(h, RTRI_KCLASS_GEMM, g16 ? dtype_code(p.gt) : pcode, gemm_flops(op.g), bytes,
+                      [&] { return launch_update(op.g, h->stream); });
         } else {
             e = timed(h, p.solve ? RTRI_KCLASS_LEAF_SOLVE : RTRI_KCLASS_LEAF_MULT, pcode, leaf_flops(op.l),
                       leaf_bytes(op.l, es), [&] { return launch_leaf(bt, p.solve, p.leaf, op.l, h->stream); });
@@ -473,6 +538,7 @@ int rtri_create(rtri_handle **out, void *stream)
     }
     h->profiling = false;
     h->pool_used = 0;
+    h->aux_ready = false;
     // a tuning database named by the environment applies to every new handle
     if (const char *db = std::getenv("RTRI_TUNE_DB"))
         (void)load_tuning_file(h, db);
@@ -495,6 +561,14 @@ int rtri_destroy(rtri_handle *h)
             (void)hipFree(h->ws[i]);
     for (hipEvent_t e : h->pool)
         (void)hipEventDestroy(e);
+    if (h->aux_ready) {
+        for (int i = 0; i < 4; ++i) {
+            (void)hipStreamSynchronize(h->aux[i]);
+            (void)hipStreamDestroy(h->aux[i]);
+        }
+        for (int i = 0; i < 5; ++i)
+            (void)hipEventDestroy(h->aux_ev[i]);
+    }
     tune_db_free(h->tune);
     delete h;
     return RTRI_OK;

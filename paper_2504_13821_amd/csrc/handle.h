@@ -71,6 +71,11 @@ struct rtri_handle {
     hipError_t last;
     void *ws[rtri::WS_COUNT];
     size_t ws_bytes[rtri::WS_COUNT];
+    // streams for independent GEMM updates (created on first use, default
+    // priority) and the events that fork them from / join them to `stream`
+    hipStream_t aux[4];
+    hipEvent_t aux_ev[5];
+    bool aux_ready;
     bool profiling;
     std::vector<rtri::ProfRec> recs;
     std::vector<hipEvent_t> pool;

@@ -52,6 +52,27 @@ def _run_trmm_ex(rt, h, side, uplo, trans, diag, alpha, A, B, dt):
 
 
 @pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("side,uplo,trans", [("L", "L", "N"), ("R", "U", "T")])
+def test_trmm_ex_leaf_schedules_agree(rt, h, orc, dt, side, uplo, trans):
+    """The 16-bit TRMM with one launch per leaf and with every leaf in one
+    launch (its updates run concurrently): bit-identical results."""
+    m, n = (700, 150) if side == "L" else (150, 700)
+    say("trmm_ex schedules", dt, side, uplo, trans)
+    g = G(3, m)
+    ka = m if side == "L" else n
+    A = rounded(synth.tri(ka, uplo, g, "stress"), dt)
+    B = rounded(synth.dense(m, n, g), dt)
+    h.set_option(rt.OPT_LEAF_F32, 64)
+    out = []
+    for mode in (1, 2):
+        h.set_option(rt.OPT_TRMM_LEAVES, mode)
+        out.append(_run_trmm_ex(rt, h, side, uplo, trans, "N", 0.5, A, B, dt))
+    h.set_option(rt.OPT_TRMM_LEAVES, 0)
+    assert np.array_equal(out[0], out[1])
+    assert orc.trmm_eta(side, uplo, trans, "N", 0.5, A, B, out[1]) <= 7 * np.sqrt(ka) * 2.0 ** -24
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
 @pytest.mark.parametrize("diag", "NU")
 @pytest.mark.parametrize("side,uplo,trans", VARIANTS_NT)
 def test_trmm_ex_parity(rt, h, orc, dt, diag, side, uplo, trans):
