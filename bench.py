@@ -67,8 +67,8 @@ def progress(*a):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the hot path here runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        print("bench.py measures one GPU only: this library runs each problem on a single MI355X "
+              "(how the path would shard over several GPUs is described in the design notes)", file=sys.stderr)
         sys.exit(2)
 
     import torch
