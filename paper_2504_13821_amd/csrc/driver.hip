@@ -274,6 +274,20 @@ int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nve
     return ka <= 1024 ? 64 : 256;
 }
 
+// GEMM tile: the handle's option, else the tuning database's rule, else
+// automatic (0).  A rule is measured at its bucket's largest size; a 128 x 128
+// tile it names for an update that would leave CUs without a workgroup (fewer
+// than 256 tiles, e.g. N far below the bucket's) falls back to automatic.
+int pick_tile(const rtri_handle *h, int dtype, int64_t M, int64_t N)
+{
+    if (h->gemm_tile != 0)
+        return h->gemm_tile;
+    const int t = tuned_tile(h->tune, dtype, M, N);
+    if ((t == 1 || t == 3) && ((M + 127) / 128) * ((N + 127) / 128) < 256)
+        return 0;
+    return t;
+}
+
 // GEMM updates with disjoint outputs and no mutual dependence, spread over
 // the handle's auxiliary streams (one stays on the handle's stream);
 // launch(g, stream) enqueues one update
@@ -385,7 +399,7 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     auto launch_update = [&](const GemmDesc &g, hipStream_t st) {
         if (g16)
             return launch_gemm16(p.gt == ElemT::BF16, p.side == RTRI_LEFT, g, st);
-        const int tile = h->gemm_tile ? h->gemm_tile : tuned_tile(h->tune, pcode, g.M, g.N);
+        const int tile = pick_tile(h, pcode, g.M, g.N);
         return launch_gemm(bt, g, tile, st);
     };
     if (one) {
@@ -771,7 +785,7 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
     const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
     const size_t es = t == DType::F64 ? 8 : 4;
     hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, es, es, es), [&] {
-        const int tile = h->gemm_tile ? h->gemm_tile : tuned_tile(h->tune, dtype, g.M, g.N);
+        const int tile = pick_tile(h, dtype, g.M, g.N);
         return launch_gemm(t, g, tile, h->stream);
     });
     return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
