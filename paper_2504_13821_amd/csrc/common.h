@@ -106,9 +106,10 @@ hipError_t launch_convert(ElemT src, ElemT dst, const void *X, int64_t ldx, void
 // Y = fl_dst(X^T): X is m-by-n FP64, Y is n-by-m (rounded once, as launch_convert)
 hipError_t launch_transpose_convert(ElemT dst, const double *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
                                     int64_t n, hipStream_t st);
-// X += s * D   (X FP64, D FP32); then W = X when W != nullptr
+// X += s * D, or X = s * D when assign (X is then not read)   (X FP64, D FP32);
+// then W = X when W != nullptr
 hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,
-                             double *W, int64_t ldw, hipStream_t st);
+                             bool assign, double *W, int64_t ldw, hipStream_t st);
 // Refinement bookkeeping.  Vectors are columns (by_cols) or rows of the m-by-n
 // matrices.  R = R0 - W; per vector v: eta_v = |R_v|inf / (anorm |X_v|inf + |R0_v|inf);
 // out[0] = max_v eta_v, out[1] = max |R| (both as ordered bit patterns of

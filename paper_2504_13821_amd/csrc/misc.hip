@@ -164,102 +164,228 @@ __device__ __forceinline__ double wave_max(double v)
 
 __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
 
-// X += s * D, and W = X when W is given
+// butterfly sum over the wavefront (the same fixed order on every run)
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// max over a 256-thread workgroup; the result is valid in thread 0
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+    v = wave_max(v);
+    if (threadIdx.x % 64 == 0)
+        red[threadIdx.x / 64] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        v = nmax(nmax(red[0], red[1]), nmax(red[2], red[3]));
+    return v;
+}
+
+// grid of a reduction over an m-by-n matrix: about REDUCE_BLOCKS workgroups,
+// so that each adds one atomic on the result (columns stride over grid rows)
+constexpr int64_t REDUCE_BLOCKS = 2048;
+
+dim3 grid2d_reduce(int64_t m, int64_t n)
+{
+    const int64_t gx = (m + NT * RPT - 1) / (NT * RPT);
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, REDUCE_BLOCKS / std::max<int64_t>(gx, 1)));
+    return dim3((unsigned)gx, (unsigned)std::min<int64_t>(gy, 65535));
+}
+
+// X += s * D (X = s * D when assign: X is not read), and W = X when W is given
 __global__ __launch_bounds__(NT) void add_scaled_kernel(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m,
-                                                        int64_t n, double s, double *W, int64_t ldw)
+                                                        int64_t n, double s, bool assign, double *W, int64_t ldw)
 {
     for_each_2d(m, n, [&](int64_t i, int64_t j) {
-        const double x = X[i + j * ldx] + s * (double)D[i + j * ldd];
+        const double d = s * (double)D[i + j * ldd];
+        const double x = assign ? d : X[i + j * ldx] + d;
         X[i + j * ldx] = x;
         if (W != nullptr)
             W[i + j * ldw] = x;
     });
 }
 
-// vectors are columns: one wavefront per column, lanes run down the rows
+// Vectors are columns.  Each wavefront takes columns j = w, w + W, ... (W
+// wavefronts in the grid), its lanes running down the rows four loads deep;
+// the workgroup's largest eta and |r| then go to memory in one atomic each.
 __global__ __launch_bounds__(NT) void resid_cols_kernel(const double *R0, int64_t ld0, const double *W, int64_t ldw,
                                                         double *R, int64_t ldr, const double *X, int64_t ldx,
                                                         int64_t m, int64_t n, double anorm, unsigned long long *out)
 {
+    __shared__ double red[NT / 64];
     const int lane = threadIdx.x % 64;
-    const int64_t j = (int64_t)blockIdx.x * (NT / 64) + threadIdx.x / 64;
-    if (j >= n)
-        return;
-    double rn = 0.0, xn = 0.0, bn = 0.0;
-    for (int64_t i = lane; i < m; i += 64) {
-        const double b = R0[i + j * ld0];
-        const double r = b - W[i + j * ldw];
-        R[i + j * ldr] = r;
-        rn = nmax(rn, fabs(r));
-        xn = nmax(xn, fabs(X[i + j * ldx]));
-        bn = nmax(bn, fabs(b));
-    }
-    rn = wave_max(rn);
-    xn = wave_max(xn);
-    bn = wave_max(bn);
-    if (lane == 0) {
+    const int64_t nw = (int64_t)gridDim.x * (NT / 64);
+    double eta_w = 0.0, rn_w = 0.0;
+    for (int64_t j = (int64_t)blockIdx.x * (NT / 64) + threadIdx.x / 64; j < n; j += nw) {
+        const double *r0 = R0 + j * ld0, *w = W + j * ldw, *x = X + j * ldx;
+        double *r = R + j * ldr;
+        double rn = 0.0, xn = 0.0, bn = 0.0;
+        for (int64_t i0 = lane; i0 < m; i0 += 4 * 64) {
+            double b[4], wv[4], xv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t i = i0 + t * 64;
+                b[t] = i < m ? r0[i] : 0.0;
+                wv[t] = i < m ? w[i] : 0.0;
+                xv[t] = i < m ? x[i] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t i = i0 + t * 64;
+                const double rv = b[t] - wv[t];
+                if (i < m)
+                    r[i] = rv;
+                rn = nmax(rn, fabs(rv));
+                xn = nmax(xn, fabs(xv[t]));
+                bn = nmax(bn, fabs(b[t]));
+            }
+        }
+        rn = wave_max(rn);
+        xn = wave_max(xn);
+        bn = wave_max(bn);
         const double den = anorm * xn + bn;
         const double eta = den > 0.0 ? rn / den : (rn > 0.0 ? __builtin_inf() : (rn != rn ? rn : 0.0));
-        atomicMax(out, ordered_bits(eta));
-        atomicMax(out + 1, ordered_bits(rn));
+        eta_w = nmax(eta_w, eta);
+        rn_w = nmax(rn_w, rn);
+    }
+    eta_w = block_max(eta_w, red);
+    __syncthreads();
+    rn_w = block_max(rn_w, red);
+    if (threadIdx.x == 0) {
+        atomicMax(out, ordered_bits(eta_w));
+        atomicMax(out + 1, ordered_bits(rn_w));
     }
 }
 
-// vectors are rows: one thread per row, walking the columns (coalesced across threads)
-__global__ __launch_bounds__(NT) void resid_rows_kernel(const double *R0, int64_t ld0, const double *W, int64_t ldw,
-                                                        double *R, int64_t ldr, const double *X, int64_t ldx,
-                                                        int64_t m, int64_t n, double anorm, unsigned long long *out)
+// Vectors are rows.  A workgroup of RESID_ROWS_NT threads takes 32 rows; its
+// 32 row groups of threads split the columns (thread (r, q) reads columns
+// q, q + 32, ...), so each load instruction of a wavefront reads two 256-byte
+// column segments.  The partial maxima of a row are combined in LDS.
+constexpr int RESID_ROWS_NT = 1024;
+constexpr int RESID_ROWS = 32;
+
+__global__ __launch_bounds__(RESID_ROWS_NT) void resid_rows_kernel(const double *R0, int64_t ld0, const double *W,
+                                                                   int64_t ldw, double *R, int64_t ldr,
+                                                                   const double *X, int64_t ldx, int64_t m, int64_t n,
+                                                                   double anorm, unsigned long long *out)
 {
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    double eta = 0.0, rn = 0.0;
+    constexpr int NQ = RESID_ROWS_NT / RESID_ROWS;
+    __shared__ double prn[RESID_ROWS_NT], pxn[RESID_ROWS_NT], pbn[RESID_ROWS_NT];
+    const int r = threadIdx.x % RESID_ROWS, q = threadIdx.x / RESID_ROWS;
+    const int64_t i = (int64_t)blockIdx.x * RESID_ROWS + r;
+    double rn = 0.0, xn = 0.0, bn = 0.0;
     if (i < m) {
-        double xn = 0.0, bn = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
+#pragma unroll 4
+        for (int64_t j = q; j < n; j += NQ) {
             const double b = R0[i + j * ld0];
-            const double r = b - W[i + j * ldw];
-            R[i + j * ldr] = r;
-            rn = nmax(rn, fabs(r));
+            const double rv = b - W[i + j * ldw];
+            R[i + j * ldr] = rv;
+            rn = nmax(rn, fabs(rv));
             xn = nmax(xn, fabs(X[i + j * ldx]));
             bn = nmax(bn, fabs(b));
         }
-        const double den = anorm * xn + bn;
-        eta = den > 0.0 ? rn / den : (rn > 0.0 ? __builtin_inf() : (rn != rn ? rn : 0.0));
     }
-    eta = wave_max(eta);
-    rn = wave_max(rn);
-    if (threadIdx.x % 64 == 0) {
-        atomicMax(out, ordered_bits(eta));
-        atomicMax(out + 1, ordered_bits(rn));
+    prn[threadIdx.x] = rn;
+    pxn[threadIdx.x] = xn;
+    pbn[threadIdx.x] = bn;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double eta = 0.0;
+        rn = 0.0;
+        if (threadIdx.x < RESID_ROWS && i < m) {
+            xn = bn = 0.0;
+            for (int k = 0; k < NQ; ++k) {
+                rn = nmax(rn, prn[r + k * RESID_ROWS]);
+                xn = nmax(xn, pxn[r + k * RESID_ROWS]);
+                bn = nmax(bn, pbn[r + k * RESID_ROWS]);
+            }
+            const double den = anorm * xn + bn;
+            eta = den > 0.0 ? rn / den : (rn > 0.0 ? __builtin_inf() : (rn != rn ? rn : 0.0));
+        }
+        eta = wave_max(eta);
+        rn = wave_max(rn);
+        if (threadIdx.x == 0) {
+            atomicMax(out, ordered_bits(eta));
+            atomicMax(out + 1, ordered_bits(rn));
+        }
     }
 }
 
-// one thread per line of Mx; lines shorter than the matrix skip the unreferenced part
+// Line sums s_i = sum_k |M(i, k)| over the referenced part of line i, then
+// their maximum.  M(i, k) = A[i + k*lda] (lines are rows of A) or, with
+// mtrans, A[k + i*lda] (lines are columns); the referenced part is k <= i
+// (mlower) or k >= i, and a unit diagonal counts as 1 without being read.
+// A workgroup takes 16 lines.  Rows: thread (r, q) sums line r over
+// k = k0 + q, k0 + q + 16, ... (each load instruction reads 128-byte row
+// segments of four columns).  Columns: each wavefront sums four lines in turn,
+// its lanes along k.  Partials are combined in a fixed order.
+constexpr int NORM_LINES = 16;
+
 __global__ __launch_bounds__(NT) void line_norm_kernel(const double *A, int64_t lda, int64_t ka, bool mtrans,
                                                        bool mlower, bool unit, unsigned long long *out)
 {
-    const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-    double s = 0.0;
-    if (i < ka) {
-        const int64_t k0 = mlower ? 0 : i, k1 = mlower ? i : ka - 1;
-        for (int64_t k = k0; k <= k1; ++k) {
-            if (k == i && unit)
-                s += 1.0;
-            else
-                s += fabs(mtrans ? A[k + i * lda] : A[i + k * lda]);
+    __shared__ double part[NT];
+    const int tid = threadIdx.x;
+    const int64_t l0 = (int64_t)blockIdx.x * NORM_LINES;
+    if (!mtrans) {
+        constexpr int NQ = NT / NORM_LINES;
+        const int r = tid % NORM_LINES, q = tid / NORM_LINES;
+        const int64_t i = l0 + r;
+        double s = 0.0;
+        if (i < ka) {
+            const int64_t k0 = mlower ? 0 : i, k1 = mlower ? i : ka - 1;   // inclusive
+#pragma unroll 4
+            for (int64_t k = k0 + q; k <= k1; k += NQ)
+                s += (k == i && unit) ? 1.0 : fabs(A[i + k * lda]);
+        }
+        part[tid] = s;
+        __syncthreads();
+        if (tid < NORM_LINES) {
+            double v = 0.0;
+            for (int k = 0; k < NQ; ++k)
+                v += part[tid + k * NORM_LINES];
+            part[tid] = v;   // only this thread reads slot tid < 16 from here on
+        }
+    } else {
+        const int w = tid / 64, lane = tid % 64;
+        constexpr int PER_WAVE = NORM_LINES / (NT / 64);
+        for (int c = 0; c < PER_WAVE; ++c) {
+            const int64_t i = l0 + w * PER_WAVE + c;
+            double s = 0.0;
+            if (i < ka) {
+                const int64_t k0 = mlower ? 0 : i, k1 = mlower ? i : ka - 1;
+                const double *col = A + i * lda;
+#pragma unroll 4
+                for (int64_t k = k0 + lane; k <= k1; k += 64)
+                    s += (k == i && unit) ? 1.0 : fabs(col[k]);
+            }
+            s = wave_sum(s);
+            if (lane == 0)
+                part[w * PER_WAVE + c] = s;
         }
     }
-    s = wave_max(s);
-    if (threadIdx.x % 64 == 0)
-        atomicMax(out, ordered_bits(s));
+    __syncthreads();
+    if (tid < 64) {
+        double v = tid < NORM_LINES ? part[tid] : 0.0;
+        v = wave_max(v);
+        if (tid == 0)
+            atomicMax(out, ordered_bits(v));
+    }
 }
 
+// launched on grid2d_reduce: one atomic per workgroup
 __global__ __launch_bounds__(NT) void max_abs_kernel(const double *X, int64_t ldx, int64_t m, int64_t n,
                                                      unsigned long long *out)
 {
+    __shared__ double red[NT / 64];
     double v = 0.0;
     for_each_2d(m, n, [&](int64_t i, int64_t j) { v = nmax(v, fabs(X[i + j * ldx])); });
-    v = wave_max(v);
-    if (threadIdx.x % 64 == 0)
+    v = block_max(v, red);
+    if (threadIdx.x == 0)
         atomicMax(out, ordered_bits(v));
 }
 
@@ -316,11 +442,11 @@ hipError_t launch_transpose_convert(ElemT dst, const double *X, int64_t ldx, voi
 }
 
 hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,
-                             double *W, int64_t ldw, hipStream_t st)
+                             bool assign, double *W, int64_t ldw, hipStream_t st)
 {
     if (m <= 0 || n <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(add_scaled_kernel, grid2d(m, n), dim3(NT), 0, st, X, ldx, D, ldd, m, n, s, W, ldw);
+    hipLaunchKernelGGL(add_scaled_kernel, grid2d(m, n), dim3(NT), 0, st, X, ldx, D, ldd, m, n, s, assign, W, ldw);
     return hipGetLastError();
 }
 
@@ -330,12 +456,17 @@ hipError_t launch_resid_eta(const double *R0, int64_t ld0, const double *W, int6
 {
     if (m <= 0 || n <= 0)
         return hipSuccess;
-    if (by_cols)
-        hipLaunchKernelGGL(resid_cols_kernel, dim3((unsigned)((n + NT / 64 - 1) / (NT / 64))), dim3(NT), 0, st, R0,
-                           ld0, W, ldw, R, ldr, X, ldx, m, n, anorm, out);
-    else
-        hipLaunchKernelGGL(resid_rows_kernel, dim3((unsigned)((m + NT - 1) / NT)), dim3(NT), 0, st, R0, ld0, W, ldw,
+    if (by_cols) {
+        const int64_t blocks = std::min<int64_t>((n + NT / 64 - 1) / (NT / 64), REDUCE_BLOCKS);
+        hipLaunchKernelGGL(resid_cols_kernel, dim3((unsigned)blocks), dim3(NT), 0, st, R0, ld0, W, ldw, R, ldr, X,
+                           ldx, m, n, anorm, out);
+    } else {
+        const int64_t blocks = (m + RESID_ROWS - 1) / RESID_ROWS;
+        if (blocks > INT32_MAX)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(resid_rows_kernel, dim3((unsigned)blocks), dim3(RESID_ROWS_NT), 0, st, R0, ld0, W, ldw,
                            R, ldr, X, ldx, m, n, anorm, out);
+    }
     return hipGetLastError();
 }
 
@@ -344,8 +475,11 @@ hipError_t launch_line_norm(const double *A, int64_t lda, int64_t ka, bool mtran
 {
     if (ka <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(line_norm_kernel, dim3((unsigned)((ka + NT - 1) / NT)), dim3(NT), 0, st, A, lda, ka, mtrans,
-                       mlower, unit, out);
+    const int64_t blocks = (ka + NORM_LINES - 1) / NORM_LINES;
+    if (blocks > INT32_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(line_norm_kernel, dim3((unsigned)blocks), dim3(NT), 0, st, A, lda, ka, mtrans, mlower, unit,
+                       out);
     return hipGetLastError();
 }
 
@@ -354,7 +488,7 @@ hipError_t launch_max_abs(const double *X, int64_t ldx, int64_t m, int64_t n, un
 {
     if (m <= 0 || n <= 0)
         return hipSuccess;
-    hipLaunchKernelGGL(max_abs_kernel, grid2d(m, n), dim3(NT), 0, st, X, ldx, m, n, out);
+    hipLaunchKernelGGL(max_abs_kernel, grid2d_reduce(m, n), dim3(NT), 0, st, X, ldx, m, n, out);
     return hipGetLastError();
 }
 

@@ -161,12 +161,10 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
         });
     if (e == hipSuccess)
         e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, B, ldb, R0, ld, m, n, alpha, st); });
+    // the first residual is alpha B itself (X = 0): it is read from R0, and the
+    // first correction is assigned to X rather than added
     if (e == hipSuccess)
-        e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, R0, ld, R, ld, m, n, 1.0, st); });
-    if (e == hipSuccess)
-        e = other(8.0 * mn, [&] { return launch_fill(DType::F64, X, m, n, ld, 0.0, st); });
-    if (e == hipSuccess)
-        e = other(8.0 * mn, [&] { return launch_max_abs(R, ld, m, n, sc + 1, st); });
+        e = other(8.0 * mn, [&] { return launch_max_abs(R0, ld, m, n, sc + 1, st); });
     unsigned long long host[4];
     if (e == hipSuccess)
         e = hipMemcpyAsync(host, sc, sizeof host, hipMemcpyDeviceToHost, st);
@@ -229,15 +227,18 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
     bool converged = eta <= tol;
     while (!converged && iters < max_iter && rmax > 0.0 && std::isfinite(rmax)) {
         const double s = std::ldexp(1.0, (int)std::ceil(std::log2(rmax)));
-        e = other(12.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F32, R, ld, D, ld, m, n, 1.0 / s, st); });
+        const double *Rk = iters == 0 ? R0 : R;
+        e = other(12.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F32, Rk, ld, D, ld, m, n, 1.0 / s, st); });
         if (e != hipSuccess)
             return hip_fail(h, e);
         rc = run_plan(h, lo);
         if (rc != RTRI_OK)
             return rc;
         lo.skip_pack = true;
-        // X += s D, and W = X for the residual's product (one pass)
-        e = other(28.0 * mn, [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, W, ld, st); });
+        // X += s D (X = s D the first time), and W = X for the residual's product (one pass)
+        const bool assign = iters == 0;
+        e = other((assign ? 20.0 : 28.0) * mn,
+                  [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, assign, W, ld, st); });
         if (e != hipSuccess)
             return hip_fail(h, e);
         rc = run_plan(h, mul);
@@ -268,7 +269,9 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
             break;
         eta_prev = eta;
     }
-    e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, X, ld, B, ldb, m, n, 1.0, st); });
+    // no correction made (alpha B is zero, or not finite): X = 0
+    e = iters == 0 ? other(8.0 * mn, [&] { return launch_fill(DType::F64, B, m, n, ldb, 0.0, st); })
+                   : other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, X, ld, B, ldb, m, n, 1.0, st); });
     if (e != hipSuccess)
         return hip_fail(h, e);
     if (info != nullptr) {

@@ -136,6 +136,10 @@ def test_mixed_variants(rt, h, orc, gemm, diag, side, uplo, trans):
     assert info["eta"] <= 1e-12
     # the library's own eta and the oracle's compensated eta describe the same residual
     assert e <= 4 * max(info["eta"], 1e-16)
+    # the norm in that eta: |op(A)|_inf for side L, |op(A)|_1 for side R (each row of X solves with op(A)^T)
+    norm = orc.opnorm_inf if side == "L" else orc.opnorm_one
+    ref = norm(uplo, trans, diag, A)
+    assert abs(info["anorm"] - ref) <= 1e-14 * ref, (info["anorm"], ref)
 
 
 @pytest.mark.parametrize("gemm", ["bf16", "f32"])
@@ -170,6 +174,17 @@ def test_mixed_alpha_zero(rt, h):
     info = rt.trsm_mixed(h, "L", "L", "N", "N", 0.0, A, B)
     torch.cuda.synchronize()
     assert info["converged"] and torch.count_nonzero(B).item() == 0
+
+
+def test_mixed_zero_rhs(rt, h):
+    """alpha B = 0 with alpha != 0: no correction is made and X = 0 is returned."""
+    A = torch.full((40, 40), float("nan"), dtype=torch.float64, device="cuda").t()
+    B = torch.zeros((40, 5), dtype=torch.float64, device="cuda").t().contiguous().t()
+    B.fill_(-0.0)
+    info = rt.trsm_mixed(h, "L", "L", "N", "N", 2.0, A, B)
+    torch.cuda.synchronize()
+    assert info["converged"] and info["iters"] == 0
+    assert torch.all(B == 0) and not torch.any(torch.signbit(B))
 
 
 def test_mixed_8192_sampled(rt, h, orc):
