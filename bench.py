@@ -185,6 +185,11 @@ def main():
     if not args.no_extras:
         out["mixed"] = bench_mixed(rt, torch, h)
         progress("mixed done")
+        out["trmm16"], sample16 = bench_trmm16(rt, torch, h)
+        if not args.no_cpu:
+            cpu_check_trmm16(out["trmm16"], sample16)
+        del sample16
+        progress("16-bit trmm done")
         out["batched"] = bench_batched(rt, torch, h)
         progress("batched done")
         out["serving"] = bench_serving(rt, args.serve_requests)
@@ -346,6 +351,63 @@ def bench_mixed(rt, torch, h, m=8192):
                           "useful_tflops": round(m ** 3 / (t * 1e-3) / 1e12, 3)}
         res["cases"].append(case)
     return res
+
+
+def bench_trmm16(rt, torch, h, m=8192, ns=16):
+    """TRMM with 16-bit inputs and FP32 accumulation, m = n = 8192, L/L/N/N:
+    lower factor with off-diagonal U(-1,1) and diagonal c + U(0,1) (c = 45),
+    B U(-1,1), drawn in FP64 on the device and rounded to BF16 / FP16.  Returns
+    the timings and, for the CPU check, the sampled columns of the inputs and
+    results (the error against the oracle is computed in the CPU leg)."""
+    import synth
+    Ad = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
+    B0 = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
+    rt.synth_fill(h, 1, synth.SEED, synth.W_MIXED, 1, Ad, param=45.0)
+    rt.synth_fill(h, 0, synth.SEED, synth.W_MIXED, 2, B0)
+    idx = np.sort(synth.rng(synth.W_MIXED, 16, 1).choice(m, ns, replace=False))
+    tidx = torch.as_tensor(idx, device="cuda")
+    res = {"workload": f"TRMM L/L/N/N m=n={m}, 16-bit A and B, FP32 accumulation and output; "
+                       "diagonal 45+U(0,1), off-diagonal U(-1,1), B U(-1,1)"}
+    sample = {"idx": idx, "A": rt.to_host(Ad), "B": np.asfortranarray(rt.to_host(B0)[:, idx])}
+    C = torch.empty((m, m), dtype=torch.float32, device="cuda").t()
+    for dt, td in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+        A16 = torch.empty((m, m), dtype=td, device="cuda").t()
+        B16 = torch.empty((m, m), dtype=td, device="cuda").t()
+        A16.copy_(Ad)
+        B16.copy_(B0)
+        t = _event_ms(torch, lambda: rt.trmm_ex(h, "L", "L", "N", "N", 1.0, A16, B16, C))
+        h.profile_begin()
+        rt.trmm_ex(h, "L", "L", "N", "N", 1.0, A16, B16, C)
+        st = {(x["kclass"], x["dtype"]): x for x in h.profile_end()}
+        g = st.get(("gemm", dt))
+        row = {"ms": round(t, 3), "tflops": round(m ** 3 / (t * 1e-3) / 1e12, 3),
+               "fraction_of_peak": round(m ** 3 / (t * 1e-3) / 1e12 / PEAK[dt], 4)}
+        if g is not None:
+            gt = g["flops"] / (g["ms"] * 1e-3) / 1e12
+            row["gemm16"] = {"ms": round(g["ms"], 3), "launches": g["launches"], "tflops": round(gt, 2),
+                             "frac": round(gt / PEAK[dt], 4)}
+        res[dt] = row
+        sample[dt] = {"A": rt.to_host(A16).astype(np.float64),
+                      "B": np.asfortranarray(rt.to_host(B16)[:, idx].astype(np.float64)),
+                      "C": np.asfortranarray(C[:, tidx].cpu().numpy().astype(np.float64))}
+        del A16, B16
+    del Ad, B0, C
+    torch.cuda.empty_cache()
+    return res, sample
+
+
+def cpu_check_trmm16(res, sample):
+    """CPU leg: the 16-bit TRMM's sampled columns against the oracle, both on the
+    original FP64 inputs (the rounding of A and B included) and on the rounded
+    16-bit values widened exactly (the FP32 accumulation alone)."""
+    import oracle
+    for dt in ("bf16", "f16"):
+        s = sample[dt]
+        res[dt]["error_vs_oracle"] = {
+            "columns": int(len(sample["idx"])),
+            "eta_vs_fp64_inputs": oracle.trmm_eta("L", "L", "N", "N", 1.0, sample["A"], sample["B"], s["C"]),
+            "eta_vs_rounded_inputs": oracle.trmm_eta("L", "L", "N", "N", 1.0, s["A"], s["B"], s["C"]),
+        }
 
 
 def bench_batched(rt, torch, h, count=4096):

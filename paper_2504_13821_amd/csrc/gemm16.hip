@@ -11,9 +11,14 @@
 // are rounded to BF16 by design.
 //
 // Layout: 256-thread workgroups, 128x128 tiles, four 64x64 wavefront tiles of
-// 16x16 MFMA blocks, BK = 32 (one MFMA k-step).  Operand tiles are staged in
-// LDS with k contiguous (rows padded to 40 elements, so the 16-byte fragment
-// reads of 16 consecutive rows fall in distinct banks).
+// 16x16 MFMA blocks, BK = 64 (two MFMA k-steps per LDS stage).  Operand tiles
+// are staged in LDS with k contiguous (rows padded to 72 elements, so the
+// 16-byte fragment reads of 8 consecutive rows fall in distinct banks), two
+// stages in LDS and two in registers: the global loads of step k + 2 are in
+// flight while step k is multiplied, since one step of 16-bit MFMA work is too
+// short to cover a memory round trip.  Registers hold the raw loaded values;
+// the FP32 operand is rounded (v_cvt_pk_bf16_f32 / v_cvt_f16_f32, nearest
+// even) when it is written to LDS.
 //
 // MFMA 16x16x32 operand layout (lane l, g = l/16, c = l%16): A operand row c,
 // k = 8g..8g+7; B operand column c, k = 8g..8g+7; D: slot r holds D[4g + r][c].
@@ -26,26 +31,22 @@ namespace rtri {
 namespace {
 
 constexpr int NT = 256;
-constexpr int BK = 32;
+constexpr int BK = 64;
 constexpr int SK = BK + 8;   // padded LDS row (16-bit elements)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-// float -> 16-bit pattern, round to nearest even (NaN stays NaN)
+// float -> 16-bit pattern, round to nearest even (hardware conversion)
 template <bool BF> __device__ __forceinline__ unsigned short to16(float x);
 template <> __device__ __forceinline__ unsigned short to16<true>(float x)
 {
-    const unsigned u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u)
-        return (unsigned short)((u >> 16) | 0x40u);
-    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    return __builtin_bit_cast(unsigned short, (__bf16)x);
 }
 template <> __device__ __forceinline__ unsigned short to16<false>(float x)
 {
-    const _Float16 h = (_Float16)x;   // v_cvt_f16_f32, round to nearest even
-    return __builtin_bit_cast(unsigned short, h);
+    return __builtin_bit_cast(unsigned short, (_Float16)x);
 }
 
 template <bool BF> __device__ __forceinline__ float4_t mfma16(u16x8 a, u16x8 b, float4_t c);
@@ -60,19 +61,20 @@ template <> __device__ __forceinline__ float4_t mfma16<false>(u16x8 a, u16x8 b, 
                                                   0, 0, 0);
 }
 
-// Load one R x BK operand tile into LDS as Ls[row * SK + k] (16-bit).
-//   SRC16: source is 16-bit (P); else FP32 rounded with to16 (Q).
+// One R x BK operand tile: global -> registers (load), registers -> LDS as
+// Ls[row * SK + k] (store).
+//   SRC16: source is 16-bit (P); else FP32, rounded with to16 at the store (Q).
 //   KC:    element (row, k) at base[k + row*ld]; else at base[row + k*ld].
 //   VEC:   16-byte aligned base and ld (8 elements for 16-bit sources, 4 for
 //          FP32): a full tile moves each 8-element chunk (contiguous in memory
 //          in either layout) with 16-byte loads.
-// Each thread moves PER elements; out-of-range elements are zero.
+// Each thread moves NCH chunks of 8 elements; out-of-range elements are zero.
 template <int R, bool SRC16, bool KC, bool BF, bool VEC>
 struct Loader16 {
-    static constexpr int PER = R * BK / NT;   // 16 for R = 128
-    static constexpr int W = 8;               // elements per chunk
-    static constexpr int NCH = PER / W;
-    unsigned short reg[PER];
+    static constexpr int W = 8;                 // elements per chunk
+    static constexpr int NCH = R * BK / NT / W;  // 4 for R = 128
+    u16x8 h[SRC16 ? NCH : 1];                    // raw 16-bit chunks
+    float4_t f[SRC16 ? 1 : 2 * NCH];             // raw FP32 chunks (two halves each)
 
     __device__ inline void coords(int v, int tid, int &row, int &k) const
     {
@@ -94,20 +96,12 @@ struct Loader16 {
                 int row, k;
                 coords(v, tid, row, k);
                 const int64_t off = KC ? k + (int64_t)row * ld : row + (int64_t)k * ld;
-                if (SRC16) {
-                    const u16x8 x = *reinterpret_cast<const u16x8 *>(static_cast<const unsigned short *>(base_) + off);
-#pragma unroll
-                    for (int w = 0; w < W; ++w)
-                        reg[v * W + w] = x[w];
+                if constexpr (SRC16) {
+                    h[v] = *reinterpret_cast<const u16x8 *>(static_cast<const unsigned short *>(base_) + off);
                 } else {
                     const float *fp = static_cast<const float *>(base_) + off;
-                    const float4_t x0 = *reinterpret_cast<const float4_t *>(fp);
-                    const float4_t x1 = *reinterpret_cast<const float4_t *>(fp + 4);
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) {
-                        reg[v * W + w] = to16<BF>(x0[w]);
-                        reg[v * W + 4 + w] = to16<BF>(x1[w]);
-                    }
+                    f[2 * v] = *reinterpret_cast<const float4_t *>(fp);
+                    f[2 * v + 1] = *reinterpret_cast<const float4_t *>(fp + 4);
                 }
             }
             return;
@@ -121,15 +115,25 @@ struct Loader16 {
                 const int rr = KC ? row : row + w;
                 const int kk = KC ? k + w : k;
                 const int64_t off = KC ? kk + (int64_t)rr * ld : rr + (int64_t)kk * ld;
-                unsigned short x = 0;
-                if (full || (rr < rlim && kk < klim)) {
-                    if (SRC16)
-                        x = static_cast<const unsigned short *>(base_)[off];
-                    else
-                        x = to16<BF>(static_cast<const float *>(base_)[off]);
-                }
-                reg[v * W + w] = x;
+                const bool in = full || (rr < rlim && kk < klim);
+                if constexpr (SRC16)
+                    h[v][w] = in ? static_cast<const unsigned short *>(base_)[off] : (unsigned short)0;
+                else
+                    f[2 * v + w / 4][w % 4] = in ? static_cast<const float *>(base_)[off] : 0.0f;
             }
+        }
+    }
+
+    __device__ inline u16x8 chunk(int v) const
+    {
+        if constexpr (SRC16) {
+            return h[v];
+        } else {
+            u16x8 x;
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                x[w] = to16<BF>(f[2 * v + w / 4][w % 4]);
+            return x;
         }
     }
 
@@ -139,20 +143,14 @@ struct Loader16 {
         for (int v = 0; v < NCH; ++v) {
             int row, k;
             coords(v, tid, row, k);
+            const u16x8 x = chunk(v);
             if (KC) {   // 8 consecutive k of one row: one 16-byte LDS write
-                u16x8 x;
-#pragma unroll
-                for (int w = 0; w < W; ++w)
-                    x[w] = reg[v * W + w];
                 *reinterpret_cast<u16x8 *>(lds + row * SK + k) = x;
                 continue;
             }
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const int rr = KC ? row : row + w;
-                const int kk = KC ? k + w : k;
-                lds[rr * SK + kk] = reg[v * W + w];
-            }
+            for (int w = 0; w < W; ++w)
+                lds[(row + w) * SK + k] = x[w];
         }
     }
 };
@@ -195,8 +193,9 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
     const int rlim_n = (int)min<int64_t>(BN, g.N - n0);
     const bool full_mn = rlim_m == BM && rlim_n == BN;
 
-    Loader16<BM, P16, TP, BF, VEC> la;
-    Loader16<BN, !P16, !TQ, BF, VEC> lb;
+    // two register stages per operand: step s lives in la[s & 1] / lb[s & 1]
+    Loader16<BM, P16, TP, BF, VEC> la0, la1;
+    Loader16<BN, !P16, !TQ, BF, VEC> lb0, lb1;
 
     float4_t acc[FM][FN];
 #pragma unroll
@@ -207,7 +206,7 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
 
     const int64_t K = g.K;
     const int nk = (int)((K + BK - 1) / BK);
-    auto load_step = [&](int kt) {
+    auto load_step = [&](int kt, auto &la, auto &lb) {
         const int64_t k0 = (int64_t)kt * BK;
         const PT *pa = TP ? Pt + k0 : Pt + k0 * ldp;
         const QT *pb = TQ ? Qt + k0 * ldq : Qt + k0;
@@ -216,34 +215,52 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
         la.load(pa, ldp, tid, rlim_m, klim, full);
         lb.load(pb, ldq, tid, rlim_n, klim, full);
     };
-
-    if (nk > 0) {
-        load_step(0);
-        la.store(As[0], tid);
-        lb.store(Bs[0], tid);
-    }
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk)
-            load_step(kt + 1);
-        u16x8 fa[FM], fb[FN];
+    auto multiply = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < FM; ++i)
-            fa[i] = *reinterpret_cast<const u16x8 *>(&As[cur][(wm * (BM / 2) + i * 16 + lc) * SK + 8 * lg]);
+        for (int ks = 0; ks < BK / 32; ++ks) {
+            u16x8 fa[FM], fb[FN];
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-            fb[j] = *reinterpret_cast<const u16x8 *>(&Bs[cur][(wn * (BN / 2) + j * 16 + lc) * SK + 8 * lg]);
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
+            for (int i = 0; i < FM; ++i)
+                fa[i] = *reinterpret_cast<const u16x8 *>(
+                    &As[buf][(wm * (BM / 2) + i * 16 + lc) * SK + ks * 32 + 8 * lg]);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
-                acc[i][j] = mfma16<BF>(fa[i], fb[j], acc[i][j]);
+                fb[j] = *reinterpret_cast<const u16x8 *>(
+                    &Bs[buf][(wn * (BN / 2) + j * 16 + lc) * SK + ks * 32 + 8 * lg]);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = mfma16<BF>(fa[i], fb[j], acc[i][j]);
+        }
+    };
+    // One step kt (its operands in LDS buffer kt & 1): issue the loads of step
+    // kt + 2 into the register stage step kt held, multiply, then write step
+    // kt + 1 (registers) to the other LDS buffer.  LA/LB: register stage of
+    // kt (and kt + 2); LA1/LB1: that of kt + 1.
+    auto step = [&](int kt, int buf, auto &LA, auto &LB, auto &LA1, auto &LB1) {
+        if (kt + 2 < nk)
+            load_step(kt + 2, LA, LB);
+        multiply(buf);
         if (kt + 1 < nk) {
-            la.store(As[cur ^ 1], tid);
-            lb.store(Bs[cur ^ 1], tid);
+            LA1.store(As[buf ^ 1], tid);
+            LB1.store(Bs[buf ^ 1], tid);
         }
         __syncthreads();
+    };
+
+    if (nk > 0) {
+        load_step(0, la0, lb0);
+        if (nk > 1)
+            load_step(1, la1, lb1);
+        la0.store(As[0], tid);
+        lb0.store(Bs[0], tid);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; kt += 2) {
+        step(kt, 0, la0, lb0, la1, lb1);
+        if (kt + 1 < nk)
+            step(kt + 1, 1, la1, lb1, la0, lb0);
     }
 
     float *C = static_cast<float *>(g.C);
