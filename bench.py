@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true", help="only the headline step")
+    ap.add_argument("--extras", default="mixed,trmm16,batched,serving,vendor",
+                    help="comma-separated extra sections to run (default: all)")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--tuning", default="", help="tuning database (default: the package's, if present)")
     return ap.parse_args()
@@ -182,18 +184,23 @@ def main():
         progress("cpu baseline done")
     del Ad, Bd, B0d
     torch.cuda.empty_cache()
-    if not args.no_extras:
+    extras = set() if args.no_extras else set(x.strip() for x in args.extras.split(",") if x.strip())
+    if "mixed" in extras:
         out["mixed"] = bench_mixed(rt, torch, h)
         progress("mixed done")
+    if "trmm16" in extras:
         out["trmm16"], sample16 = bench_trmm16(rt, torch, h)
         if not args.no_cpu:
             cpu_check_trmm16(out["trmm16"], sample16)
         del sample16
         progress("16-bit trmm done")
+    if "batched" in extras:
         out["batched"] = bench_batched(rt, torch, h)
         progress("batched done")
+    if "serving" in extras:
         out["serving"] = bench_serving(rt, args.serve_requests)
         progress("serving done")
+    if "vendor" in extras:
         out["vendor_context"] = bench_vendor(rt, torch, h, m)
         progress("vendor context done")
     print(json.dumps(out), flush=True)
@@ -446,8 +453,10 @@ def bench_batched(rt, torch, h, count=4096):
 
 def serving_stream(count, seed_key=0):
     """TRSM 80 % / TRMM 20 %; m log-uniform [32,8192]; nrhs log-uniform [1,512];
-    FP64 or mixed (BF16) 50/50 for TRSM; factors shared by 1-16 requests spread
-    over a 256-request window; uplo and trans 50/50; side L."""
+    FP64 or mixed precision 50/50 for TRSM (refinement around FP32 GEMM updates:
+    two corrections where BF16 updates need four, so fewer launches and FP64
+    residuals per request); factors shared by 1-16 requests spread over a
+    256-request window; uplo and trans 50/50; side L."""
     import numpy as np
     import synth
     g = synth.rng(synth.W_SERVE, 1000, seed_key)
@@ -476,7 +485,7 @@ def serving_stream(count, seed_key=0):
             if j >= count:
                 continue
             op = "trsm" if g.random() < 0.8 else "trmm"
-            prec = (0 if g.random() < 0.5 else 1) if op == "trsm" else 0
+            prec = (0 if g.random() < 0.5 else 2) if op == "trsm" else 0
             reqs[j] = dict(op=op, side="L", uplo=uplo, trans="N" if g.random() < 0.5 else "T", diag="N", m=ka,
                            n=int(synth.loguniform_int(g, 1, 512, 1)[0]), alpha=1.0, precision=prec, factor_id=fid,
                            rhs_id=j + 1)
@@ -495,7 +504,7 @@ def bench_serving(rt, count):
     reqs = serving_stream(count)
     flops = sum(r["m"] * r["m"] * r["n"] for r in reqs)
     res = {"workload": f"{count} requests (TRSM 80%/TRMM 20%, m log-uniform [32,8192], nrhs log-uniform [1,512], "
-                       "FP64 or mixed+IR 50/50 for TRSM, factors shared by 1-16 requests), 64 GB budget",
+                       "FP64 or mixed+IR (FP32 GEMM updates) 50/50 for TRSM, factors shared by 1-16 requests), 64 GB budget",
            "requests": count}
 
     def tag(r):
