@@ -170,7 +170,9 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
  * FP32 (c_type == RTRI_F32), m-by-n with leading dimension ldc.  Every product
  * of two 16-bit values is exact in FP32 and the sums accumulate in FP32, so the
  * result is the FP32-accumulated product of the 16-bit inputs.  C must not
- * overlap A or B; A and B are not modified.
+ * overlap A or B; A and B are not modified.  For side LEFT with trans N (or
+ * RIGHT with trans T) the handle's workspace grows to hold a transposed copy
+ * of A (order x ceil8(order) 16-bit elements), kept until rtri_destroy.
  * Argument codes: -1..-6 as for rtri_dtrmm, -8 A NULL, -9 lda, -10 B NULL,
  * -11 ldb < max(1, m), -12 C NULL, -13 ldc < max(1, m); RTRI_ERR_UNSUPPORTED
  * for any other type combination. */

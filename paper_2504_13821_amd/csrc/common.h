@@ -106,6 +106,8 @@ hipError_t launch_convert(ElemT src, ElemT dst, const void *X, int64_t ldx, void
 // Y = fl_dst(X^T): X is m-by-n FP64, Y is n-by-m (rounded once, as launch_convert)
 hipError_t launch_transpose_convert(ElemT dst, const double *X, int64_t ldx, void *Y, int64_t ldy, int64_t m,
                                     int64_t n, hipStream_t st);
+// Y = X^T for 16-bit X (m-by-n) and Y (n-by-m), bit patterns copied
+hipError_t launch_transpose16(const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st);
 // X += s * D, or X = s * D when assign (X is then not read)   (X FP64, D FP32);
 // then W = X when W != nullptr
 hipError_t launch_add_scaled(double *X, int64_t ldx, const float *D, int64_t ldd, int64_t m, int64_t n, double s,

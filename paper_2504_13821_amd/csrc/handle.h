@@ -93,6 +93,10 @@ int pick_leaf(const rtri_handle *h, DType t, bool solve, int64_t ka, int64_t nve
 // whether a TRMM with this leaf size runs all its leaves in one launch after
 // saving the panel (workspace WS_SAVE, m x n elements)
 bool trmm_one_launch(const rtri_handle *h, int leaf, int64_t ka, int64_t nvec);
+// leading dimension of the refinement's workspace matrices and of the converted
+// copy of A: rows rounded up to 8 elements, so every column starts on a 16-byte
+// boundary and the GEMM kernels take their vector-load paths
+inline int64_t ws_ld(int64_t rows) { return (rows + 7) / 8 * 8; }
 int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, const void *A, int64_t lda,
                const void *B, int64_t ldb, bool need_a);
 // enqueue a whole plan on the handle's stream (returns an RTRI_* status)

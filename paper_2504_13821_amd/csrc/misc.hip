@@ -130,6 +130,26 @@ __global__ __launch_bounds__(NT) void transpose_convert_kernel(const double *X, 
     }
 }
 
+// Y = X^T for 16-bit X (m-by-n) and Y (n-by-m), through 32x32 LDS tiles as above
+__global__ __launch_bounds__(NT) void transpose16_kernel(const unsigned short *X, int64_t ldx, unsigned short *Y,
+                                                         int64_t ldy, int64_t m, int64_t n)
+{
+    __shared__ unsigned short t[32][33];
+    const int64_t tiles_m = (m + 31) / 32;
+    const int64_t i0 = (blockIdx.x % tiles_m) * 32, j0 = (blockIdx.x / tiles_m) * 32;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t i = i0 + tx, j = j0 + r;
+        t[r][tx] = (i < m && j < n) ? X[i + j * ldx] : (unsigned short)0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int64_t yi = j0 + tx, yj = i0 + r;
+        if (yi < n && yj < m)
+            Y[yi + yj * ldy] = t[tx][r];
+    }
+}
+
 template <ElemT S>
 hipError_t convert_from(ElemT dst, const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m, int64_t n,
                         double scale, hipStream_t st)
@@ -438,6 +458,18 @@ hipError_t launch_transpose_convert(ElemT dst, const double *X, int64_t ldx, voi
     case ElemT::BF16: hipLaunchKernelGGL((transpose_convert_kernel<ElemT::BF16>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n); break;
     case ElemT::F16: hipLaunchKernelGGL((transpose_convert_kernel<ElemT::F16>), g, dim3(NT), 0, st, X, ldx, Y, ldy, m, n); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose16(const void *X, int64_t ldx, void *Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st)
+{
+    if (m <= 0 || n <= 0)
+        return hipSuccess;
+    const int64_t tiles = ((m + 31) / 32) * ((n + 31) / 32);
+    if (tiles > INT32_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(transpose16_kernel, dim3((unsigned)tiles), dim3(NT), 0, st,
+                       static_cast<const unsigned short *>(X), ldx, static_cast<unsigned short *>(Y), ldy, m, n);
     return hipGetLastError();
 }
 

@@ -63,11 +63,30 @@ int rtri_trmm_ex(rtri_handle *h, int side, int uplo, int trans, int diag, int64_
               [&] { return launch_convert(et, ElemT::F32, B, ldb, C, ldc, m, n, 1.0, h->stream); });
     if (e != hipSuccess)
         return hip_fail(h, e);
+    // The 16-bit GEMM reads its triangle operand fastest with k contiguous: for
+    // side L and trans N (or side R and trans T) its GEMM updates read a
+    // transposed copy of A (handle workspace), as the refined solve does.
+    const int tr = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    const bool left = side == RTRI_LEFT;
+    const int64_t ka = left ? m : n;
+    const bool ag_trans = left ? tr == RTRI_NOTRANS : tr != RTRI_NOTRANS;
+    const void *Ag = A;
+    int64_t ldag = lda;
+    if (ag_trans) {
+        ldag = ws_ld(ka);
+        e = ensure_ws(h, WS_ACOPY, (size_t)ka * (size_t)ldag * 2);
+        if (e == hipSuccess)
+            e = timed(h, RTRI_KCLASS_OTHER, a_type, 0.0, 4.0 * ka * ka,
+                      [&] { return launch_transpose16(A, lda, h->ws[WS_ACOPY], ldag, ka, ka, h->stream); });
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        Ag = h->ws[WS_ACOPY];
+    }
     PlanIn p{};
     p.solve = false;
     p.side = side;
     p.uplo = uplo;
-    p.trans = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    p.trans = tr;
     p.diag = diag;
     p.m = m;
     p.n = n;
@@ -76,8 +95,9 @@ int rtri_trmm_ex(rtri_handle *h, int side, int uplo, int trans, int diag, int64_
     p.B = static_cast<char *>(C);
     p.ldb = ldc;
     p.gt = et;
-    p.Ag = static_cast<const char *>(A);
-    p.ldag = lda;
+    p.Ag = static_cast<const char *>(Ag);
+    p.ldag = ldag;
+    p.ag_trans = ag_trans;
     p.st = et;
     p.As = A;
     p.ldas = lda;
@@ -125,7 +145,9 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
     const ElemT gt = gemm_type == RTRI_BF16 ? ElemT::BF16 : ElemT::F32;
     const size_t mn = (size_t)m * (size_t)n;
 
-    const size_t need[] = {(size_t)ka * ka * elem_size(gt), mn * 4, mn * 8, mn * 8, mn * 8, mn * 8, 64};
+    const int64_t ld = ws_ld(m), ldag = ws_ld(ka);
+    const size_t ln = (size_t)ld * (size_t)n;
+    const size_t need[] = {(size_t)ka * (size_t)ldag * elem_size(gt), ln * 4, ln * 8, ln * 8, ln * 8, ln * 8, 64};
     const int slot[] = {WS_ACOPY, WS_PANEL32, WS_X, WS_R0, WS_R, WS_W, WS_SCALARS};
     for (int i = 0; i < 7; ++i) {
         e = ensure_ws(h, slot[i], need[i]);
@@ -139,7 +161,6 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
     double *R = static_cast<double *>(h->ws[WS_R]);
     double *W = static_cast<double *>(h->ws[WS_W]);
     unsigned long long *sc = static_cast<unsigned long long *>(h->ws[WS_SCALARS]);
-    const int64_t ld = m;
 
     // once per call: the GEMM copy of A, |op(A)|, alpha B, X = 0, max |R|
     auto other = [&](double bytes, auto &&f) { return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, bytes, f); };
@@ -148,8 +169,8 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
     // trans T, the BF16 copy holds A^T.
     const bool ag_trans = gt == ElemT::BF16 && (left ? tr == RTRI_NOTRANS : tr != RTRI_NOTRANS);
     e = other(8.0 * ka * ka, [&] {
-        return ag_trans ? launch_transpose_convert(gt, A, lda, Acopy, ka, ka, ka, st)
-                        : launch_convert(ElemT::F64, gt, A, lda, Acopy, ka, ka, ka, 1.0, st);
+        return ag_trans ? launch_transpose_convert(gt, A, lda, Acopy, ldag, ka, ka, st)
+                        : launch_convert(ElemT::F64, gt, A, lda, Acopy, ldag, ka, ka, 1.0, st);
     });
     if (e == hipSuccess)
         e = launch_zero_u64(sc, 4, st);
@@ -191,7 +212,7 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
     lo.ldb = ld;
     lo.gt = gt;
     lo.Ag = static_cast<const char *>(Acopy);
-    lo.ldag = ka;
+    lo.ldag = ldag;
     lo.ag_trans = ag_trans;
     lo.st = ElemT::F64;
     lo.As = A;

@@ -118,7 +118,8 @@ size_t ws_bound(const rtri_request &r, int64_t ka)
     // a TRMM (and the residual product of a mixed solve) may save its panel (mn * 8)
     if (r.precision == RTRI_PREC_F64)
         return 8 * pack + WS_MIN + (r.op == 1 ? mn * 8 + WS_MIN : 0);
-    return (size_t)ka * ka * 4 + mn * (4 + 8 * 5) + 12 * pack + 10 * WS_MIN;
+    const size_t ln = (size_t)ws_ld(r.m) * (size_t)r.n;
+    return (size_t)ka * (size_t)ws_ld(ka) * 4 + ln * (4 + 8 * 4) + mn * 8 + 12 * pack + 10 * WS_MIN;
 }
 
 // device memory the slot's handle allocates to run q alone: for every
@@ -142,10 +143,11 @@ size_t alone_growth(const rtri_handle *h, const Req &q)
         if (r.op == 1)
             need[WS_SAVE] = save_bytes();
     } else {
-        const size_t mn = (size_t)r.m * (size_t)r.n;
-        need[WS_ACOPY] = (size_t)q.ka * q.ka * (r.precision == RTRI_PREC_MIXED_BF16 ? 2 : 4);
-        need[WS_PANEL32] = mn * 4;
-        need[WS_X] = need[WS_R0] = need[WS_R] = need[WS_W] = mn * 8;
+        // the refinement's matrices use the padded leading dimension ws_ld
+        const size_t ln = (size_t)ws_ld(r.m) * (size_t)r.n;
+        need[WS_ACOPY] = (size_t)q.ka * (size_t)ws_ld(q.ka) * (r.precision == RTRI_PREC_MIXED_BF16 ? 2 : 4);
+        need[WS_PANEL32] = ln * 4;
+        need[WS_X] = need[WS_R0] = need[WS_R] = need[WS_W] = ln * 8;
         need[WS_SCALARS] = 64;
         need[WS_PACK2] = pack_bytes(DType::F32, true);
         need[WS_PACK] = pack_bytes(DType::F64, false);
