@@ -83,8 +83,9 @@ enum class ElemT { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 inline size_t elem_size(ElemT t) { return t == ElemT::F64 ? 8 : t == ElemT::F32 ? 4 : 2; }
 
 hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st);
-// 16-bit GEMM: the 16-bit operand is P (p16) or Q (!p16); the other operand and C are FP32
-hipError_t launch_gemm16(bool bf16, bool p16, const GemmDesc &g, hipStream_t st);
+// 16-bit GEMM: P is 16-bit when p16 (else FP32), Q when q16 (at least one of
+// them); C is FP32
+hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st);
 // pack diagonal blocks read from A of type src into packed triangles of type dst
 hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);

@@ -64,12 +64,19 @@ struct Planner {
     // before all leaves run in one launch
     const char *src = nullptr;
     int64_t ldsrc = 0;
+    size_t ses = 0;   // element size of src
 
     explicit Planner(const PlanIn &pr) : p(pr)
     {
         es = p.bt == DType::F64 ? 8 : 4;
         src = p.B;
         ldsrc = p.ldb;
+        ses = es;
+        if (!p.solve && p.Bsrc16 != nullptr) {
+            src = p.Bsrc16;
+            ldsrc = p.ldbsrc16;
+            ses = 2;
+        }
         low = (p.uplo == RTRI_LOWER) != (p.trans != RTRI_NOTRANS);
         const bool fwd_solve = p.side == RTRI_LEFT ? low : !low;
         forward = p.solve ? fwd_solve : !fwd_solve;
@@ -120,14 +127,14 @@ struct Planner {
             g.P = tri_block(p, t0, s0);
             g.ldp = p.ldag;
             g.tp = tr;
-            g.Q = (p.solve ? p.B : src) + s0 * (int64_t)es;
+            g.Q = p.solve ? p.B + s0 * (int64_t)es : src + s0 * (int64_t)ses;
             g.ldq = p.solve ? p.ldb : ldsrc;
             g.tq = false;
             g.C = p.B + t0 * (int64_t)es;
         } else {
             g.M = p.m;
             g.N = th;
-            g.P = p.solve ? p.B + s0 * p.ldb * (int64_t)es : src + s0 * ldsrc * (int64_t)es;
+            g.P = p.solve ? p.B + s0 * p.ldb * (int64_t)es : src + s0 * ldsrc * (int64_t)ses;
             g.ldp = p.solve ? p.ldb : ldsrc;
             g.tp = false;
             g.Q = tri_block(p, s0, t0);
@@ -355,7 +362,9 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     // first; every update sees the same operands as in recursion order
     const int64_t nvec_all = p.side == RTRI_LEFT ? p.n : p.m;
     const bool one = !p.solve && trmm_one_launch(h, p.leaf, ka, nvec_all);
-    if (one) {
+    // a TRMM whose updates read the 16-bit original needs no saved copy
+    const bool save = one && p.Bsrc16 == nullptr;
+    if (save) {
         hipError_t e0 = ensure_ws(h, WS_SAVE, (size_t)p.m * (size_t)p.n * es);
         if (e0 != hipSuccess)
             return hip_fail(h, e0);
@@ -397,16 +406,22 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     const size_t ges = elem_size(p.gt);
     // one GEMM update on a stream: 16-bit factor copy or panel-type MFMA tiles
     auto launch_update = [&](const GemmDesc &g, hipStream_t st) {
-        if (g16)
-            return launch_gemm16(p.gt == ElemT::BF16, p.side == RTRI_LEFT, g, st);
+        if (g16) {
+            // the factor's block is 16-bit; the panel operand too when a TRMM reads the 16-bit original
+            const bool panel16 = !p.solve && p.Bsrc16 != nullptr;
+            const bool left = p.side == RTRI_LEFT;
+            return launch_gemm16(p.gt == ElemT::BF16, left || panel16, !left || panel16, g, st);
+        }
         const int tile = pick_tile(h, pcode, g.M, g.N);
         return launch_gemm(bt, g, tile, st);
     };
     if (one) {
-        hipError_t e = timed(h, RTRI_KCLASS_OTHER, pcode, 0.0, 2.0 * es * p.m * p.n, [&] {
-            return hipMemcpy2DAsync(h->ws[WS_SAVE], p.m * es, p.B, p.ldb * es, p.m * es, p.n,
-                                    hipMemcpyDeviceToDevice, h->stream);
-        });
+        hipError_t e = hipSuccess;
+        if (save)
+            e = timed(h, RTRI_KCLASS_OTHER, pcode, 0.0, 2.0 * es * p.m * p.n, [&] {
+                return hipMemcpy2DAsync(h->ws[WS_SAVE], p.m * es, p.B, p.ldb * es, p.m * es, p.n,
+                                        hipMemcpyDeviceToDevice, h->stream);
+            });
         if (e != hipSuccess)
             return hip_fail(h, e);
         LeafDesc all{};
@@ -453,7 +468,8 @@ int run_plan(rtri_handle *h, const PlanIn &p)
             continue;
         if (op.gemm) {
             const bool left = p.side == RTRI_LEFT;
-            const double bytes = gemm_bytes(op.g, left ? ges : es, left ? es : ges, es);
+            const size_t pes = (p.solve || p.Bsrc16 == nullptr) ? es : 2;   // panel operand as read
+            const double bytes = gemm_bytes(op.g, left ? ges : pes, left ? pes : ges, es);
             e = timed(h, RTRI_KCLASS_GEMM, g16 ? dtype_code(p.gt) : pcode, gemm_flops(op.g), bytes,
                       [&] { return launch_update(op.g, h->stream); });
         } else {

@@ -1,14 +1,14 @@
 // 16-bit GEMM update for the low-precision paths:
 //     C(MxN) = beta * C + s * op(P)(MxK) * op(Q)(KxN)
-// One of P, Q (the triangular factor's block) is stored in BF16 or FP16; the
-// other (a block of the right-hand side) and C are FP32 in memory, and that
-// operand is rounded to the 16-bit type (round to nearest even) as it is
-// loaded; products accumulate in FP32 (v_mfma_f32_16x16x32_bf16 / _f16).
+// The triangular factor's block is stored in BF16 or FP16; the other operand
+// (a block of the right-hand side) is 16-bit too or FP32, rounded to the 16-bit
+// type (round to nearest even) on its way to LDS; C is FP32 and products
+// accumulate in FP32 (v_mfma_f32_16x16x32_bf16 / _f16).
 //
-// Used by (a) the TRMM with 16-bit inputs, where the Q block read by every
-// GEMM still holds original 16-bit values so the rounding is exact, and (b)
-// the low-precision solve inside the mixed-precision TRSM, whose GEMM operands
-// are rounded to BF16 by design.
+// Used by (a) the TRMM with 16-bit inputs, whose updates read the original
+// 16-bit right-hand side (both operands 16-bit), and (b) the low-precision
+// solve inside the mixed-precision TRSM, whose FP32 panel is rounded to BF16
+// by design.
 //
 // Layout: 256-thread workgroups, 128x128 tiles, four 64x64 wavefront tiles of
 // 16x16 MFMA blocks, BK = 64 (two MFMA k-steps per LDS stage).  Operand tiles
@@ -155,7 +155,7 @@ struct Loader16 {
     }
 };
 
-template <int BM, int BN, bool TP, bool TQ, bool BF, bool P16, bool VEC>
+template <int BM, int BN, bool TP, bool TQ, bool BF, bool P16, bool Q16, bool VEC>
 __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, int tiles_n)
 {
     constexpr int FM = BM / 32, FN = BN / 32;
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
     const int lc = lane % 16, lg = lane / 16;
 
     using PT = typename std::conditional<P16, unsigned short, float>::type;
-    using QT = typename std::conditional<P16, float, unsigned short>::type;
+    using QT = typename std::conditional<Q16, unsigned short, float>::type;
     const PT *P = static_cast<const PT *>(g.P);
     const QT *Q = static_cast<const QT *>(g.Q);
     const int64_t ldp = g.ldp, ldq = g.ldq;
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
 
     // two register stages per operand: step s lives in la[s & 1] / lb[s & 1]
     Loader16<BM, P16, TP, BF, VEC> la0, la1;
-    Loader16<BN, !P16, !TQ, BF, VEC> lb0, lb1;
+    Loader16<BN, Q16, !TQ, BF, VEC> lb0, lb1;
 
     float4_t acc[FM][FN];
 #pragma unroll
@@ -289,41 +289,49 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
-template <bool TP, bool TQ, bool BF, bool P16>
+template <bool TP, bool TQ, bool BF, bool P16, bool Q16>
 hipError_t launch_t16(const GemmDesc &g, hipStream_t st)
 {
     constexpr int BM = 128, BN = 128;
     const int tm = (int)((g.M + BM - 1) / BM), tn = (int)((g.N + BN - 1) / BN);
-    // 16-byte chunks: 8 elements of the 16-bit operand, 4 of the FP32 one
-    const int64_t lp = P16 ? 8 : 4, lq = P16 ? 4 : 8;
+    // 16-byte chunks: 8 elements of a 16-bit operand, 4 of an FP32 one
+    const int64_t lp = P16 ? 8 : 4, lq = Q16 ? 8 : 4;
     const bool vec = aligned16(g.P) && aligned16(g.Q) && g.ldp % lp == 0 && g.ldq % lq == 0;
     if (vec)
-        hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16, true>), dim3((unsigned)(tm * tn)), dim3(NT), 0, st,
-                           g, tm, tn);
+        hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16, Q16, true>), dim3((unsigned)(tm * tn)), dim3(NT),
+                           0, st, g, tm, tn);
     else
-        hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16, false>), dim3((unsigned)(tm * tn)), dim3(NT), 0,
-                           st, g, tm, tn);
+        hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16, Q16, false>), dim3((unsigned)(tm * tn)),
+                           dim3(NT), 0, st, g, tm, tn);
     return hipGetLastError();
 }
 
-template <bool BF, bool P16>
+template <bool BF, bool P16, bool Q16>
 hipError_t launch_bf(const GemmDesc &g, hipStream_t st)
 {
-    if (!g.tp && !g.tq) return launch_t16<false, false, BF, P16>(g, st);
-    if (g.tp && !g.tq) return launch_t16<true, false, BF, P16>(g, st);
-    if (!g.tp && g.tq) return launch_t16<false, true, BF, P16>(g, st);
-    return launch_t16<true, true, BF, P16>(g, st);
+    if (!g.tp && !g.tq) return launch_t16<false, false, BF, P16, Q16>(g, st);
+    if (g.tp && !g.tq) return launch_t16<true, false, BF, P16, Q16>(g, st);
+    if (!g.tp && g.tq) return launch_t16<false, true, BF, P16, Q16>(g, st);
+    return launch_t16<true, true, BF, P16, Q16>(g, st);
+}
+
+template <bool BF>
+hipError_t launch_types(bool p16, bool q16, const GemmDesc &g, hipStream_t st)
+{
+    if (p16 && q16)
+        return launch_bf<BF, true, true>(g, st);
+    return p16 ? launch_bf<BF, true, false>(g, st) : launch_bf<BF, false, true>(g, st);
 }
 
 }  // namespace
 
-hipError_t launch_gemm16(bool bf16, bool p16, const GemmDesc &g, hipStream_t st)
+hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st)
 {
+    if (!p16 && !q16)
+        return hipErrorInvalidValue;
     if (g.M <= 0 || g.N <= 0)
         return hipSuccess;
-    if (bf16)
-        return p16 ? launch_bf<true, true>(g, st) : launch_bf<true, false>(g, st);
-    return p16 ? launch_bf<false, true>(g, st) : launch_bf<false, false>(g, st);
+    return bf16 ? launch_types<true>(p16, q16, g, st) : launch_types<false>(p16, q16, g, st);
 }
 
 }  // namespace rtri

@@ -58,6 +58,11 @@ struct PlanIn {
     int leaf;
     int pack_slot;                 // workspace slot holding the packed blocks
     bool skip_pack;                // the packed blocks are already in pack_slot
+    // TRMM with a 16-bit GEMM copy of A: the original panel in that 16-bit type
+    // (the panel B holds it widened), read by the GEMM updates in place of the
+    // panel or its saved copy; nullptr otherwise
+    const char *Bsrc16;
+    int64_t ldbsrc16;
 };
 
 }  // namespace rtri

@@ -98,6 +98,8 @@ int rtri_trmm_ex(rtri_handle *h, int side, int uplo, int trans, int diag, int64_
     p.Ag = static_cast<const char *>(Ag);
     p.ldag = ldag;
     p.ag_trans = ag_trans;
+    p.Bsrc16 = static_cast<const char *>(B);   // the updates read the 16-bit original of C
+    p.ldbsrc16 = ldb;
     p.st = et;
     p.As = A;
     p.ldas = lda;
