@@ -82,7 +82,18 @@ enum class DType { F64, F32 };
 enum class ElemT { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 inline size_t elem_size(ElemT t) { return t == ElemT::F64 ? 8 : t == ElemT::F32 ? 4 : 2; }
 
-hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st);
+// Split K of one FP64 / FP32 update: slices (>= 2) of kslice values along K,
+// partial products in part (slices * ldpart * N elements of the panel type)
+struct Split {
+    int slices = 0;
+    int64_t kslice = 0, ldpart = 0;
+    void *part = nullptr;
+};
+constexpr int64_t SPLIT_MIN_K = 1024;   // shorter updates never split
+// the split for an update with fewer 64x64 tiles than CUs and K >= SPLIT_MIN_K
+// whose partials fit in cap bytes (slices = 0: none); part is left unset
+Split plan_split(DType t, const GemmDesc &g, int tile, size_t cap);
+hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st, const Split &sp = Split{});
 // 16-bit GEMM: P is 16-bit when p16 (else FP32), Q when q16 (at least one of
 // them); C is FP32
 hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st);

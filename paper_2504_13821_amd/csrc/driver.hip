@@ -404,6 +404,28 @@ int run_plan(rtri_handle *h, const PlanIn &p)
 
     const bool g16 = p.gt == ElemT::BF16 || p.gt == ElemT::F16;
     const size_t ges = elem_size(p.gt);
+    // updates short of tiles with a long K split K (partials in workspace, one
+    // region per stream, since one depth's TRMM updates may run concurrently)
+    bool any_split = false;
+    if (!g16 && may_split(ka))
+        for (const Op &op : pl.ops)
+            if (op.gemm && plan_split(bt, op.g, pick_tile(h, pcode, op.g.M, op.g.N), SPLIT_REGION_BYTES).slices >= 2)
+                any_split = true;
+    if (any_split) {
+        hipError_t e0 = ensure_ws(h, WS_SPLIT, SPLIT_WS_BYTES);
+        if (e0 != hipSuccess)
+            return hip_fail(h, e0);
+    }
+    auto split_region = [&](hipStream_t st) -> void * {
+        int r = 0;
+        if (st != h->stream)
+            for (int i = 0; i < 4; ++i)
+                if (h->aux_ready && st == h->aux[i])
+                    r = i + 1;
+        if (r == 0 && st != h->stream)
+            return nullptr;   // unknown stream: no split
+        return static_cast<char *>(h->ws[WS_SPLIT]) + (size_t)r * SPLIT_REGION_BYTES;
+    };
     // one GEMM update on a stream: 16-bit factor copy or panel-type MFMA tiles
     auto launch_update = [&](const GemmDesc &g, hipStream_t st) {
         if (g16) {
@@ -413,7 +435,12 @@ int run_plan(rtri_handle *h, const PlanIn &p)
             return launch_gemm16(p.gt == ElemT::BF16, left || panel16, !left || panel16, g, st);
         }
         const int tile = pick_tile(h, pcode, g.M, g.N);
-        return launch_gemm(bt, g, tile, st);
+        Split sp{};
+        if (any_split) {
+            sp = plan_split(bt, g, tile, SPLIT_REGION_BYTES);
+            sp.part = sp.slices >= 2 ? split_region(st) : nullptr;
+        }
+        return launch_gemm(bt, g, tile, st, sp);
     };
     if (one) {
         hipError_t e = hipSuccess;

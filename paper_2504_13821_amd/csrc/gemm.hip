@@ -28,10 +28,26 @@ using namespace gk;
 // made of 16 x 16 MFMA blocks.
 // Two workgroups per CU: 2 wavefronts per SIMD with 4-wavefront tiles, 4 with
 // 8-wavefront tiles (at most 128 registers each).
+//
+// Split K (kslice > 0): grid row y computes the K range [y*kslice, (y+1)*kslice)
+// into its own partial product part + y*ldpart*N (leading dimension ldpart,
+// beta 0, s 1); split_reduce_kernel then forms C = beta*C + s*(sum of the
+// partials in y order).
 template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(WM * WN / 2))) void
-gemm_kernel(GemmDesc g, int tiles_m, int tiles_n)
+gemm_kernel(GemmDesc g, int tiles_m, int tiles_n, int64_t kslice, T *part, int64_t ldpart)
 {
+    if (kslice > 0) {
+        const int64_t k0 = (int64_t)blockIdx.y * kslice;
+        const T *P = static_cast<const T *>(g.P), *Q = static_cast<const T *>(g.Q);
+        g.P = P + (TP ? k0 : k0 * g.ldp);
+        g.Q = Q + (TQ ? k0 * g.ldq : k0);
+        g.K = min(kslice, g.K - k0);
+        g.C = part + (int64_t)blockIdx.y * ldpart * g.N;
+        g.ldc = ldpart;
+        g.beta = 0.0;
+        g.s = 1.0;
+    }
     constexpr bool KCA = TP, KCB = !TQ;
     __shared__ __attribute__((aligned(16))) T As[2 * lds_elems<T, BM, KCA>()];
     __shared__ __attribute__((aligned(16))) T Bs[2 * lds_elems<T, BN, KCB>()];
@@ -57,53 +73,127 @@ gemm_kernel(GemmDesc g, int tiles_m, int tiles_n)
                                                                            As, Bs);
 }
 
+// C = beta*C + s*(part_0 + part_1 + ... + part_{S-1}), partials added in order
+template <typename T>
+__global__ __launch_bounds__(256) void split_reduce_kernel(const T *part, int S, int64_t ldpart, int64_t M, int64_t N,
+                                                           T *C, int64_t ldc, T beta, T s)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= M)
+        return;
+    for (int64_t j = blockIdx.y; j < N; j += gridDim.y) {
+        const T *p = part + i + j * ldpart;
+        T acc = p[0];
+        for (int y = 1; y < S; ++y)
+            acc += p[(int64_t)y * ldpart * N];
+        const T v = s * acc;
+        T *c = C + i + j * ldc;
+        *c = beta == T(0) ? v : fmat(beta, *c, v);
+    }
+}
+
 template <typename T, int BM, int BN, int WM, int WN, bool TP, bool TQ>
-hipError_t launch_t(const GemmDesc &g, bool vec, hipStream_t st)
+hipError_t launch_t(const GemmDesc &g, bool vec, const Split &sp, hipStream_t st)
 {
     const int tm = (int)((g.M + BM - 1) / BM), tn = (int)((g.N + BN - 1) / BN);
-    const dim3 grid((unsigned)(tm * tn)), block(64 * WM * WN);
+    const dim3 grid((unsigned)(tm * tn), (unsigned)std::max(1, sp.slices)), block(64 * WM * WN);
+    T *part = static_cast<T *>(sp.part);
     if (vec)
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TP, TQ, true, WM, WN>), grid, block, 0, st, g, tm, tn);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TP, TQ, true, WM, WN>), grid, block, 0, st, g, tm, tn, sp.kslice,
+                           part, sp.ldpart);
     else
-        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TP, TQ, false, WM, WN>), grid, block, 0, st, g, tm, tn);
+        hipLaunchKernelGGL((gemm_kernel<T, BM, BN, TP, TQ, false, WM, WN>), grid, block, 0, st, g, tm, tn, sp.kslice,
+                           part, sp.ldpart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || sp.slices < 2)
+        return e;
+    const dim3 rg((unsigned)((g.M + 255) / 256), (unsigned)std::min<int64_t>(g.N, 65535));
+    hipLaunchKernelGGL(split_reduce_kernel<T>, rg, dim3(256), 0, st, static_cast<const T *>(part), sp.slices,
+                       sp.ldpart, g.M, g.N, static_cast<T *>(g.C), g.ldc, (T)g.beta, (T)g.s);
     return hipGetLastError();
 }
 
 template <typename T, int BM, int BN, int WM = 2, int WN = 2>
-hipError_t launch_tile(const GemmDesc &g, bool vec, hipStream_t st)
+hipError_t launch_tile(const GemmDesc &g, bool vec, const Split &sp, hipStream_t st)
 {
-    if (!g.tp && !g.tq) return launch_t<T, BM, BN, WM, WN, false, false>(g, vec, st);
-    if (g.tp && !g.tq) return launch_t<T, BM, BN, WM, WN, true, false>(g, vec, st);
-    if (!g.tp && g.tq) return launch_t<T, BM, BN, WM, WN, false, true>(g, vec, st);
-    return launch_t<T, BM, BN, WM, WN, true, true>(g, vec, st);
+    if (!g.tp && !g.tq) return launch_t<T, BM, BN, WM, WN, false, false>(g, vec, sp, st);
+    if (g.tp && !g.tq) return launch_t<T, BM, BN, WM, WN, true, false>(g, vec, sp, st);
+    if (!g.tp && g.tq) return launch_t<T, BM, BN, WM, WN, false, true>(g, vec, sp, st);
+    return launch_t<T, BM, BN, WM, WN, true, true>(g, vec, sp, st);
 }
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+int auto_tile(const GemmDesc &g)
+{
+    // 128x128 tiles of 8 wavefronts (4 per SIMD with 2 workgroups per CU) once
+    // they fill the chip's 512 workgroup slots; smaller problems run 64x64
+    // tiles (measured faster up to M = 256 at N = 16384)
+    const int64_t big = ((g.M + 127) / 128) * ((g.N + 127) / 128);
+    return big >= 512 ? 3 : 2;
+}
+
+}  // namespace
+
+Split plan_split(DType t, const GemmDesc &g, int tile, size_t cap)
+{
+    Split sp{};
+    if (g.M <= 0 || g.N <= 0 || g.K < SPLIT_MIN_K)
+        return sp;
+    if ((tile == 0 ? auto_tile(g) : tile) != 2)
+        return sp;
+    // an update short of tiles (fewer 64x64 tiles than CUs) with a long K:
+    // aim at ~512 workgroups, slices of at least 512 along K (multiples of 64)
+    const int64_t tiles = ((g.M + 63) / 64) * ((g.N + 63) / 64);
+    if (tiles >= 256)
+        return sp;
+    const size_t es = t == DType::F64 ? 8 : 4;
+    const int64_t ldpart = (g.M + 7) / 8 * 8;   // 16-byte aligned columns
+    int64_t s = std::min<int64_t>({8, std::max<int64_t>(1, 512 / tiles), g.K / 512});
+    while (s >= 2) {
+        const int64_t ks = ((g.K + s - 1) / s + 63) / 64 * 64;
+        const int64_t n = (g.K + ks - 1) / ks;
+        if (n >= 2 && (size_t)n * (size_t)ldpart * (size_t)g.N * es <= cap) {
+            sp.slices = (int)n;
+            sp.kslice = ks;
+            sp.ldpart = ldpart;
+            return sp;
+        }
+        --s;
+    }
+    return sp;
+}
+
+namespace {
+
+template <typename T>
+hipError_t launch_typed(const GemmDesc &g, int tile, bool vec, const Split &sp, hipStream_t st)
+{
+    return tile == 1   ? launch_tile<T, 128, 128>(g, vec, sp, st)
+           : tile == 3 ? launch_tile<T, 128, 128, 2, 4>(g, vec, sp, st)
+                       : launch_tile<T, 64, 64>(g, vec, sp, st);
+}
+
 }  // namespace
 
 // tile: 1 = 128x128 (4 wavefronts), 2 = 64x64, 3 = 128x128 (8 wavefronts of
-// 64x32), 0 = pick by problem size
-hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st)
+// 64x32), 0 = pick by problem size.  A split (from plan_split, with sp.part
+// set to at least slices * ldpart * N elements) runs 64x64 tiles over slices
+// of K and a reduction pass.
+hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st, const Split &sp)
 {
     if (g.M <= 0 || g.N <= 0)
         return hipSuccess;
     const int64_t w = t == DType::F64 ? 2 : 4;
     const bool vec = aligned16(g.P) && aligned16(g.Q) && g.ldp % w == 0 && g.ldq % w == 0;
-    if (tile == 0) {
-        // 128x128 tiles of 8 wavefronts (4 per SIMD with 2 workgroups per CU)
-        // once they fill the chip's 512 workgroup slots; smaller problems run
-        // 64x64 tiles (measured faster up to M = 256 at N = 16384)
-        const int64_t big = ((g.M + 127) / 128) * ((g.N + 127) / 128);
-        tile = big >= 512 ? 3 : 2;
-    }
-    if (t == DType::F64)
-        return tile == 1   ? launch_tile<double, 128, 128>(g, vec, st)
-               : tile == 3 ? launch_tile<double, 128, 128, 2, 4>(g, vec, st)
-                           : launch_tile<double, 64, 64>(g, vec, st);
-    return tile == 1   ? launch_tile<float, 128, 128>(g, vec, st)
-           : tile == 3 ? launch_tile<float, 128, 128, 2, 4>(g, vec, st)
-                       : launch_tile<float, 64, 64>(g, vec, st);
+    Split s = sp;
+    if (s.slices >= 2 && s.part != nullptr)
+        tile = 2;
+    else
+        s = Split{};
+    if (tile == 0)
+        tile = auto_tile(g);
+    return t == DType::F64 ? launch_typed<double>(g, tile, vec, s, st) : launch_typed<float>(g, tile, vec, s, st);
 }
 
 }  // namespace rtri

@@ -34,6 +34,7 @@ enum WsSlot {
     WS_W,            // FP64 op(A) * X
     WS_SCALARS,      // small reduction results
     WS_SAVE,         // copy of a TRMM panel's original values (all leaves in one launch)
+    WS_SPLIT,        // split-K partial products, one region per stream an update may run on
     WS_COUNT
 };
 
@@ -102,6 +103,14 @@ bool trmm_one_launch(const rtri_handle *h, int leaf, int64_t ka, int64_t nvec);
 // copy of A: rows rounded up to 8 elements, so every column starts on a 16-byte
 // boundary and the GEMM kernels take their vector-load paths
 inline int64_t ws_ld(int64_t rows) { return (rows + 7) / 8 * 8; }
+// split-K workspace: one region for the handle's stream and one per auxiliary stream
+constexpr size_t SPLIT_REGION_BYTES = (size_t)16 << 20;
+constexpr int SPLIT_REGIONS = 5;
+constexpr size_t SPLIT_WS_BYTES = SPLIT_REGION_BYTES * SPLIT_REGIONS;
+// whether some update of an order-ka recursion may split K: the longest K is
+// the top split, leaf * ceil(ka / (2 leaf)), which reaches SPLIT_MIN_K only
+// for ka > 2 SPLIT_MIN_K - 2 leaf (leaf <= 256)
+inline bool may_split(int64_t ka) { return ka > 2 * SPLIT_MIN_K - 512; }
 int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, const void *A, int64_t lda,
                const void *B, int64_t ldb, bool need_a);
 // enqueue a whole plan on the handle's stream (returns an RTRI_* status)

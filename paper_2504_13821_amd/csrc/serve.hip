@@ -116,10 +116,11 @@ size_t ws_bound(const rtri_request &r, int64_t ka)
     const size_t mn = (size_t)r.m * (size_t)r.n;
     const size_t pack = (size_t)((ka + 255) / 256 + 1) * (size_t)pack_elems(256) + (size_t)ka * 136;
     // a TRMM (and the residual product of a mixed solve) may save its panel (mn * 8)
+    const size_t split = may_split(ka) ? SPLIT_WS_BYTES : 0;
     if (r.precision == RTRI_PREC_F64)
-        return 8 * pack + WS_MIN + (r.op == 1 ? mn * 8 + WS_MIN : 0);
+        return 8 * pack + WS_MIN + (r.op == 1 ? mn * 8 + WS_MIN : 0) + split;
     const size_t ln = (size_t)ws_ld(r.m) * (size_t)r.n;
-    return (size_t)ka * (size_t)ws_ld(ka) * 4 + ln * (4 + 8 * 4) + mn * 8 + 12 * pack + 10 * WS_MIN;
+    return (size_t)ka * (size_t)ws_ld(ka) * 4 + ln * (4 + 8 * 4) + mn * 8 + 12 * pack + 10 * WS_MIN + split;
 }
 
 // device memory the slot's handle allocates to run q alone: for every
@@ -138,6 +139,9 @@ size_t alone_growth(const rtri_handle *h, const Req &q)
         const int leaf = pick_leaf(h, DType::F64, false, q.ka, nvec);
         return trmm_one_launch(h, leaf, q.ka, nvec) ? (size_t)r.m * (size_t)r.n * 8 : (size_t)0;
     };
+    // split-K partials (an upper bound: allocated once some update of the plan splits)
+    if (may_split(q.ka))
+        need[WS_SPLIT] = SPLIT_WS_BYTES;
     if (r.precision == RTRI_PREC_F64) {
         need[WS_PACK] = pack_bytes(DType::F64, r.op == 0);
         if (r.op == 1)
