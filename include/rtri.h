@@ -117,7 +117,11 @@ int rtri_strsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t 
                float alpha, const float *A, int64_t lda, float *B, int64_t ldb);
 
 /* Triangular multiply, eqs. (1)/(2): B := alpha op(A) B (LEFT) or
- * B := alpha B op(A) (RIGHT), in place.  FP64 / FP32. */
+ * B := alpha B op(A) (RIGHT), in place.  FP64 / FP32.
+ * Workspace of both (owned by the handle, grown on demand, freed by
+ * rtri_destroy): the packed diagonal blocks; for a TRMM whose leaves run in one
+ * launch, a copy of B (m x n); for factor orders above 1536 whose updates are
+ * short of tiles (narrow panels), 80 MiB of split-K partial products. */
 int rtri_dtrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                double alpha, const double *A, int64_t lda, double *B, int64_t ldb);
 int rtri_strmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
