@@ -34,7 +34,7 @@ HBM_PEAK = 8000.0                                                    # GB/s
 # PMC passes (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 2 GiB copy in the
 # same process; profiles/gemm_f64_16384_traffic.txt).  Valid only for the GEMM
 # sources they were taken on: reported as null once those change.
-GEMM_TRAFFIC = {"bytes_per_launch": 1.0367e9, "sources_sha256_16": "3673354ce5cccd85"}
+GEMM_TRAFFIC = {"bytes_per_launch": 1.0347e9, "sources_sha256_16": "b190c45f11c15130"}
 
 
 def gemm_sources_digest():
