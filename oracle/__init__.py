@@ -64,6 +64,23 @@ def lib():
             f = getattr(L, name)
             f.argtypes = [ctypes.c_int] * 3 + [_c_i64, _c_dp, _c_i64]
             f.restype = ctypes.c_double
+        zsig = [ctypes.c_int] * 4 + [_c_i64, _c_i64, ctypes.c_double, ctypes.c_double, _c_dp, _c_i64, _c_dp, _c_i64]
+        for name in ("oracle_ztrmm", "oracle_ztrsm"):
+            f = getattr(L, name)
+            f.argtypes = zsig
+            f.restype = None
+        L.oracle_ztrsm_residual.argtypes = zsig + [_c_dp, _c_i64, _c_dp]
+        L.oracle_ztrsm_residual.restype = None
+        L.oracle_ztrmm_dot2.argtypes = zsig + [_c_dp]
+        L.oracle_ztrmm_dot2.restype = None
+        for name in ("oracle_ztrsm_eta", "oracle_ztrmm_eta"):
+            f = getattr(L, name)
+            f.argtypes = zsig + [_c_dp, _c_i64]
+            f.restype = ctypes.c_double
+        L.oracle_zopnorm.argtypes = [ctypes.c_int] * 3 + [_c_i64, _c_dp, _c_i64, ctypes.c_int]
+        L.oracle_zopnorm.restype = ctypes.c_double
+        L.oracle_trtri.argtypes = [ctypes.c_int, ctypes.c_int, _c_i64, _c_dp, _c_i64]
+        L.oracle_trtri.restype = None
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -188,6 +205,128 @@ def cond_one(uplo, diag, A) -> float:
     m = A.shape[0]
     inv = trsm("L", uplo, "N", diag, 1.0, A, np.eye(m, order="F"))
     return opnorm_one(uplo, "N", diag, A) * float(np.abs(inv).sum(axis=0).max())
+
+
+# ---- complex (interleaved complex128, column-major) ---------------------------
+
+def _c128(a: np.ndarray) -> np.ndarray:
+    a = np.asarray(a)
+    if a.dtype != np.complex128 or not a.flags["F_CONTIGUOUS"]:
+        a = np.asfortranarray(a, dtype=np.complex128)
+    return a
+
+
+def _zp(a: np.ndarray):
+    return a.ctypes.data_as(_c_dp)
+
+
+def _zld(a: np.ndarray) -> int:
+    return max(1, a.shape[0])
+
+
+def _zargs(side, uplo, trans, diag, alpha, A, B):
+    A, B = _c128(A), _c128(B)
+    m, n = B.shape
+    ka = m if side.upper() == "L" else n
+    if A.shape[0] < ka or A.shape[1] < ka:
+        raise ValueError(f"A is {A.shape}, side {side} needs order {ka}")
+    al = complex(alpha)
+    return A, B, m, n, (*_codes(side, uplo, trans, diag), m, n, al.real, al.imag, _zp(A), _zld(A))
+
+
+def ztrmm(side, uplo, trans, diag, alpha, A, B) -> np.ndarray:
+    """Complex TRMM (eqs. (1)/(2), op(A) = A, A^T or conj(A^T)): a new array."""
+    A, B, m, n, args = _zargs(side, uplo, trans, diag, alpha, A, B)
+    X = B.copy(order="F")
+    lib().oracle_ztrmm(*args, _zp(X), _zld(X))
+    return X
+
+
+def ztrsm(side, uplo, trans, diag, alpha, A, B) -> np.ndarray:
+    """Complex TRSM (eqs. (3)/(4)) by substitution: a new array."""
+    A, B, m, n, args = _zargs(side, uplo, trans, diag, alpha, A, B)
+    X = B.copy(order="F")
+    lib().oracle_ztrsm(*args, _zp(X), _zld(X))
+    return X
+
+
+def ztrsm_residual(side, uplo, trans, diag, alpha, A, B, X) -> np.ndarray:
+    A, B, m, n, args = _zargs(side, uplo, trans, diag, alpha, A, B)
+    X = _c128(X)
+    R = np.zeros((m, n), dtype=np.complex128, order="F")
+    lib().oracle_ztrsm_residual(*args, _zp(B), _zld(B), _zp(X), _zld(X), _zp(R))
+    return R
+
+
+def ztrmm_dot2(side, uplo, trans, diag, alpha, A, B) -> np.ndarray:
+    A, B, m, n, args = _zargs(side, uplo, trans, diag, alpha, A, B)
+    C = np.zeros((m, n), dtype=np.complex128, order="F")
+    lib().oracle_ztrmm_dot2(*args, _zp(B), _zld(B), _zp(C))
+    return C
+
+
+def ztrsm_eta(side, uplo, trans, diag, alpha, A, B, X) -> float:
+    A, B, m, n, args = _zargs(side, uplo, trans, diag, alpha, A, B)
+    X = _c128(X)
+    return float(lib().oracle_ztrsm_eta(*args, _zp(B), _zld(B), _zp(X), _zld(X)))
+
+
+def ztrmm_eta(side, uplo, trans, diag, alpha, A, B, C) -> float:
+    A, B, m, n, args = _zargs(side, uplo, trans, diag, alpha, A, B)
+    C = _c128(C)
+    return float(lib().oracle_ztrmm_eta(*args, _zp(B), _zld(B), _zp(C), _zld(C)))
+
+
+def zopnorm(uplo, trans, diag, A, by_rows=True) -> float:
+    """|op(A)|_inf (by_rows) or |op(A)|_1, entries measured by their modulus."""
+    A = _c128(A)
+    return float(lib().oracle_zopnorm(_UPLO[uplo.upper()], _TRANS[trans.upper()], _DIAG[diag.upper()], A.shape[0],
+                                      _zp(A), _zld(A), int(bool(by_rows))))
+
+
+def trtri(uplo, diag, A) -> np.ndarray:
+    """A copy of A whose triangle named by uplo (and diagonal unless diag='U')
+    holds that triangle of inv(A); the other triangle is copied unchanged."""
+    X = _f64(A).copy(order="F")
+    n = X.shape[0]
+    if X.shape[1] != n:
+        raise ValueError("A must be square")
+    lib().oracle_trtri(_UPLO[uplo.upper()], _DIAG[diag.upper()], n, _p(X), _ld(X))
+    return X
+
+
+def potrs(uplo, A, B) -> np.ndarray:
+    """X with S X = B for S = L L^T (uplo 'L', L the lower triangle of A) or
+    S = U^T U (uplo 'U'): the two triangular solves of the factored system,
+    in order (L then L^T; U^T then U)."""
+    if uplo.upper() == "L":
+        return trsm("L", "L", "T", "N", 1.0, A, trsm("L", "L", "N", "N", 1.0, A, B))
+    return trsm("L", "U", "N", "N", 1.0, A, trsm("L", "U", "T", "N", 1.0, A, B))
+
+
+def laswp(B, ipiv, forward=True) -> np.ndarray:
+    """Row interchanges of LAPACK's pivot sequence (1-based ipiv): for i in
+    order, swap rows i and ipiv[i]-1 of a copy of B (in reverse order when
+    forward is False, which applies the inverse permutation)."""
+    X = _f64(B).copy(order="F")
+    order = range(len(ipiv)) if forward else range(len(ipiv) - 1, -1, -1)
+    for i in order:
+        p = int(ipiv[i]) - 1
+        if p != i:
+            X[[i, p], :] = X[[p, i], :]
+    return X
+
+
+def getrs(trans, LU, ipiv, B) -> np.ndarray:
+    """X with S X = B (trans 'N') or S^T X = B (trans 'T') for P S = L U, the
+    unit lower L and upper U packed in LU with LAPACK's pivot sequence ipiv:
+    trans N: rows of B interchanged by ipiv, then L, then U;
+    trans T: U^T, then L^T, then the interchanges undone in reverse order."""
+    if trans.upper() == "N":
+        Y = trsm("L", "L", "N", "U", 1.0, LU, laswp(B, ipiv, True))
+        return trsm("L", "U", "N", "N", 1.0, LU, Y)
+    Y = trsm("L", "U", "T", "N", 1.0, LU, B)
+    return laswp(trsm("L", "L", "T", "U", 1.0, LU, Y), ipiv, False)
 
 
 def num_threads() -> int:

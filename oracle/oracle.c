@@ -161,6 +161,195 @@ void oracle_trsm(int side, int uplo, int trans, int diag, int64_t m, int64_t n,
     }
 }
 
+/* ---- complex TRMM / TRSM, eqs. (1)-(4) with op(A) = A, A^T or conj(A^T) ----- */
+
+/*
+ * Complex matrices are stored interleaved (real part, then imaginary part) in
+ * column-major order: element (i, k) of A is (A[2(i + k lda)], A[2(i + k lda) + 1]),
+ * lda counted in complex elements.  Products use the textbook formula
+ * (a + bi)(c + di) = (ac - bd) + (ad + bc)i; quotients use Smith's method
+ * (Smith 1962: divide through by the larger part of the divisor).
+ */
+typedef struct {
+    double re, im;
+} cplx;
+
+static inline cplx c_mul(cplx a, cplx b)
+{
+    cplx r = {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return r;
+}
+
+static inline cplx c_div(cplx a, cplx b)
+{
+    cplx r;
+    if (fabs(b.re) >= fabs(b.im)) {
+        double q = b.im / b.re, den = b.re + b.im * q;
+        r.re = (a.re + a.im * q) / den;
+        r.im = (a.im - a.re * q) / den;
+    } else {
+        double q = b.re / b.im, den = b.re * q + b.im;
+        r.re = (a.re * q + a.im) / den;
+        r.im = (a.im * q - a.re) / den;
+    }
+    return r;
+}
+
+static inline cplx c_ld(const double *X, int64_t i, int64_t j, int64_t ld)
+{
+    cplx r = {X[2 * (i + j * ld)], X[2 * (i + j * ld) + 1]};
+    return r;
+}
+
+static inline void c_st(double *X, int64_t i, int64_t j, int64_t ld, cplx v)
+{
+    X[2 * (i + j * ld)] = v.re;
+    X[2 * (i + j * ld) + 1] = v.im;
+}
+
+/* op(A)(i, k) for (i, k) inside the effective triangle: A(i, k), A(k, i) or conj(A(k, i)) */
+static inline cplx ztri_val(const double *A, int64_t lda, int trans, int diag, int64_t i, int64_t k)
+{
+    if (i == k && diag == 1) {
+        cplx one = {1.0, 0.0};
+        return one;
+    }
+    cplx a = trans == 0 ? c_ld(A, i, k, lda) : c_ld(A, k, i, lda);
+    if (trans == 2)
+        a.im = -a.im;
+    return a;
+}
+
+/* side L: C(i,j) = alpha sum_k op(A)(i,k) B(k,j);  side R: C(i,j) = alpha sum_k B(i,k) op(A)(k,j) */
+void oracle_ztrmm(int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha_re,
+                  double alpha_im, const double *A, int64_t lda, double *B, int64_t ldb)
+{
+    const int low = eff_lower(uplo, trans);
+    const cplx alpha = {alpha_re, alpha_im};
+    if (m <= 0 || n <= 0)
+        return;
+    double *C = (double *)malloc(sizeof(double) * 2 * (size_t)(m * n));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            cplx s = {0.0, 0.0};
+            if (side == 0) {
+                int64_t k0 = low ? 0 : i, k1 = low ? i : m - 1;
+                for (int64_t k = k0; k <= k1; ++k) {
+                    cplx p = c_mul(ztri_val(A, lda, trans, diag, i, k), c_ld(B, k, j, ldb));
+                    s.re += p.re;
+                    s.im += p.im;
+                }
+            } else {
+                int64_t k0 = low ? j : 0, k1 = low ? n - 1 : j;
+                for (int64_t k = k0; k <= k1; ++k) {
+                    cplx p = c_mul(c_ld(B, i, k, ldb), ztri_val(A, lda, trans, diag, k, j));
+                    s.re += p.re;
+                    s.im += p.im;
+                }
+            }
+            c_st(C, i, j, m, c_mul(alpha, s));
+        }
+    }
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i)
+            c_st(B, i, j, ldb, c_ld(C, i, j, m));
+    free(C);
+}
+
+/* substitution as oracle_trsm, in complex arithmetic */
+void oracle_ztrsm(int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha_re,
+                  double alpha_im, const double *A, int64_t lda, double *B, int64_t ldb)
+{
+    const int low = eff_lower(uplo, trans);
+    const cplx alpha = {alpha_re, alpha_im};
+    if (m <= 0 || n <= 0)
+        return;
+    if (side == 0) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t j = 0; j < n; ++j) {
+            for (int64_t r = 0; r < m; ++r) {
+                int64_t i = low ? r : m - 1 - r;
+                int64_t k0 = low ? 0 : i + 1, k1 = low ? i - 1 : m - 1;
+                cplx s = {0.0, 0.0};
+                for (int64_t k = k0; k <= k1; ++k) {
+                    cplx p = c_mul(ztri_val(A, lda, trans, diag, i, k), c_ld(B, k, j, ldb));
+                    s.re += p.re;
+                    s.im += p.im;
+                }
+                cplx v = c_mul(alpha, c_ld(B, i, j, ldb));
+                v.re -= s.re;
+                v.im -= s.im;
+                c_st(B, i, j, ldb, diag == 1 ? v : c_div(v, ztri_val(A, lda, trans, diag, i, i)));
+            }
+        }
+    } else {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < m; ++i) {
+            for (int64_t r = 0; r < n; ++r) {
+                int64_t j = low ? n - 1 - r : r;
+                int64_t k0 = low ? j + 1 : 0, k1 = low ? n - 1 : j - 1;
+                cplx s = {0.0, 0.0};
+                for (int64_t k = k0; k <= k1; ++k) {
+                    cplx p = c_mul(c_ld(B, i, k, ldb), ztri_val(A, lda, trans, diag, k, j));
+                    s.re += p.re;
+                    s.im += p.im;
+                }
+                cplx v = c_mul(alpha, c_ld(B, i, j, ldb));
+                v.re -= s.re;
+                v.im -= s.im;
+                c_st(B, i, j, ldb, diag == 1 ? v : c_div(v, ztri_val(A, lda, trans, diag, j, j)));
+            }
+        }
+    }
+}
+
+/* ---- TRTRI: inverse of a triangular matrix ---------------------------------- */
+
+/*
+ * In place: the triangle of A named by uplo (and its diagonal unless unit)
+ * becomes the same triangle of inv(A).  Column j of the inverse is the
+ * solution x of A x = e_j, by the substitution of oracle_trsm:
+ *   lower: x_i = 0 for i < j;  for i = j..n-1:  x_i = (delta_ij - sum_{j<=k<i} a_ik x_k) / a_ii
+ *   upper: x_i = 0 for i > j;  for i = j..0:    x_i = (delta_ij - sum_{i<k<=j} a_ik x_k) / a_ii
+ * (no division when unit).  The columns are formed in a temporary from the
+ * original A and written back at the end; the other triangle is not touched.
+ */
+void oracle_trtri(int uplo, int diag, int64_t n, double *A, int64_t lda)
+{
+    if (n <= 0)
+        return;
+    double *X = (double *)calloc((size_t)(n * n), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        double *x = X + j * n;
+        if (uplo == 0) {
+            for (int64_t i = j; i < n; ++i) {
+                double s = 0.0;
+                for (int64_t k = j; k < i; ++k)
+                    s += A[i + k * lda] * x[k];
+                double v = (i == j ? 1.0 : 0.0) - s;
+                x[i] = (diag == 1) ? v : v / A[i + i * lda];
+            }
+        } else {
+            for (int64_t i = j; i >= 0; --i) {
+                double s = 0.0;
+                for (int64_t k = i + 1; k <= j; ++k)
+                    s += A[i + k * lda] * x[k];
+                double v = (i == j ? 1.0 : 0.0) - s;
+                x[i] = (diag == 1) ? v : v / A[i + i * lda];
+            }
+        }
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t i0 = uplo == 0 ? j : 0, i1 = uplo == 0 ? n - 1 : j;
+        for (int64_t i = i0; i <= i1; ++i)
+            if (i != j || diag != 1)
+                A[i + j * lda] = X[i + j * n];
+    }
+    free(X);
+}
+
 /* ---- compensated arithmetic for the error metrics -------------------------- */
 
 /* error-free transformations: a + b = s + e exactly, a * b = p + e exactly */
@@ -378,6 +567,194 @@ double oracle_trmm_eta(int side, int uplo, int trans, int diag, int64_t m, int64
             bn = vnorm_inf(B + v, n, ldb);
         }
         double den = fabs(alpha) * an * bn;
+        double e = den > 0.0 ? dn / den : (dn > 0.0 ? INFINITY : 0.0);
+        if (e != e) {
+            worst = NAN;
+            break;
+        }
+        if (e > worst)
+            worst = e;
+    }
+    free(C);
+    return worst;
+}
+
+/* ---- complex error metrics (compensated real and imaginary parts) ---------- */
+
+/* acc_re + i acc_im += a b, every real product and sum compensated */
+static inline void zdot2_add_prod(dot2_acc *re, dot2_acc *im, cplx a, cplx b)
+{
+    dot2_add_prod(re, a.re, b.re);
+    dot2_add_prod(re, -a.im, b.im);
+    dot2_add_prod(im, a.re, b.im);
+    dot2_add_prod(im, a.im, b.re);
+}
+
+static inline double c_abs(cplx z) { return hypot(z.re, z.im); }
+
+/* |op(A)|_inf (rows) or |op(A)|_1 (columns, by_rows = 0), moduli of the effective triangle */
+double oracle_zopnorm(int uplo, int trans, int diag, int64_t ka, const double *A, int64_t lda, int by_rows)
+{
+    const int low = eff_lower(uplo, trans);
+    double best = 0.0;
+    for (int64_t l = 0; l < ka; ++l) {
+        double s = 0.0;
+        if (by_rows) {
+            int64_t k0 = low ? 0 : l, k1 = low ? l : ka - 1;
+            for (int64_t k = k0; k <= k1; ++k)
+                s += c_abs(ztri_val(A, lda, trans, diag, l, k));
+        } else {
+            int64_t i0 = low ? l : 0, i1 = low ? ka - 1 : l;
+            for (int64_t i = i0; i <= i1; ++i)
+                s += c_abs(ztri_val(A, lda, trans, diag, i, l));
+        }
+        if (s > best)
+            best = s;
+    }
+    return best;
+}
+
+/* compensated R = alpha B - op(A) X (side L) or alpha B - X op(A) (side R); R has ld m */
+void oracle_ztrsm_residual(int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha_re,
+                           double alpha_im, const double *A, int64_t lda, const double *B, int64_t ldb,
+                           const double *X, int64_t ldx, double *R)
+{
+    const int low = eff_lower(uplo, trans);
+    const cplx alpha = {alpha_re, alpha_im};
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            dot2_acc re = {0.0, 0.0}, im = {0.0, 0.0};
+            zdot2_add_prod(&re, &im, alpha, c_ld(B, i, j, ldb));
+            if (side == 0) {
+                int64_t k0 = low ? 0 : i, k1 = low ? i : m - 1;
+                for (int64_t k = k0; k <= k1; ++k) {
+                    cplx a = ztri_val(A, lda, trans, diag, i, k);
+                    a.re = -a.re;
+                    a.im = -a.im;
+                    zdot2_add_prod(&re, &im, a, c_ld(X, k, j, ldx));
+                }
+            } else {
+                int64_t k0 = low ? j : 0, k1 = low ? n - 1 : j;
+                for (int64_t k = k0; k <= k1; ++k) {
+                    cplx x = c_ld(X, i, k, ldx);
+                    x.re = -x.re;
+                    x.im = -x.im;
+                    zdot2_add_prod(&re, &im, x, ztri_val(A, lda, trans, diag, k, j));
+                }
+            }
+            cplx v = {dot2_value(&re), dot2_value(&im)};
+            c_st(R, i, j, m, v);
+        }
+    }
+}
+
+/* compensated C = alpha op(A) B (side L) or alpha B op(A) (side R); C has ld m */
+void oracle_ztrmm_dot2(int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha_re,
+                       double alpha_im, const double *A, int64_t lda, const double *B, int64_t ldb, double *C)
+{
+    const int low = eff_lower(uplo, trans);
+    const cplx alpha = {alpha_re, alpha_im};
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = 0; i < m; ++i) {
+            dot2_acc re = {0.0, 0.0}, im = {0.0, 0.0};
+            if (side == 0) {
+                int64_t k0 = low ? 0 : i, k1 = low ? i : m - 1;
+                for (int64_t k = k0; k <= k1; ++k)
+                    zdot2_add_prod(&re, &im, ztri_val(A, lda, trans, diag, i, k), c_ld(B, k, j, ldb));
+            } else {
+                int64_t k0 = low ? j : 0, k1 = low ? n - 1 : j;
+                for (int64_t k = k0; k <= k1; ++k)
+                    zdot2_add_prod(&re, &im, c_ld(B, i, k, ldb), ztri_val(A, lda, trans, diag, k, j));
+            }
+            /* alpha (s + c), with s + c the compensated sum of each part */
+            cplx sh = {re.s, im.s}, cl = {re.c, im.c};
+            dot2_acc ore = {0.0, 0.0}, oim = {0.0, 0.0};
+            zdot2_add_prod(&ore, &oim, alpha, sh);
+            zdot2_add_prod(&ore, &oim, alpha, cl);
+            cplx v = {dot2_value(&ore), dot2_value(&oim)};
+            c_st(C, i, j, m, v);
+        }
+    }
+}
+
+static double zvnorm_inf(const double *v, int64_t len, int64_t stride)
+{
+    double best = 0.0;
+    for (int64_t t = 0; t < len; ++t) {
+        cplx z = {v[2 * t * stride], v[2 * t * stride + 1]};
+        double a = c_abs(z);
+        if (a > best || a != a)
+            best = a;
+    }
+    return best;
+}
+
+/* complex TRSM backward error (moduli in every norm), as oracle_trsm_eta */
+double oracle_ztrsm_eta(int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha_re,
+                        double alpha_im, const double *A, int64_t lda, const double *B, int64_t ldb,
+                        const double *X, int64_t ldx)
+{
+    if (m <= 0 || n <= 0)
+        return 0.0;
+    int64_t ka = side == 0 ? m : n;
+    double *R = (double *)malloc(sizeof(double) * 2 * (size_t)(m * n));
+    oracle_ztrsm_residual(side, uplo, trans, diag, m, n, alpha_re, alpha_im, A, lda, B, ldb, X, ldx, R);
+    double an = oracle_zopnorm(uplo, trans, diag, ka, A, lda, side == 0);
+    double aa = hypot(alpha_re, alpha_im);
+    int64_t nvec = side == 0 ? n : m;
+    double worst = 0.0;
+    for (int64_t v = 0; v < nvec; ++v) {
+        double rn, xn, bn;
+        if (side == 0) {
+            rn = zvnorm_inf(R + 2 * v * m, m, 1);
+            xn = zvnorm_inf(X + 2 * v * ldx, m, 1);
+            bn = zvnorm_inf(B + 2 * v * ldb, m, 1);
+        } else {
+            rn = zvnorm_inf(R + 2 * v, n, m);
+            xn = zvnorm_inf(X + 2 * v, n, ldx);
+            bn = zvnorm_inf(B + 2 * v, n, ldb);
+        }
+        double den = an * xn + aa * bn;
+        double e = den > 0.0 ? rn / den : (rn > 0.0 ? INFINITY : 0.0);
+        if (e != e) {
+            worst = NAN;
+            break;
+        }
+        if (e > worst)
+            worst = e;
+    }
+    free(R);
+    return worst;
+}
+
+/* complex TRMM normwise error of Chat against the compensated product */
+double oracle_ztrmm_eta(int side, int uplo, int trans, int diag, int64_t m, int64_t n, double alpha_re,
+                        double alpha_im, const double *A, int64_t lda, const double *B, int64_t ldb,
+                        const double *Chat, int64_t ldc)
+{
+    if (m <= 0 || n <= 0)
+        return 0.0;
+    int64_t ka = side == 0 ? m : n;
+    double *C = (double *)malloc(sizeof(double) * 2 * (size_t)(m * n));
+    oracle_ztrmm_dot2(side, uplo, trans, diag, m, n, alpha_re, alpha_im, A, lda, B, ldb, C);
+    double an = oracle_zopnorm(uplo, trans, diag, ka, A, lda, side == 0);
+    double aa = hypot(alpha_re, alpha_im);
+    int64_t nvec = side == 0 ? n : m;
+    double worst = 0.0;
+    for (int64_t v = 0; v < nvec; ++v) {
+        double dn = 0.0, bn;
+        int64_t len = side == 0 ? m : n;
+        for (int64_t t = 0; t < len; ++t) {
+            int64_t i = side == 0 ? t : v, j = side == 0 ? v : t;
+            cplx d = {Chat[2 * (i + j * ldc)] - C[2 * (i + j * m)], Chat[2 * (i + j * ldc) + 1] - C[2 * (i + j * m) + 1]};
+            double a = c_abs(d);
+            if (a > dn || a != a)
+                dn = a;
+        }
+        bn = side == 0 ? zvnorm_inf(B + 2 * v * ldb, m, 1) : zvnorm_inf(B + 2 * v, n, ldb);
+        double den = aa * an * bn;
         double e = den > 0.0 ? dn / den : (dn > 0.0 ? INFINITY : 0.0);
         if (e != e) {
             worst = NAN;

@@ -21,3 +21,15 @@ def test_worked_example(orc, case):
     fn = orc.trsm if case["op"] == "trsm" else orc.trmm
     got = fn(case["side"], case["uplo"], case["trans"], case["diag"], case["alpha"], A, B)
     assert np.array_equal(got, want)
+
+
+def test_c3_condition_labels():
+    """The mixed-precision workload's factors (written by make_c3_cond.py with
+    the oracle alone): each 1-norm condition number within a factor of two of
+    its class 1e2 / 1e4 / 1e6, the classes in order of decreasing offset c."""
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_cond.json")) as f:
+        d = json.load(f)
+    assert d["m"] == 8192
+    cases = sorted(d["cases"], key=lambda c: -c["c"])
+    for case, target in zip(cases, (1e2, 1e4, 1e6)):
+        assert target / 2 <= case["cond1"] <= target * 2, (case, target)

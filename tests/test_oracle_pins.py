@@ -16,7 +16,7 @@ import pytest
 import scipy.linalg.blas as sblas
 
 import synth
-from dense_ref import (VARIANTS, VARIANTS_NT, dense_op, exact_trmm, exact_trsm, frac_to_f64_exact,
+from dense_ref import (VARIANTS, VARIANTS_NT, dense_op, exact_trmm, exact_trsm, frac_solve, frac_to_f64_exact,
                        to_frac)
 
 RNG = lambda *k: synth.rng(synth.W_TEST, *k)  # noqa: E731
@@ -319,6 +319,33 @@ def test_cond_one_diagonal(orc):
     d = np.array([1.0, 4.0, 0.5, 2.0])
     A = np.diag(d).copy(order="F")
     assert orc.cond_one("L", "N", A) == pytest.approx(d.max() / d.min(), rel=1e-15)
+
+
+@pytest.mark.parametrize("uplo", "LU")
+@pytest.mark.parametrize("diag", "NU")
+def test_cond_one_exact_nondiagonal(orc, uplo, diag):
+    """kappa_1 = |A|_1 |A^-1|_1 of a small integer triangle, the inverse taken
+    exactly by rational Gaussian elimination.  The case is chosen so that the
+    1-norm and the inf-norm differ for both A and its inverse: a slip that
+    takes row sums for column sums (of either factor) cannot pass."""
+    g = RNG(15, uplo == "U", diag == "U")
+    for _ in range(50):
+        A = synth.exact_tri(7, uplo, g, offdiag=(-3, -1, 0, 1, 2), diag=(1.0, 2.0, -4.0, 0.5))
+        if diag == "U":
+            np.fill_diagonal(A, np.nan)
+        T = dense_op(A, uplo, "N", diag)
+        inv = frac_solve(to_frac(T), to_frac(np.eye(7)))
+        absinv = [[abs(v) for v in row] for row in inv]
+        inv_one = max(sum(absinv[i][j] for i in range(7)) for j in range(7))
+        inv_inf = max(sum(absinv[i][j] for j in range(7)) for i in range(7))
+        a_one, a_inf = np.abs(T).sum(axis=0).max(), np.abs(T).sum(axis=1).max()
+        if inv_one != inv_inf and a_one != a_inf:
+            break
+    else:
+        pytest.fail("no discriminating case drawn")
+    want = float(Fraction(float(a_one)) * inv_one)
+    assert orc.cond_one(uplo, diag, A) == pytest.approx(want, rel=1e-14)
+    assert abs(want - float(a_inf) * float(inv_inf)) > 1e-6 * want
 
 
 # ---- the counter-based input generator against its published answers ----------
