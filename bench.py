@@ -55,8 +55,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true", help="only the headline step")
-    ap.add_argument("--extras", default="mixed,trmm16,batched,serving,vendor",
-                    help="comma-separated extra sections to run (default: all)")
+    ap.add_argument("--extras", default="mixed,rect256,solvers,trmm16,batched,serving",
+                    help="comma-separated extra sections to run (default: all but 'vendor', the rocBLAS "
+                         "comparison, which runs only when named)")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--tuning", default="", help="tuning database (default: the package's, if present)")
     return ap.parse_args()
@@ -186,8 +187,23 @@ def main():
     torch.cuda.empty_cache()
     extras = set() if args.no_extras else set(x.strip() for x in args.extras.split(",") if x.strip())
     if "mixed" in extras:
-        out["mixed"] = bench_mixed(rt, torch, h)
+        out["mixed"], sample_mx = bench_mixed(rt, torch, h)
+        if not args.no_cpu:
+            cpu_check_mixed(out["mixed"], sample_mx)
+        del sample_mx
         progress("mixed done")
+    if "rect256" in extras:
+        out["rect256"], sample_r = bench_rect256(rt, torch, h)
+        if not args.no_cpu:
+            cpu_check_rect256(out["rect256"], sample_r)
+        del sample_r
+        progress("rect256 done")
+    if "solvers" in extras:
+        out["solvers"], sample_s = bench_solvers(rt, torch, h)
+        if not args.no_cpu:
+            cpu_check_solvers(out["solvers"], sample_s)
+        del sample_s
+        progress("solvers done")
     if "trmm16" in extras:
         out["trmm16"], sample16 = bench_trmm16(rt, torch, h)
         if not args.no_cpu:
@@ -325,28 +341,42 @@ def bench_vendor(rt, torch, h, m):
     return res
 
 
-# diagonal offset c of the m = 8192 mixed-precision factor (diagonal c + U(0,1),
-# off-diagonal U(-1,1), device Philox fill, id 1) -> its 1-norm condition
-# number, computed on the host with LAPACK dtrtri on the bit-identical host twin
-MIXED_COND = ((450.0, 1.04e2), (45.0, 1.15e4), (17.0, 1.17e6))
+def mixed_cond_labels():
+    """Diagonal offset c of the m = 8192 mixed-precision factors (diagonal
+    c + U(0,1), off-diagonal U(-1,1), device Philox fill, id 1) -> 1-norm
+    condition number, as computed by the CPU oracle on the bit-identical host
+    twin (tests/golden/make_c3_cond.py writes the file)."""
+    with open(os.path.join(ROOT, "tests", "golden", "c3_cond.json")) as f:
+        return [(case["c"], case["cond1"]) for case in json.load(f)["cases"]]
 
 
-def bench_mixed(rt, torch, h, m=8192):
+def bench_mixed(rt, torch, h, m=8192, ns=8):
     """Mixed-precision refined TRSM against the plain FP64 TRSM on the same
     system: m = n = 8192, lower factor with off-diagonal U(-1,1) and diagonal
     c + U(0,1) for three condition classes, dense right-hand sides U(-1,1);
-    inputs drawn on the device (Philox)."""
+    plus the headline order m = n = 16384 on its own factor (diagonal
+    m + U(0,1)).  Inputs drawn on the device (Philox).  Returns the timings
+    and, for the CPU leg, sampled columns of every input and result."""
     import synth
-    Ad = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
-    B0 = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
-    rt.synth_fill(h, 0, synth.SEED, synth.W_MIXED, 2, B0)
-    Bd = B0.clone()
-    res = {"workload": f"FP64-accurate TRSM L/L/N/N m=n={m}, diagonal c+U(0,1), tol 1e-12", "cases": []}
-    for c, kappa in MIXED_COND:
-        rt.synth_fill(h, 1, synth.SEED, synth.W_MIXED, 1, Ad, param=c)
+    res = {"workload": f"FP64-accurate TRSM L/L/N/N m=n={m}, diagonal c+U(0,1), tol 1e-12; "
+                       "and m=n=16384, diagonal m+U(0,1)", "cases": []}
+    samples = []
+    cases = [(m, c, kappa) for c, kappa in mixed_cond_labels()] + [(16384, 16384.0, None)]
+    for mm, c, kappa in cases:
+        Ad = torch.empty((mm, mm), dtype=torch.float64, device="cuda").t()
+        B0 = torch.empty((mm, mm), dtype=torch.float64, device="cuda").t()
+        w = synth.W_MIXED if mm == m else synth.W_SWEEP
+        rt.synth_fill(h, 0, synth.SEED, w, 2, B0)
+        rt.synth_fill(h, 1, synth.SEED, w, 1, Ad, param=c)
+        Bd = B0.clone()
+        idx = np.sort(synth.rng(synth.W_MIXED, 3, mm, int(c)).choice(mm, ns, replace=False))
+        tidx = torch.as_tensor(idx, device="cuda")
+        smp = {"m": mm, "c": c, "A": rt.to_host(Ad), "B": np.asfortranarray(B0[:, tidx].cpu().numpy())}
         t_plain = _event_ms(torch, lambda: rt.trsm(h, "L", "L", "N", "N", 1.0, Ad, Bd), lambda: Bd.copy_(B0))
-        case = {"c": c, "cond1": kappa, "fp64_ms": round(t_plain, 3)}
-        for gemm in ("bf16", "f32"):
+        case = {"m": mm, "c": c, "cond1": kappa, "fp64_ms": round(t_plain, 3),
+                "fp64_tflops": round(mm ** 3 / (t_plain * 1e-3) / 1e12, 3)}
+        smp["fp64"] = np.asfortranarray(Bd[:, tidx].cpu().numpy())
+        for gemm in (("bf16", "f32") if mm == m else ("f32",)):
             info = {}
 
             def run():
@@ -354,10 +384,173 @@ def bench_mixed(rt, torch, h, m=8192):
                                           allow_not_converged=True))
             t = _event_ms(torch, run, lambda: Bd.copy_(B0))
             case[gemm] = {"ms": round(t, 3), "speedup_vs_fp64": round(t_plain / t, 3), "iters": info["iters"],
-                          "eta": info["eta"], "converged": info["converged"],
-                          "useful_tflops": round(m ** 3 / (t * 1e-3) / 1e12, 3)}
+                          "eta_library": info["eta"], "converged": info["converged"],
+                          "useful_tflops": round(mm ** 3 / (t * 1e-3) / 1e12, 3)}
+            smp[gemm] = np.asfortranarray(Bd[:, tidx].cpu().numpy())
         res["cases"].append(case)
-    return res
+        samples.append(smp)
+        del Ad, B0, Bd
+        torch.cuda.empty_cache()
+    return res, samples
+
+
+def cpu_check_mixed(res, samples):
+    """CPU leg: every refined solve (and the plain FP64 solve beside it) on its
+    sampled columns against the oracle: the compensated backward error and the
+    forward error relative to the oracle's own solution."""
+    import oracle
+    for case, smp in zip(res["cases"], samples):
+        Xo = oracle.trsm("L", "L", "N", "N", 1.0, smp["A"], smp["B"])
+        for key in ("fp64", "bf16", "f32"):
+            if key not in smp:
+                continue
+            X = smp[key]
+            err = {"columns": int(X.shape[1]),
+                   "eta_oracle": oracle.trsm_eta("L", "L", "N", "N", 1.0, smp["A"], smp["B"], X),
+                   "forward_error": float(np.max(np.abs(X - Xo)) / np.max(np.abs(Xo)))}
+            if key == "fp64":
+                case["fp64_error_vs_oracle"] = err
+            else:
+                case[key]["error_vs_oracle"] = err
+
+
+def bench_rect256(rt, torch, h, ns=16):
+    """The paper's narrow workload (its Sec. 4.1-4.2 rectangular case): FP32
+    TRSM and TRMM, side L, lower, no transpose, non-unit, alpha = 1, A m x m
+    (off-diagonal U(-1,1), diagonal m + U(0,1)), B m x 256 U(-1,1), for
+    m = 1024 ... 16384, the shipped tuning rules loaded.  Per m: event-timed
+    call (median of 5, B restored outside the timed region), TFLOP/s at
+    m^2 * 256 flops, and the per-class kernel profile of one more call (the
+    GEMM-update class is the roofline kernel: MFMA-bound, FP32 peak).  Returns
+    the timings and, for the CPU leg, sampled columns of inputs and results."""
+    import synth
+    res = {"workload": "FP32 TRSM / TRMM L/L/N/N, A m x m (diagonal m+U(0,1)), B m x 256, alpha 1", "rows": []}
+    samples = []
+    for mm in (1024, 2048, 4096, 8192, 16384):
+        n = 256
+        Ad = torch.empty((mm, mm), dtype=torch.float32, device="cuda").t()
+        B0 = torch.empty((n, mm), dtype=torch.float32, device="cuda").t()
+        rt.synth_fill(h, 1, synth.SEED, synth.W_SWEEP, 3, Ad, param=float(mm))
+        rt.synth_fill(h, 0, synth.SEED, synth.W_SWEEP, 4, B0)
+        Bd = B0.clone()
+        idx = np.sort(synth.rng(synth.W_SWEEP, 256, mm).choice(n, ns, replace=False))
+        tidx = torch.as_tensor(idx, device="cuda")
+        smp = {"m": mm, "A": rt.to_host(Ad).astype(np.float64),
+               "B": np.asfortranarray(B0[:, tidx].cpu().numpy().astype(np.float64))}
+        fl = float(mm) * mm * n
+        row = {"m": mm, "n": n}
+        for op, fn in (("trsm", rt.trsm), ("trmm", rt.trmm)):
+            ts = []
+            for _ in range(5):
+                ts.append(_event_ms(torch, lambda: fn(h, "L", "L", "N", "N", 1.0, Ad, Bd), lambda: Bd.copy_(B0),
+                                    reps=1))
+            t = float(np.median(ts))
+            Bd.copy_(B0)
+            h.profile_begin()
+            fn(h, "L", "L", "N", "N", 1.0, Ad, Bd)
+            st = {(x["kclass"], x["dtype"]): x for x in h.profile_end()}
+            smp[op] = np.asfortranarray(Bd[:, tidx].cpu().numpy().astype(np.float64))
+            tf = fl / (t * 1e-3) / 1e12
+            r = {"ms": round(t, 4), "tflops": round(tf, 2), "fraction_of_peak": round(tf / PEAK["f32"], 4),
+                 "leaf": h.leaf("f32", op, mm, n), "kernels": {}}
+            for (kc, dt), x in st.items():
+                r["kernels"][f"{kc}_{dt}"] = {"launches": x["launches"], "ms": round(x["ms"], 4),
+                                              "tflops": round(x["flops"] / max(x["ms"], 1e-9) / 1e9, 2)}
+            g = st.get(("gemm", "f32"))
+            if g is not None:
+                gt = g["flops"] / (g["ms"] * 1e-3) / 1e12
+                r["roofline"] = {"kernel": "GEMM update class (FP32 MFMA)", "bound": "mfma", "achieved": round(gt, 2),
+                                 "peak": PEAK["f32"], "unit": "TFLOP/s", "frac": round(gt / PEAK["f32"], 4),
+                                 "avg_launch_ms": round(g["ms"] / g["launches"], 5)}
+            row[op] = r
+        res["rows"].append(row)
+        samples.append(smp)
+        del Ad, B0, Bd
+        torch.cuda.empty_cache()
+    return res, samples
+
+
+def cpu_check_rect256(res, samples):
+    """CPU leg: sampled columns of every narrow-panel result against the oracle
+    (compensated backward error; FP32 bound 5e-5)."""
+    import oracle
+    for row, smp in zip(res["rows"], samples):
+        row["trsm"]["eta_oracle"] = oracle.trsm_eta("L", "L", "N", "N", 1.0, smp["A"], smp["B"], smp["trsm"])
+        row["trmm"]["eta_oracle"] = oracle.trmm_eta("L", "L", "N", "N", 1.0, smp["A"], smp["B"], smp["trmm"])
+
+
+def bench_solvers(rt, torch, h, n=16384, ns=8):
+    """The operations built on the recursive TRSM, FP64, order n = 16384:
+    TRTRI (lower, non-unit; n^3/3 flops), POTRS (lower Cholesky-type factor,
+    n right-hand sides; 2 n^3 flops) and GETRS (P S = L U, unit lower L with
+    off-diagonal U(-1,1)/n, upper U with diagonal n + U(0,1), local row
+    interchanges; n right-hand sides, trans N; 2 n^3 flops).  Factors: the
+    sweep recipe (off-diagonal U(-1,1), diagonal n + U(0,1)), device-drawn.
+    Returns timings and, for the CPU leg, sampled columns."""
+    import synth
+    res = {"workload": f"FP64, order {n}: TRTRI lower non-unit; POTRS lower, {n} rhs; GETRS trans N, {n} rhs"}
+    smp = {}
+    idx = np.sort(synth.rng(synth.W_SWEEP, 77, n).choice(n, ns, replace=False))
+    tidx = torch.as_tensor(idx, device="cuda")
+    A0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    rt.synth_fill(h, 1, synth.SEED, synth.W_SWEEP, 11, A0, param=float(n))
+    A = A0.clone()
+    t = _event_ms(torch, lambda: rt.trtri(h, "L", "N", A), lambda: A.copy_(A0))
+    smp["A"] = rt.to_host(A0)
+    smp["trtri"] = np.asfortranarray(A[:, tidx].cpu().numpy())
+    res["trtri"] = {"ms": round(t, 3), "tflops": round(n ** 3 / 3 / (t * 1e-3) / 1e12, 3),
+                    "fraction_of_peak": round(n ** 3 / 3 / (t * 1e-3) / 1e12 / PEAK["f64"], 4)}
+    del A
+    B0 = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    rt.synth_fill(h, 0, synth.SEED, synth.W_SWEEP, 12, B0)
+    B = B0.clone()
+    smp["B"] = np.asfortranarray(B0[:, tidx].cpu().numpy())
+    t = _event_ms(torch, lambda: rt.potrs(h, "L", A0, B), lambda: B.copy_(B0))
+    smp["potrs"] = np.asfortranarray(B[:, tidx].cpu().numpy())
+    res["potrs"] = {"ms": round(t, 3), "tflops": round(2.0 * n ** 3 / (t * 1e-3) / 1e12, 3),
+                    "fraction_of_peak": round(2.0 * n ** 3 / (t * 1e-3) / 1e12 / PEAK["f64"], 4)}
+    # LU: unit lower part scaled by 1/n (a unit triangle with O(1) entries grows
+    # exponentially), upper part of the sweep recipe
+    LU = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    rt.synth_fill(h, 2, synth.SEED, synth.W_SWEEP, 13, LU, param=float(n))
+    Ltmp = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    rt.synth_fill(h, 1, synth.SEED, synth.W_SWEEP, 14, Ltmp, param=0.0)
+    LU += torch.tril(Ltmp, -1) / n
+    del Ltmp
+    g = synth.rng(synth.W_SWEEP, 15, n)
+    ipiv = np.array([i + 1 + int(g.integers(0, min(8, n - i))) for i in range(n)], dtype=np.int32)
+    t = _event_ms(torch, lambda: rt.getrs(h, "N", LU, ipiv, B), lambda: B.copy_(B0))
+    smp["getrs"] = np.asfortranarray(B[:, tidx].cpu().numpy())
+    smp["LU"] = rt.to_host(LU)
+    smp["ipiv"] = ipiv
+    res["getrs"] = {"ms": round(t, 3), "tflops": round(2.0 * n ** 3 / (t * 1e-3) / 1e12, 3),
+                    "fraction_of_peak": round(2.0 * n ** 3 / (t * 1e-3) / 1e12 / PEAK["f64"], 4)}
+    smp["idx"] = idx
+    del A0, B0, B, LU
+    torch.cuda.empty_cache()
+    return res, smp
+
+
+def cpu_check_solvers(res, smp):
+    """CPU leg: sampled columns against the oracle.  TRTRI: column j of the
+    inverse solves A x = e_j, so its backward error is the TRSM's on e_j.
+    POTRS / GETRS: the oracle's own two substitutions on the sampled
+    right-hand sides, forward error relative to them."""
+    import oracle
+    n = smp["A"].shape[0]
+    E = np.zeros((n, len(smp["idx"])), order="F")
+    E[smp["idx"], np.arange(len(smp["idx"]))] = 1.0
+    Xt = np.tril(smp["trtri"][:, :])
+    for c, j in enumerate(smp["idx"]):
+        Xt[:j, c] = 0.0   # the strictly upper part of the column is not part of the lower inverse
+    res["trtri"]["eta_oracle"] = oracle.trsm_eta("L", "L", "N", "N", 1.0, smp["A"], E, Xt)
+    Xo = oracle.trsm("L", "L", "N", "N", 1.0, smp["A"], E)
+    res["trtri"]["forward_error"] = float(np.max(np.abs(Xt - Xo)) / np.max(np.abs(Xo)))
+    Xo = oracle.potrs("L", smp["A"], smp["B"])
+    res["potrs"]["forward_error_vs_oracle"] = float(np.max(np.abs(smp["potrs"] - Xo)) / np.max(np.abs(Xo)))
+    Xo = oracle.getrs("N", smp["LU"], smp["ipiv"], smp["B"])
+    res["getrs"]["forward_error_vs_oracle"] = float(np.max(np.abs(smp["getrs"] - Xo)) / np.max(np.abs(Xo)))
+    res["columns_checked"] = int(len(smp["idx"]))
 
 
 def bench_trmm16(rt, torch, h, m=8192, ns=16):

@@ -127,6 +127,23 @@ int rtri_dtrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t 
 int rtri_strmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                float alpha, const float *A, int64_t lda, float *B, int64_t ldb);
 
+/* Complex (FP64 complex, interleaved real / imaginary parts) TRSM and TRMM,
+ * eqs. (1)-(4) with op(A) = A (RTRI_NOTRANS), A^T (RTRI_TRANS) or conj(A^T)
+ * (RTRI_CONJTRANS).  A and B hold complex elements (two doubles each); lda,
+ * ldb count complex elements.  alpha points to two doubles (real,
+ * imaginary) in host memory.  The same recursion as the real calls: its GEMM
+ * updates run on the real FP64 matrix cores through the real 2x2-block
+ * embedding of op(A) (a + bi -> [a -b; b a]), made once per call in the
+ * handle's workspace (4 ka^2 doubles); leaves of at most 64 rows work in
+ * complex arithmetic (division by Smith's method).  alpha multiplies B first
+ * (alpha = 0: B := 0, A not read).  Side R is computed as side L on the
+ * transpose of B (a copy in the workspace).  Codes as rtri_dtrsm, and -7 for
+ * alpha == NULL. */
+int rtri_ztrsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, const double *alpha,
+               const void *A, int64_t lda, void *B, int64_t ldb);
+int rtri_ztrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, const double *alpha,
+               const void *A, int64_t lda, void *B, int64_t ldb);
+
 /* Per-kernel profile: while a profile is open, every kernel the handle
  * launches is bracketed by two HIP events recorded on the handle's stream, and
  * its algorithmic work is attributed to a kernel class.  rtri_profile_end waits
@@ -212,6 +229,102 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
                      const double *A, int64_t lda, double *B, int64_t ldb, int gemm_type, double tol,
                      int max_iter, rtri_refine_info *info);
 
+/* ---- operations built on the recursive TRSM -------------------------------- */
+
+/* Inverse of a triangular matrix, in place: the triangle of A named by uplo
+ * (and its diagonal unless diag = RTRI_UNIT) is overwritten by that triangle
+ * of inv(A); the other triangle is neither read nor written.  The midpoint
+ * recursion of the TRSM (Sec. 3.1) with, for a lower triangle split at k,
+ * inv([L11 0; L21 L22]) = [inv(L11) 0; -inv(L22) L21 inv(L11)  inv(L22)]: the
+ * off-diagonal block by two recursive TRSMs (side R with L11 and alpha -1,
+ * then side L with L22), then both halves recursively; diagonal blocks of at
+ * most 64 rows are inverted by substitution, all in one launch (an upper
+ * triangle mirrors this).  n^3/3 flops.  Codes: -2 uplo, -3 diag, -4 n < 0,
+ * -5 A NULL, -6 lda < max(1, n). */
+int rtri_dtrtri(rtri_handle *h, int uplo, int diag, int64_t n, double *A, int64_t lda);
+int rtri_strtri(rtri_handle *h, int uplo, int diag, int64_t n, float *A, int64_t lda);
+
+/* Solve S X = B (B n x nrhs, overwritten by X) with S = L L^T (uplo LOWER, L
+ * the lower triangle of A) or S = U^T U (uplo UPPER): two recursive TRSMs, L
+ * then L^T (U^T then U).  A is a Cholesky factor (non-unit diagonal).  Codes:
+ * -2 uplo, -3 n < 0, -4 nrhs < 0, -5 A NULL, -6 lda < max(1, n), -7 B NULL,
+ * -8 ldb < max(1, n). */
+int rtri_dpotrs(rtri_handle *h, int uplo, int64_t n, int64_t nrhs, const double *A, int64_t lda, double *B,
+                int64_t ldb);
+int rtri_spotrs(rtri_handle *h, int uplo, int64_t n, int64_t nrhs, const float *A, int64_t lda, float *B, int64_t ldb);
+
+/* Solve S X = B (trans N) or S^T X = B (trans T or C) (B n x nrhs, overwritten
+ * by X) given P S = L U in LAPACK's packed form: LU holds the unit lower L
+ * below its diagonal and U on and above it; ipiv (HOST memory, n entries,
+ * 1-based) is the sequence of row interchanges (row i swapped with row
+ * ipiv[i] - 1, in order).  trans N: the interchanges applied to B, then L,
+ * then U; trans T: U^T, then L^T, then the interchanges undone.  The
+ * workspace holds a copy of B while its rows are interchanged.  Codes: -2
+ * trans, -3 n < 0, -4 nrhs < 0, -5 LU NULL, -6 lda < max(1, n), -7 ipiv NULL
+ * or an entry outside 1..n, -8 B NULL, -9 ldb < max(1, n). */
+int rtri_dgetrs(rtri_handle *h, int trans, int64_t n, int64_t nrhs, const double *LU, int64_t lda,
+                const int32_t *ipiv, double *B, int64_t ldb);
+int rtri_sgetrs(rtri_handle *h, int trans, int64_t n, int64_t nrhs, const float *LU, int64_t lda, const int32_t *ipiv,
+                float *B, int64_t ldb);
+
+/* ---- factor objects: one triangular factor, many right-hand sides --------- */
+
+/* A triangular factor A (order ka, the triangle named by uplo, diag as in
+ * rtri_dtrsm) kept for repeated solves and multiplies against it, eqs. (1)-(4)
+ * with A fixed.  The first call that needs them makes, and the factor then
+ * keeps in device memory it owns:
+ *   - the packed diagonal blocks each plan's leaves read (per op, side, trans,
+ *     leaf size and precision), so later calls skip the pack pass;
+ *   - for refined solves: the copy of A in the GEMM type (BF16 or FP32,
+ *     transposed where the 16-bit GEMM wants it) and |op(A)| (per side and
+ *     trans), so later calls skip the conversion and the norm.
+ * Results are bit for bit those of rtri_dtrsm / rtri_strsm / rtri_dtrmm /
+ * rtri_strmm / rtri_dtrsm_mixed with the same handle options.
+ * Parts are made on the calling handle's stream; a call on another stream
+ * waits for them on the device.  Calls on one factor from several host
+ * threads are safe (parts are made under a lock). */
+typedef struct rtri_factor rtri_factor;
+
+/* flags of rtri_factor_create */
+enum { RTRI_FACTOR_COPY = 1 };   /* keep a copy of A (the caller may release A once create returns) */
+
+/* Create a factor.  dtype RTRI_F64 or RTRI_F32 (the element type of A and of
+ * every B used with it).  Without RTRI_FACTOR_COPY the factor reads the
+ * caller's A (device memory) on every call: it must stay valid and unchanged
+ * until rtri_factor_destroy.  With it, A is copied (ka x ka, blocking) into
+ * memory the factor owns.  Codes: -2 uplo, -3 diag, -4 ka < 0, -5 dtype,
+ * -6 A NULL, -7 lda < max(1, ka), -8 unknown flag, -9 out NULL. */
+int rtri_factor_create(rtri_handle *h, int uplo, int diag, int64_t ka, int dtype, const void *A, int64_t lda,
+                       unsigned flags, rtri_factor **f);
+
+/* TRSM against the factor, eqs. (3)/(4): B := X with op(A) X = alpha B (LEFT,
+ * B is ka x n) or X op(A) = alpha B (RIGHT, B is m x ka).  B is double* for
+ * an FP64 factor, float* for an FP32 one (alpha rounded to it).
+ *   precision RTRI_PREC_F64: the plain recursive solve in the factor's type
+ *     (tol, max_iter, info ignored; info, if given, reports converged = 1);
+ *   RTRI_PREC_MIXED_BF16 / RTRI_PREC_MIXED_F32 (FP64 factors only): the
+ *     refined solve of rtri_dtrsm_mixed, host-blocking, returns
+ *     RTRI_NOT_CONVERGED if tol was not reached (B and *info still filled).
+ * Codes: -2 factor invalid, -3 side, -4 trans, -5 m (< 0, or != ka for LEFT),
+ * -6 n (< 0, or != ka for RIGHT), -8 B NULL, -9 ldb < max(1, m),
+ * -10 precision, -11 tol < 0, -12 max_iter not in 1..32;
+ * RTRI_ERR_UNSUPPORTED for a refined solve on an FP32 factor. */
+int rtri_factor_trsm(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, double alpha, void *B,
+                     int64_t ldb, int precision, double tol, int max_iter, rtri_refine_info *info);
+
+/* TRMM against the factor, eqs. (1)/(2): B := alpha op(A) B (LEFT) or
+ * alpha B op(A) (RIGHT), in place.  Codes as rtri_factor_trsm (-2 .. -9). */
+int rtri_factor_trmm(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, double alpha, void *B,
+                     int64_t ldb);
+
+/* Device bytes the factor holds (its copy of A and every part made so far). */
+int rtri_factor_bytes(rtri_factor *f, int64_t *bytes);
+
+/* Free the factor and everything it holds.  Waits for no work: synchronise
+ * first if calls using it may still be running.  RTRI_ERR_INVALID for a NULL
+ * or destroyed factor. */
+int rtri_factor_destroy(rtri_factor *f);
+
 /* Synthetic inputs for benchmarks and serving workloads (not part of the
  * method).  Fills an m-by-n column-major matrix X (device, ldx) with values
  * from Philox4x32-10 (Salmon et al., SC'11): element (i, j) uses counter
@@ -234,7 +347,8 @@ int rtri_synth_fill(rtri_handle *h, int dtype, int kind, uint64_t seed, uint32_t
  * frees; keep the winners in the handle (rules for the other dtype are kept)
  * and, if db_path != NULL, write them there as JSON.  Blocking.  Options set
  * with rtri_set_option still take precedence.  Codes: -2 dtype, -3 max_order
- * < 256; RTRI_ERR_INVALID if the file cannot be written. */
+ * < 256; RTRI_ERR_INVALID if the file cannot be written.  If a timed run
+ * fails, its code is returned and the handle keeps the rules it had. */
 int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path);
 
 /* Load a tuning database written by rtri_tune into the handle (replacing any

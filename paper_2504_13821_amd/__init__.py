@@ -73,6 +73,25 @@ class RefineInfo(ctypes.Structure):
 
 rtri_dtrsm_mixed = _sig("rtri_dtrsm_mixed", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64, _int,
                         ctypes.c_double, _int, ctypes.POINTER(RefineInfo))
+_c2 = ctypes.c_double * 2
+rtri_ztrsm = _sig("rtri_ztrsm", _int, *_OPARGS, ctypes.POINTER(ctypes.c_double), _vp, _i64, _vp, _i64)
+rtri_ztrmm = _sig("rtri_ztrmm", _int, *_OPARGS, ctypes.POINTER(ctypes.c_double), _vp, _i64, _vp, _i64)
+rtri_dtrtri = _sig("rtri_dtrtri", _int, _vp, _int, _int, _i64, _vp, _i64)
+rtri_strtri = _sig("rtri_strtri", _int, _vp, _int, _int, _i64, _vp, _i64)
+rtri_dpotrs = _sig("rtri_dpotrs", _int, _vp, _int, _i64, _i64, _vp, _i64, _vp, _i64)
+rtri_spotrs = _sig("rtri_spotrs", _int, _vp, _int, _i64, _i64, _vp, _i64, _vp, _i64)
+rtri_dgetrs = _sig("rtri_dgetrs", _int, _vp, _int, _i64, _i64, _vp, _i64, _vp, _vp, _i64)
+rtri_sgetrs = _sig("rtri_sgetrs", _int, _vp, _int, _i64, _i64, _vp, _i64, _vp, _vp, _i64)
+rtri_factor_create = _sig("rtri_factor_create", _int, _vp, _int, _int, _i64, _int, _vp, _i64, ctypes.c_uint,
+                          ctypes.POINTER(_vp))
+rtri_factor_trsm = _sig("rtri_factor_trsm", _int, _vp, _vp, _int, _int, _i64, _i64, ctypes.c_double, _vp, _i64, _int,
+                        ctypes.c_double, _int, ctypes.POINTER(RefineInfo))
+rtri_factor_trmm = _sig("rtri_factor_trmm", _int, _vp, _vp, _int, _int, _i64, _i64, ctypes.c_double, _vp, _i64)
+rtri_factor_bytes = _sig("rtri_factor_bytes", _int, _vp, ctypes.POINTER(_i64))
+rtri_factor_destroy = _sig("rtri_factor_destroy", _int, _vp)
+FACTOR_COPY = 1
+
+
 class BatchEntry(ctypes.Structure):
     _fields_ = [("op", _int), ("side", _int), ("uplo", _int), ("trans", _int), ("diag", _int), ("m", _i64),
                 ("n", _i64), ("alpha", ctypes.c_double), ("A", _vp), ("lda", _i64), ("B", _vp), ("ldb", _i64)]
@@ -241,10 +260,33 @@ def _colmajor(t, name):
     return max(1, t.stride(1) if t.shape[1] > 1 else t.shape[0])
 
 
+def _need_shape(t, name, rows, cols):
+    """Reject a tensor smaller than the rows x cols the call will read or write
+    (the C ABI sees only pointers and leading dimensions, so an undersized
+    tensor would be read past its end)."""
+    if t.dim() != 2 or t.shape[0] < rows or t.shape[1] < cols:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, needs at least ({rows}, {cols})")
+
+
+def _same_device(**ts):
+    devs = {str(t.device) for t in ts.values()}
+    if len(devs) > 1:
+        raise ValueError("tensors on different devices: " + ", ".join(f"{k} on {t.device}" for k, t in ts.items()))
+
+
+def _factor_order(side, B):
+    return B.shape[0] if str(side).upper() == "L" else B.shape[1]
+
+
 def _call(h: Handle, solve: bool, side, uplo, trans, diag, alpha, A, B):
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
+    m, n = B.shape
+    ka = _factor_order(side, B)
+    _need_shape(A, "A", ka, ka)
+    _same_device(A=A, B=B)
     lda = _colmajor(A, "A")
     ldb = _colmajor(B, "B")
-    m, n = B.shape
     if A.dtype != B.dtype:
         raise TypeError("A and B must have the same dtype")
     if B.dtype == torch.float64:
@@ -270,10 +312,15 @@ def trmm(h: Handle, side, uplo, trans, diag, alpha, A, B):
 
 def gemm_update(h: Handle, trans_p: str, trans_q: str, s, P, Q, beta, C):
     """In place: C := beta C + s op(P) op(Q) (the recursion's GEMM update on its own)."""
-    ldp, ldq, ldc = _colmajor(P, "P"), _colmajor(Q, "Q"), _colmajor(C, "C")
     tp, tq = _TRANS[trans_p.upper()], _TRANS[trans_q.upper()]
+    if C.dim() != 2 or P.dim() != 2:
+        raise ValueError("P, Q and C must be 2-D")
     M, N = C.shape
     K = P.shape[0] if tp else P.shape[1]
+    _need_shape(P, "P", K if tp else M, M if tp else K)
+    _need_shape(Q, "Q", N if tq else K, K if tq else N)
+    _same_device(P=P, Q=Q, C=C)
+    ldp, ldq, ldc = _colmajor(P, "P"), _colmajor(Q, "Q"), _colmajor(C, "C")
     dt = {torch.float64: F64, torch.float32: F32}[C.dtype]
     check(rtri_gemm_update(h.ptr, dt, tp, tq, M, N, K, s, P.data_ptr(), ldp, Q.data_ptr(), ldq, beta,
                            C.data_ptr(), ldc), "rtri_gemm_update")
@@ -283,12 +330,18 @@ def gemm_update(h: Handle, trans_p: str, trans_q: str, s, P, Q, beta, C):
 def trmm_ex(h: Handle, side, uplo, trans, diag, alpha, A, B, C):
     """Out of place: C := alpha op(A) B (side 'L') or alpha B op(A) (side 'R'); A, B bfloat16 or float16
     (same type), C float32; FP32 accumulation."""
+    if C.dim() != 2:
+        raise ValueError("C must be 2-D")
+    m, n = C.shape
+    ka = _factor_order(side, C)
+    _need_shape(A, "A", ka, ka)
+    _need_shape(B, "B", m, n)
+    _same_device(A=A, B=B, C=C)
     lda, ldb, ldc = _colmajor(A, "A"), _colmajor(B, "B"), _colmajor(C, "C")
     t = {torch.bfloat16: BF16, torch.float16: F16}[A.dtype]
     tb = {torch.bfloat16: BF16, torch.float16: F16}[B.dtype]
     if C.dtype != torch.float32:
         raise TypeError("C must be float32")
-    m, n = C.shape
     check(rtri_trmm_ex(h.ptr, *codes(side, uplo, trans, diag), m, n, alpha, A.data_ptr(), t, lda, B.data_ptr(), tb,
                        ldb, C.data_ptr(), F32, ldc), "rtri_trmm_ex")
     return C
@@ -299,10 +352,15 @@ def trsm_mixed(h: Handle, side, uplo, trans, diag, alpha, A, B, gemm="bf16", tol
     """In place, FP64: B := X with op(A) X = alpha B (or X op(A) = alpha B) by iterative refinement
     around a low-precision recursive solve (GEMM updates in 'bf16' or 'f32').  Returns the refinement
     record as a dict."""
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
+    m, n = B.shape
+    ka = _factor_order(side, B)
+    _need_shape(A, "A", ka, ka)
+    _same_device(A=A, B=B)
     lda, ldb = _colmajor(A, "A"), _colmajor(B, "B")
     if A.dtype != torch.float64 or B.dtype != torch.float64:
         raise TypeError("A and B must be float64")
-    m, n = B.shape
     info = RefineInfo()
     rc = rtri_dtrsm_mixed(h.ptr, *codes(side, uplo, trans, diag), m, n, alpha, A.data_ptr(), lda, B.data_ptr(),
                           ldb, {"bf16": BF16, "f32": F32}[gemm], tol, max_iter, ctypes.byref(info))
@@ -312,6 +370,169 @@ def trsm_mixed(h: Handle, side, uplo, trans, diag, alpha, A, B, gemm="bf16", tol
                 eta_hist=list(info.eta_hist[:info.iters]))
 
 
+def ztrsm(h: Handle, side, uplo, trans, diag, alpha, A, B):
+    """Complex (complex128) in place: B := X with op(A) X = alpha B or X op(A) = alpha B; trans 'C' is
+    conj(A^T)."""
+    return _zcall(h, True, side, uplo, trans, diag, alpha, A, B)
+
+
+def ztrmm(h: Handle, side, uplo, trans, diag, alpha, A, B):
+    """Complex (complex128) in place: B := alpha op(A) B or alpha B op(A)."""
+    return _zcall(h, False, side, uplo, trans, diag, alpha, A, B)
+
+
+def _zcall(h, solve, side, uplo, trans, diag, alpha, A, B):
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
+    m, n = B.shape
+    ka = _factor_order(side, B)
+    _need_shape(A, "A", ka, ka)
+    _same_device(A=A, B=B)
+    lda, ldb = _colmajor(A, "A"), _colmajor(B, "B")
+    if A.dtype != torch.complex128 or B.dtype != torch.complex128:
+        raise TypeError("A and B must be complex128")
+    a = complex(alpha)
+    al = _c2(a.real, a.imag)
+    fn = rtri_ztrsm if solve else rtri_ztrmm
+    check(fn(h.ptr, *codes(side, uplo, trans, diag), m, n, al, A.data_ptr(), lda, B.data_ptr(), ldb), fn.__name__)
+    return B
+
+
+def trtri(h: Handle, uplo, diag, A):
+    """In place: the triangle of A named by uplo (and its diagonal unless diag='U') becomes that
+    triangle of inv(A)."""
+    if A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError(f"A must be square, got {tuple(A.shape)}")
+    lda = _colmajor(A, "A")
+    fn = {torch.float64: rtri_dtrtri, torch.float32: rtri_strtri}.get(A.dtype)
+    if fn is None:
+        raise TypeError(f"unsupported dtype {A.dtype}")
+    check(fn(h.ptr, _UPLO.get(uplo.upper(), -1), _DIAG.get(diag.upper(), -1), A.shape[0], A.data_ptr(), lda),
+          fn.__name__)
+    return A
+
+
+def potrs(h: Handle, uplo, A, B):
+    """In place: B := X with (L L^T) X = B (uplo 'L') or (U^T U) X = B (uplo 'U'), the factor in A."""
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
+    n, nrhs = B.shape
+    _need_shape(A, "A", n, n)
+    _same_device(A=A, B=B)
+    lda, ldb = _colmajor(A, "A"), _colmajor(B, "B")
+    if A.dtype != B.dtype:
+        raise TypeError("A and B must have the same dtype")
+    fn = {torch.float64: rtri_dpotrs, torch.float32: rtri_spotrs}.get(B.dtype)
+    if fn is None:
+        raise TypeError(f"unsupported dtype {B.dtype}")
+    check(fn(h.ptr, _UPLO.get(uplo.upper(), -1), n, nrhs, A.data_ptr(), lda, B.data_ptr(), ldb), fn.__name__)
+    return B
+
+
+def getrs(h: Handle, trans, LU, ipiv, B):
+    """In place: B := X with S X = B (trans 'N') or S^T X = B (trans 'T') for P S = L U packed in LU;
+    ipiv: LAPACK's 1-based interchange sequence (host integers)."""
+    import numpy as np
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
+    n, nrhs = B.shape
+    _need_shape(LU, "LU", n, n)
+    _same_device(LU=LU, B=B)
+    lda, ldb = _colmajor(LU, "LU"), _colmajor(B, "B")
+    if LU.dtype != B.dtype:
+        raise TypeError("LU and B must have the same dtype")
+    piv = np.ascontiguousarray(np.asarray(ipiv), dtype=np.int32)
+    if piv.shape != (n,):
+        raise ValueError(f"ipiv must have {n} entries")
+    fn = {torch.float64: rtri_dgetrs, torch.float32: rtri_sgetrs}.get(B.dtype)
+    if fn is None:
+        raise TypeError(f"unsupported dtype {B.dtype}")
+    check(fn(h.ptr, _TRANS.get(trans.upper(), -1), n, nrhs, LU.data_ptr(), lda, piv.ctypes.data, B.data_ptr(), ldb),
+          fn.__name__)
+    return B
+
+
+_PREC = {"f64": 0, "mixed_bf16": 1, "mixed_f32": 2}
+
+
+class Factor:
+    """A triangular factor kept for repeated solves and multiplies (see
+    rtri_factor_*): packed diagonal blocks, and for refined solves the GEMM-type
+    copy of A and |op(A)|, are made on first use and kept on the device.
+    Without copy=True the tensor A must stay unchanged while the factor lives
+    (the factor keeps a reference to it)."""
+
+    def __init__(self, h: Handle, uplo, diag, A, copy=False):
+        if A.dim() != 2 or A.shape[0] != A.shape[1]:
+            raise ValueError(f"A must be square, got {tuple(A.shape)}")
+        lda = _colmajor(A, "A")
+        dt = {torch.float64: F64, torch.float32: F32}.get(A.dtype)
+        if dt is None:
+            raise TypeError(f"unsupported dtype {A.dtype}")
+        self.dtype = A.dtype
+        self.order = A.shape[0]
+        u, d = _UPLO.get(uplo.upper(), -1), _DIAG.get(diag.upper(), -1)
+        p = _vp()
+        check(rtri_factor_create(h.ptr, u, d, self.order, dt, A.data_ptr(), lda, FACTOR_COPY if copy else 0,
+                                 ctypes.byref(p)), "rtri_factor_create")
+        self._f = p
+        self._A = None if copy else A
+
+    @property
+    def ptr(self):
+        return self._f
+
+    def _b(self, side, B):
+        if B.dim() != 2:
+            raise ValueError("B must be 2-D")
+        if B.dtype != self.dtype:
+            raise TypeError("B must have the factor's dtype")
+        ka = _factor_order(side, B)
+        if ka != self.order:
+            raise ValueError(f"B has shape {tuple(B.shape)}: side {side} needs order {self.order}")
+        return _colmajor(B, "B")
+
+    def trsm(self, h: Handle, side, trans, alpha, B, precision="f64", tol=1e-12, max_iter=30,
+             allow_not_converged=False):
+        """In place: B := X with op(A) X = alpha B (or X op(A) = alpha B); precision 'f64' (the factor's
+        own type), 'mixed_bf16' or 'mixed_f32' (refined to tol, FP64 factors).  Returns the refinement
+        record as a dict."""
+        ldb = self._b(side, B)
+        m, n = B.shape
+        info = RefineInfo()
+        rc = rtri_factor_trsm(h.ptr, self._f, _SIDE.get(side.upper(), -1), _TRANS.get(trans.upper(), -1), m, n, alpha,
+                              B.data_ptr(), ldb, _PREC[precision], tol, max_iter, ctypes.byref(info))
+        if not (rc == OK or (allow_not_converged and rc == NOT_CONVERGED)):
+            check(rc, "rtri_factor_trsm")
+        return dict(status=rc, iters=info.iters, converged=bool(info.converged), eta=info.eta, anorm=info.anorm,
+                    eta_hist=list(info.eta_hist[:info.iters]))
+
+    def trmm(self, h: Handle, side, trans, alpha, B):
+        """In place: B := alpha op(A) B (or alpha B op(A))."""
+        ldb = self._b(side, B)
+        m, n = B.shape
+        check(rtri_factor_trmm(h.ptr, self._f, _SIDE.get(side.upper(), -1), _TRANS.get(trans.upper(), -1), m, n,
+                               alpha, B.data_ptr(), ldb), "rtri_factor_trmm")
+        return B
+
+    def bytes(self) -> int:
+        v = _i64()
+        check(rtri_factor_bytes(self._f, ctypes.byref(v)), "rtri_factor_bytes")
+        return v.value
+
+    def close(self):
+        if self._f:
+            rtri_factor_destroy(self._f)
+            self._f = _vp()
+            self._A = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def batch_entries(problems):
     """problems: iterable of (op 'trsm'|'trmm', side, uplo, trans, diag, alpha, A, B) with column-major
     device tensors of one dtype.  Returns (ctypes array of BatchEntry, dtype code)."""
@@ -319,6 +540,11 @@ def batch_entries(problems):
     arr = (BatchEntry * max(1, len(problems)))()
     dt = None
     for i, (op, side, uplo, trans, diag, alpha, A, B) in enumerate(problems):
+        if B.dim() != 2:
+            raise ValueError(f"problem {i}: B must be 2-D")
+        ka = _factor_order(side, B)
+        _need_shape(A, f"problem {i}: A", ka, ka)
+        _same_device(A=A, B=B)
         lda, ldb = _colmajor(A, "A"), _colmajor(B, "B")
         d = {torch.float64: F64, torch.float32: F32}[B.dtype]
         if dt is None:
@@ -451,7 +677,8 @@ def to_device(a, dtype=None, device="cuda", ld=None):
     a = np.asarray(a)
     m, n = a.shape
     ld = m if ld is None else ld
-    dt = dtype if dtype is not None else {np.dtype("float64"): torch.float64, np.dtype("float32"): torch.float32}[a.dtype]
+    dt = dtype if dtype is not None else {np.dtype("float64"): torch.float64, np.dtype("float32"): torch.float32,
+                                          np.dtype("complex128"): torch.complex128}[a.dtype]
     store = torch.zeros((n, ld), dtype=dt, device=device)
     # narrower types are rounded by torch (round to nearest even)
     store[:, :m] = torch.from_numpy(np.ascontiguousarray(a.T)).to(device=device).to(dtype=dt)

@@ -348,6 +348,65 @@ bool trmm_one_launch(const rtri_handle *h, int leaf, int64_t ka, int64_t nvec)
     return nvec < 8192;
 }
 
+size_t plan_pack_bytes(const PlanIn &p)
+{
+    const int64_t ka = p.side == RTRI_LEFT ? p.m : p.n;
+    const int64_t nblk = (ka + p.leaf - 1) / p.leaf;
+    return (size_t)(nblk * pack_elems(p.leaf)) * (p.bt == DType::F64 ? 8 : 4);
+}
+
+hipError_t pack_plan(rtri_handle *h, const PlanIn &p, void *out)
+{
+    const int64_t ka = p.side == RTRI_LEFT ? p.m : p.n;
+    const int64_t nblk = (ka + p.leaf - 1) / p.leaf;
+    const size_t es = p.bt == DType::F64 ? 8 : 4;
+    const bool low = (p.uplo == RTRI_LOWER) != (p.trans != RTRI_NOTRANS);
+    PackDesc pk{};
+    pk.A = p.As;
+    pk.lda = p.ldas;
+    pk.ka = ka;
+    pk.unit = p.diag == RTRI_UNIT;
+    if (p.side == RTRI_LEFT) {
+        pk.mtrans = p.trans != RTRI_NOTRANS;
+        pk.mlower = low;
+    } else {
+        pk.mtrans = p.trans == RTRI_NOTRANS;
+        pk.mlower = !low;
+    }
+    pk.out = out;
+    return timed(h, RTRI_KCLASS_OTHER, dtype_code(p.st), 0.0,
+                 (double)elem_size(p.st) * ka * (double)p.leaf + (double)es * nblk * pack_elems(p.leaf),
+                 [&] { return launch_pack(p.st, p.bt, p.solve, p.leaf, pk, h->stream); });
+}
+
+PlanIn plain_plan(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                  double alpha, const void *A, int64_t lda, void *B, int64_t ldb)
+{
+    PlanIn p{};
+    p.solve = solve;
+    p.side = side;
+    p.uplo = uplo;
+    p.trans = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    p.diag = diag;
+    p.m = m;
+    p.n = n;
+    p.alpha = alpha;
+    p.bt = t;
+    p.B = static_cast<char *>(B);
+    p.ldb = ldb;
+    p.gt = t == DType::F64 ? ElemT::F64 : ElemT::F32;
+    p.Ag = static_cast<const char *>(A);
+    p.ldag = lda;
+    p.st = p.gt;
+    p.As = A;
+    p.ldas = lda;
+    p.leaf = pick_leaf(h, t, solve, side == RTRI_LEFT ? m : n, side == RTRI_LEFT ? n : m);
+    p.pack_slot = WS_PACK;
+    p.skip_pack = false;
+    p.packed = nullptr;
+    return p;
+}
+
 int run_plan(rtri_handle *h, const PlanIn &p)
 {
     const int64_t ka = p.side == RTRI_LEFT ? p.m : p.n;
@@ -374,33 +433,18 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     pl.rec(0, ka, p.alpha);
 
     // pack every diagonal block once into the canonical form the leaves read
-    const int64_t nblk = (ka + p.leaf - 1) / p.leaf;
-    if (!p.skip_pack) {
-        hipError_t e0 = ensure_ws(h, p.pack_slot, (size_t)(nblk * pack_elems(p.leaf)) * es);
-        if (e0 != hipSuccess)
-            return hip_fail(h, e0);
-        PackDesc pk{};
-        pk.A = p.As;
-        pk.lda = p.ldas;
-        pk.ka = ka;
-        pk.unit = p.diag == RTRI_UNIT;
-        if (p.side == RTRI_LEFT) {
-            pk.mtrans = p.trans != RTRI_NOTRANS;
-            pk.mlower = pl.low;
-        } else {
-            pk.mtrans = p.trans == RTRI_NOTRANS;
-            pk.mlower = !pl.low;
-        }
-        pk.out = h->ws[p.pack_slot];
-        e0 = timed(h, RTRI_KCLASS_OTHER, dtype_code(p.st), 0.0,
-                   (double)elem_size(p.st) * ka * (double)p.leaf + (double)es * nblk * pack_elems(p.leaf),
-                   [&] { return launch_pack(p.st, bt, p.solve, p.leaf, pk, h->stream); });
+    // (unless the plan brings its blocks packed already)
+    if (p.packed == nullptr && !p.skip_pack) {
+        hipError_t e0 = ensure_ws(h, p.pack_slot, plan_pack_bytes(p));
+        if (e0 == hipSuccess)
+            e0 = pack_plan(h, p, h->ws[p.pack_slot]);
         if (e0 != hipSuccess)
             return hip_fail(h, e0);
     }
+    const char *pack_base = static_cast<const char *>(p.packed != nullptr ? p.packed : h->ws[p.pack_slot]);
     for (Op &op : pl.ops)
         if (!op.gemm)
-            op.l.Lp = static_cast<const char *>(h->ws[p.pack_slot]) + reinterpret_cast<intptr_t>(op.l.Lp);
+            op.l.Lp = pack_base + reinterpret_cast<intptr_t>(op.l.Lp);
 
     const bool g16 = p.gt == ElemT::BF16 || p.gt == ElemT::F16;
     const size_t ges = elem_size(p.gt);
@@ -458,7 +502,7 @@ int run_plan(rtri_handle *h, const PlanIn &p)
                 if (all.nvec == 0) {
                     all = op.l;
                     all.B = p.B;   // block 0 starts at element 0 of the panel
-                    all.Lp = h->ws[p.pack_slot];
+                    all.Lp = pack_base;
                     all.nb = p.leaf;
                     all.ka = ka;
                 }
@@ -530,28 +574,7 @@ int run(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int 
                              [&] { return launch_fill(t, B, m, n, ldb, 0.0, h->stream); });
         return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
     }
-    PlanIn p{};
-    p.solve = solve;
-    p.side = side;
-    p.uplo = uplo;
-    p.trans = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
-    p.diag = diag;
-    p.m = m;
-    p.n = n;
-    p.alpha = alpha;
-    p.bt = t;
-    p.B = static_cast<char *>(B);
-    p.ldb = ldb;
-    p.gt = t == DType::F64 ? ElemT::F64 : ElemT::F32;
-    p.Ag = static_cast<const char *>(A);
-    p.ldag = lda;
-    p.st = p.gt;
-    p.As = A;
-    p.ldas = lda;
-    p.leaf = pick_leaf(h, t, solve, side == RTRI_LEFT ? m : n, side == RTRI_LEFT ? n : m);
-    p.pack_slot = WS_PACK;
-    p.skip_pack = false;
-    return run_plan(h, p);
+    return run_plan(h, plain_plan(h, t, solve, side, uplo, trans, diag, m, n, alpha, A, lda, B, ldb));
 }
 
 }  // namespace
@@ -596,6 +619,7 @@ int rtri_create(rtri_handle **out, void *stream)
     h->profiling = false;
     h->pool_used = 0;
     h->aux_ready = false;
+    h->mem_pool = nullptr;
     // a tuning database named by the environment applies to every new handle
     if (const char *db = std::getenv("RTRI_TUNE_DB"))
         (void)load_tuning_file(h, db);

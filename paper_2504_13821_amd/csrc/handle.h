@@ -35,6 +35,10 @@ enum WsSlot {
     WS_SCALARS,      // small reduction results
     WS_SAVE,         // copy of a TRMM panel's original values (all leaves in one launch)
     WS_SPLIT,        // split-K partial products, one region per stream an update may run on
+    WS_ROWS,         // copy of a right-hand side whose rows are interchanged (GETRS)
+    WS_PERM,         // the row permutation of those interchanges
+    WS_ZEMB,         // real embedding of a complex op(A) (2 ka x 2 ka)
+    WS_ZT,           // transposed complex right-hand side (side R)
     WS_COUNT
 };
 
@@ -59,6 +63,9 @@ struct PlanIn {
     int leaf;
     int pack_slot;                 // workspace slot holding the packed blocks
     bool skip_pack;                // the packed blocks are already in pack_slot
+    // packed blocks made earlier for this exact plan (a factor keeps them):
+    // used in place of pack_slot, and no pack pass runs; nullptr otherwise
+    const void *packed;
     // TRMM with a 16-bit GEMM copy of A: the original panel in that 16-bit type
     // (the panel B holds it widened), read by the GEMM updates in place of the
     // panel or its saved copy; nullptr otherwise
@@ -86,6 +93,10 @@ struct rtri_handle {
     std::vector<rtri::ProfRec> recs;
     std::vector<hipEvent_t> pool;
     size_t pool_used;
+    // memory pool for the parts of factors this handle prepares (a serving
+    // slot's own pool, so freed blocks are reused only in its stream's order);
+    // nullptr: plain hipMalloc / hipFree
+    hipMemPool_t mem_pool;
 };
 
 namespace rtri {
@@ -115,9 +126,52 @@ int check_args(int side, int uplo, int trans, int diag, int64_t m, int64_t n, co
                const void *B, int64_t ldb, bool need_a);
 // enqueue a whole plan on the handle's stream (returns an RTRI_* status)
 int run_plan(rtri_handle *h, const PlanIn &p);
+// the packed diagonal blocks of a plan: their size in bytes, and the pack pass
+// writing them to out (on the handle's stream)
+size_t plan_pack_bytes(const PlanIn &p);
+hipError_t pack_plan(rtri_handle *h, const PlanIn &p, void *out);
+// the plan of a plain FP64 / FP32 TRSM or TRMM as the BLAS-style entry points
+// build it (trans 'C' folded to 'T', leaf from the handle's policy)
+PlanIn plain_plan(rtri_handle *h, DType t, bool solve, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                  double alpha, const void *A, int64_t lda, void *B, int64_t ldb);
 // launch through f(); inside a profile, bracket it with events and record its work
 hipError_t timed_launch(rtri_handle *h, int kclass, int dtype, double flops, double bytes, hipError_t (*fn)(void *),
                         void *ctx);
+
+// What the refined solve needs from A besides A itself, made once per call by
+// rtri_dtrsm_mixed or once per factor by a factor object (eqs. (3)/(4)):
+struct MixedPrep {
+    const void *Acopy = nullptr;    // A (or A^T when ag_trans) in the GEMM type, leading dimension ldag
+    int64_t ldag = 0;
+    bool ag_trans = false;
+    const void *lo_pack = nullptr;  // packed FP32 solve blocks for leaf lo_leaf; nullptr: packed on first use
+    const void *mul_pack = nullptr; // packed FP64 multiply blocks for leaf mul_leaf; nullptr: likewise
+    int lo_leaf = 0, mul_leaf = 0;
+    bool have_anorm = false;        // anorm known (else computed by the call)
+    double anorm = 0.0;             // |op(A)|_inf (side L) or |op(A)|_1 (side R)
+};
+// the GEMM copy's orientation: A^T where the 16-bit GEMM's triangle operand is
+// then k-contiguous (side L with trans N, side R with trans T)
+inline bool mixed_ag_trans(ElemT gt, int side, int tr)
+{
+    return gt == ElemT::BF16 && (side == RTRI_LEFT ? tr == RTRI_NOTRANS : tr != RTRI_NOTRANS);
+}
+// refined solve on checked arguments (m, n > 0, alpha != 0, trans 'C' folded)
+int mixed_core(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
+               const double *A, int64_t lda, double *B, int64_t ldb, ElemT gt, double tol, int max_iter,
+               rtri_refine_info *info, const MixedPrep &prep);
+// lines of op(A) (side L) or op(A)^T (side R) summed into out[0] (anorm)
+hipError_t launch_mixed_norm(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t ka, const double *A,
+                             int64_t lda, unsigned long long *out);
+// the GEMM copy of A for the refined solve (conversion, transposed when ag_trans)
+hipError_t launch_mixed_copy(rtri_handle *h, ElemT gt, bool ag_trans, int64_t ka, const double *A, int64_t lda,
+                             void *Acopy, int64_t ldag);
+// the two plans of the refined solve: low-precision solve on the FP32 panel D
+// and the FP64 multiply of the residual on W (workspace pointers filled by the caller)
+PlanIn mixed_lo_plan(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, ElemT gt,
+                     const double *A, int64_t lda);
+PlanIn mixed_mul_plan(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, const double *A,
+                      int64_t lda);
 
 // Reusable staging for batched launches issued by a long-lived caller (a
 // serving slot): pinned host tables and their device copy, grown on demand.

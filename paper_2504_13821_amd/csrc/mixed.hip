@@ -32,6 +32,204 @@ double from_bits(unsigned long long b)
 
 }  // namespace
 
+namespace rtri {
+
+hipError_t launch_mixed_copy(rtri_handle *h, ElemT gt, bool ag_trans, int64_t ka, const double *A, int64_t lda,
+                             void *Acopy, int64_t ldag)
+{
+    return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, 8.0 * ka * ka, [&] {
+        return ag_trans ? launch_transpose_convert(gt, A, lda, Acopy, ldag, ka, ka, h->stream)
+                        : launch_convert(ElemT::F64, gt, A, lda, Acopy, ldag, ka, ka, 1.0, h->stream);
+    });
+}
+
+hipError_t launch_mixed_norm(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t ka, const double *A,
+                             int64_t lda, unsigned long long *out)
+{
+    const bool left = side == RTRI_LEFT;
+    const bool low = (uplo == RTRI_LOWER) != (tr != RTRI_NOTRANS);
+    return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, 4.0 * ka * ka, [&] {
+        // lines of op(A) (LEFT) or of op(A)^T (RIGHT): |op(A)|_inf or |op(A)|_1
+        return launch_line_norm(A, lda, ka, left ? tr != RTRI_NOTRANS : tr == RTRI_NOTRANS, left ? low : !low,
+                                diag == RTRI_UNIT, out, h->stream);
+    });
+}
+
+PlanIn mixed_lo_plan(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, ElemT gt,
+                     const double *A, int64_t lda)
+{
+    const int64_t ka = side == RTRI_LEFT ? m : n;
+    PlanIn lo{};
+    lo.solve = true;
+    lo.side = side;
+    lo.uplo = uplo;
+    lo.trans = tr;
+    lo.diag = diag;
+    lo.m = m;
+    lo.n = n;
+    lo.alpha = 1.0;
+    lo.bt = DType::F32;
+    lo.gt = gt;
+    lo.ag_trans = mixed_ag_trans(gt, side, tr);
+    lo.st = ElemT::F64;
+    lo.As = A;
+    lo.ldas = lda;
+    lo.leaf = pick_leaf(h, DType::F32, true, ka, side == RTRI_LEFT ? n : m);
+    lo.pack_slot = WS_PACK2;
+    return lo;
+}
+
+PlanIn mixed_mul_plan(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, const double *A,
+                      int64_t lda)
+{
+    const int64_t ka = side == RTRI_LEFT ? m : n;
+    PlanIn mul{};
+    mul.solve = false;
+    mul.side = side;
+    mul.uplo = uplo;
+    mul.trans = tr;
+    mul.diag = diag;
+    mul.m = m;
+    mul.n = n;
+    mul.alpha = 1.0;
+    mul.bt = DType::F64;
+    mul.gt = ElemT::F64;
+    mul.Ag = reinterpret_cast<const char *>(A);
+    mul.ldag = lda;
+    mul.st = ElemT::F64;
+    mul.As = A;
+    mul.ldas = lda;
+    mul.leaf = pick_leaf(h, DType::F64, false, ka, side == RTRI_LEFT ? n : m);
+    mul.pack_slot = WS_PACK;
+    return mul;
+}
+
+int mixed_core(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
+               const double *A, int64_t lda, double *B, int64_t ldb, ElemT gt, double tol, int max_iter,
+               rtri_refine_info *info, const MixedPrep &prep)
+{
+    hipStream_t st = h->stream;
+    hipError_t e;
+    int rc;
+    const bool left = side == RTRI_LEFT;
+    const int64_t ka = left ? m : n;
+    const size_t mn = (size_t)m * (size_t)n;
+
+    const int64_t ld = ws_ld(m);
+    const size_t ln = (size_t)ld * (size_t)n;
+    const size_t need[] = {ln * 4, ln * 8, ln * 8, ln * 8, ln * 8, 64};
+    const int slot[] = {WS_PANEL32, WS_X, WS_R0, WS_R, WS_W, WS_SCALARS};
+    for (int i = 0; i < 6; ++i) {
+        e = ensure_ws(h, slot[i], need[i]);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+    }
+    float *D = static_cast<float *>(h->ws[WS_PANEL32]);
+    double *X = static_cast<double *>(h->ws[WS_X]);
+    double *R0 = static_cast<double *>(h->ws[WS_R0]);
+    double *R = static_cast<double *>(h->ws[WS_R]);
+    double *W = static_cast<double *>(h->ws[WS_W]);
+    unsigned long long *sc = static_cast<unsigned long long *>(h->ws[WS_SCALARS]);
+
+    // once per call: |op(A)| (unless known), alpha B, max |R|
+    auto other = [&](double bytes, auto &&f) { return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, bytes, f); };
+    e = launch_zero_u64(sc, 4, st);
+    if (e == hipSuccess && !prep.have_anorm)
+        e = launch_mixed_norm(h, side, uplo, tr, diag, ka, A, lda, sc + 2);
+    if (e == hipSuccess)
+        e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, B, ldb, R0, ld, m, n, alpha, st); });
+    // the first residual is alpha B itself (X = 0): it is read from R0, and the
+    // first correction is assigned to X rather than added
+    if (e == hipSuccess)
+        e = other(8.0 * mn, [&] { return launch_max_abs(R0, ld, m, n, sc + 1, st); });
+    unsigned long long host[4];
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, sc, sizeof host, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    const double anorm = prep.have_anorm ? prep.anorm : from_bits(host[2]);
+    double rmax = from_bits(host[1]);
+    if (info != nullptr)
+        info->anorm = anorm;
+
+    PlanIn lo = mixed_lo_plan(h, side, uplo, tr, diag, m, n, gt, A, lda);
+    lo.B = reinterpret_cast<char *>(D);
+    lo.ldb = ld;
+    lo.Ag = static_cast<const char *>(prep.Acopy);
+    lo.ldag = prep.ldag;
+    lo.ag_trans = prep.ag_trans;
+    if (prep.lo_pack != nullptr && prep.lo_leaf == lo.leaf)
+        lo.packed = prep.lo_pack;
+    PlanIn mul = mixed_mul_plan(h, side, uplo, tr, diag, m, n, A, lda);
+    mul.B = reinterpret_cast<char *>(W);
+    mul.ldb = ld;
+    if (prep.mul_pack != nullptr && prep.mul_leaf == mul.leaf)
+        mul.packed = prep.mul_pack;
+
+    double eta = rmax == 0.0 ? 0.0 : INFINITY, eta_prev = INFINITY;
+    int iters = 0;
+    bool converged = eta <= tol;
+    while (!converged && iters < max_iter && rmax > 0.0 && std::isfinite(rmax)) {
+        const double s = std::ldexp(1.0, (int)std::ceil(std::log2(rmax)));
+        const double *Rk = iters == 0 ? R0 : R;
+        e = other(12.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F32, Rk, ld, D, ld, m, n, 1.0 / s, st); });
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        rc = run_plan(h, lo);
+        if (rc != RTRI_OK)
+            return rc;
+        lo.skip_pack = true;
+        // X += s D (X = s D the first time), and W = X for the residual's product (one pass)
+        const bool assign = iters == 0;
+        e = other((assign ? 20.0 : 28.0) * mn,
+                  [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, assign, W, ld, st); });
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        rc = run_plan(h, mul);
+        if (rc != RTRI_OK)
+            return rc;
+        mul.skip_pack = true;
+        e = launch_zero_u64(sc, 2, st);
+        if (e == hipSuccess)
+            e = other(32.0 * mn, [&] {
+                return launch_resid_eta(R0, ld, W, ld, R, ld, X, ld, m, n, left, anorm, sc, st);
+            });
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(host, sc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        eta = from_bits(host[0]);
+        rmax = from_bits(host[1]);
+        if (info != nullptr && iters < 32)
+            info->eta_hist[iters] = eta;
+        ++iters;
+        if (eta <= tol) {
+            converged = true;
+            break;
+        }
+        if (!(eta <= 0.5 * eta_prev))   // stagnation (or NaN)
+            break;
+        eta_prev = eta;
+    }
+    // no correction made (alpha B is zero, or not finite): X = 0
+    e = iters == 0 ? other(8.0 * mn, [&] { return launch_fill(DType::F64, B, m, n, ldb, 0.0, st); })
+                   : other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, X, ld, B, ldb, m, n, 1.0, st); });
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    if (info != nullptr) {
+        info->iters = iters;
+        info->converged = converged ? 1 : 0;
+        info->eta = eta;
+    }
+    return converged ? RTRI_OK : RTRI_NOT_CONVERGED;
+}
+
+}  // namespace rtri
+
 extern "C" {
 
 int rtri_trmm_ex(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, float alpha,
@@ -124,185 +322,31 @@ int rtri_dtrsm_mixed(rtri_handle *h, int side, int uplo, int trans, int diag, in
         return -14;
     if (max_iter < 1 || max_iter > 32)
         return -15;
-    if (info != nullptr) {
+    if (info != nullptr)
         std::memset(info, 0, sizeof *info);
-    }
-    if (m == 0 || n == 0) {
+    if (m == 0 || n == 0 || alpha == 0.0) {
         if (info != nullptr)
             info->converged = 1;
-        return RTRI_OK;
-    }
-    hipStream_t st = h->stream;
-    hipError_t e;
-    if (alpha == 0.0) {
-        e = launch_fill(DType::F64, B, m, n, ldb, 0.0, st);
-        if (info != nullptr)
-            info->converged = 1;
+        if (m == 0 || n == 0)
+            return RTRI_OK;
+        const hipError_t e = launch_fill(DType::F64, B, m, n, ldb, 0.0, h->stream);
         return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
     }
-    const bool left = side == RTRI_LEFT;
-    const int64_t ka = left ? m : n;
+    const int64_t ka = side == RTRI_LEFT ? m : n;
     const int tr = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
-    const bool low = (uplo == RTRI_LOWER) != (tr != RTRI_NOTRANS);
     const ElemT gt = gemm_type == RTRI_BF16 ? ElemT::BF16 : ElemT::F32;
-    const size_t mn = (size_t)m * (size_t)n;
-
-    const int64_t ld = ws_ld(m), ldag = ws_ld(ka);
-    const size_t ln = (size_t)ld * (size_t)n;
-    const size_t need[] = {(size_t)ka * (size_t)ldag * elem_size(gt), ln * 4, ln * 8, ln * 8, ln * 8, ln * 8, 64};
-    const int slot[] = {WS_ACOPY, WS_PANEL32, WS_X, WS_R0, WS_R, WS_W, WS_SCALARS};
-    for (int i = 0; i < 7; ++i) {
-        e = ensure_ws(h, slot[i], need[i]);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-    }
-    void *Acopy = h->ws[WS_ACOPY];
-    float *D = static_cast<float *>(h->ws[WS_PANEL32]);
-    double *X = static_cast<double *>(h->ws[WS_X]);
-    double *R0 = static_cast<double *>(h->ws[WS_R0]);
-    double *R = static_cast<double *>(h->ws[WS_R]);
-    double *W = static_cast<double *>(h->ws[WS_W]);
-    unsigned long long *sc = static_cast<unsigned long long *>(h->ws[WS_SCALARS]);
-
-    // once per call: the GEMM copy of A, |op(A)|, alpha B, X = 0, max |R|
-    auto other = [&](double bytes, auto &&f) { return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, bytes, f); };
-    // The 16-bit GEMM wants its triangle operand with k contiguous: for side L
-    // (operand op(A)) and trans N, or side R (operand op(A), k = rows) and
-    // trans T, the BF16 copy holds A^T.
-    const bool ag_trans = gt == ElemT::BF16 && (left ? tr == RTRI_NOTRANS : tr != RTRI_NOTRANS);
-    e = other(8.0 * ka * ka, [&] {
-        return ag_trans ? launch_transpose_convert(gt, A, lda, Acopy, ldag, ka, ka, st)
-                        : launch_convert(ElemT::F64, gt, A, lda, Acopy, ldag, ka, ka, 1.0, st);
-    });
+    // once per call: the GEMM copy of A (the packed blocks and |op(A)| are
+    // made by the core on its first use)
+    MixedPrep prep;
+    prep.ldag = ws_ld(ka);
+    prep.ag_trans = mixed_ag_trans(gt, side, tr);
+    hipError_t e = ensure_ws(h, WS_ACOPY, (size_t)ka * (size_t)prep.ldag * elem_size(gt));
     if (e == hipSuccess)
-        e = launch_zero_u64(sc, 4, st);
-    if (e == hipSuccess)
-        e = other(4.0 * ka * ka, [&] {
-            // lines of op(A) (LEFT) or of op(A)^T (RIGHT): |op(A)|_inf or |op(A)|_1
-            return launch_line_norm(A, lda, ka, left ? tr != RTRI_NOTRANS : tr == RTRI_NOTRANS, left ? low : !low,
-                                    diag == RTRI_UNIT, sc + 2, st);
-        });
-    if (e == hipSuccess)
-        e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, B, ldb, R0, ld, m, n, alpha, st); });
-    // the first residual is alpha B itself (X = 0): it is read from R0, and the
-    // first correction is assigned to X rather than added
-    if (e == hipSuccess)
-        e = other(8.0 * mn, [&] { return launch_max_abs(R0, ld, m, n, sc + 1, st); });
-    unsigned long long host[4];
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(host, sc, sizeof host, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(st);
+        e = launch_mixed_copy(h, gt, prep.ag_trans, ka, A, lda, h->ws[WS_ACOPY], prep.ldag);
     if (e != hipSuccess)
         return hip_fail(h, e);
-    const double anorm = from_bits(host[2]);
-    double rmax = from_bits(host[1]);
-    if (info != nullptr)
-        info->anorm = anorm;
-
-    PlanIn lo{};
-    lo.solve = true;
-    lo.side = side;
-    lo.uplo = uplo;
-    lo.trans = tr;
-    lo.diag = diag;
-    lo.m = m;
-    lo.n = n;
-    lo.alpha = 1.0;
-    lo.bt = DType::F32;
-    lo.B = reinterpret_cast<char *>(D);
-    lo.ldb = ld;
-    lo.gt = gt;
-    lo.Ag = static_cast<const char *>(Acopy);
-    lo.ldag = ldag;
-    lo.ag_trans = ag_trans;
-    lo.st = ElemT::F64;
-    lo.As = A;
-    lo.ldas = lda;
-    lo.leaf = pick_leaf(h, DType::F32, true, ka, left ? n : m);
-    lo.pack_slot = WS_PACK2;
-    lo.skip_pack = false;
-
-    PlanIn mul{};
-    mul.solve = false;
-    mul.side = side;
-    mul.uplo = uplo;
-    mul.trans = tr;
-    mul.diag = diag;
-    mul.m = m;
-    mul.n = n;
-    mul.alpha = 1.0;
-    mul.bt = DType::F64;
-    mul.B = reinterpret_cast<char *>(W);
-    mul.ldb = ld;
-    mul.gt = ElemT::F64;
-    mul.Ag = reinterpret_cast<const char *>(A);
-    mul.ldag = lda;
-    mul.st = ElemT::F64;
-    mul.As = A;
-    mul.ldas = lda;
-    mul.leaf = pick_leaf(h, DType::F64, false, ka, left ? n : m);
-    mul.pack_slot = WS_PACK;
-    mul.skip_pack = false;
-
-    double eta = rmax == 0.0 ? 0.0 : INFINITY, eta_prev = INFINITY;
-    int iters = 0;
-    bool converged = eta <= tol;
-    while (!converged && iters < max_iter && rmax > 0.0 && std::isfinite(rmax)) {
-        const double s = std::ldexp(1.0, (int)std::ceil(std::log2(rmax)));
-        const double *Rk = iters == 0 ? R0 : R;
-        e = other(12.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F32, Rk, ld, D, ld, m, n, 1.0 / s, st); });
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        rc = run_plan(h, lo);
-        if (rc != RTRI_OK)
-            return rc;
-        lo.skip_pack = true;
-        // X += s D (X = s D the first time), and W = X for the residual's product (one pass)
-        const bool assign = iters == 0;
-        e = other((assign ? 20.0 : 28.0) * mn,
-                  [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, assign, W, ld, st); });
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        rc = run_plan(h, mul);
-        if (rc != RTRI_OK)
-            return rc;
-        mul.skip_pack = true;
-        e = launch_zero_u64(sc, 2, st);
-        if (e == hipSuccess)
-            e = other(32.0 * mn, [&] {
-                return launch_resid_eta(R0, ld, W, ld, R, ld, X, ld, m, n, left, anorm, sc, st);
-            });
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(host, sc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(st);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        eta = from_bits(host[0]);
-        rmax = from_bits(host[1]);
-        if (info != nullptr && iters < 32)
-            info->eta_hist[iters] = eta;
-        ++iters;
-        if (eta <= tol) {
-            converged = true;
-            break;
-        }
-        if (!(eta <= 0.5 * eta_prev))   // stagnation (or NaN)
-            break;
-        eta_prev = eta;
-    }
-    // no correction made (alpha B is zero, or not finite): X = 0
-    e = iters == 0 ? other(8.0 * mn, [&] { return launch_fill(DType::F64, B, m, n, ldb, 0.0, st); })
-                   : other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, X, ld, B, ldb, m, n, 1.0, st); });
-    if (e != hipSuccess)
-        return hip_fail(h, e);
-    if (info != nullptr) {
-        info->iters = iters;
-        info->converged = converged ? 1 : 0;
-        info->eta = eta;
-    }
-    return converged ? RTRI_OK : RTRI_NOT_CONVERGED;
+    prep.Acopy = h->ws[WS_ACOPY];
+    return mixed_core(h, side, uplo, tr, diag, m, n, alpha, A, lda, B, ldb, gt, tol, max_iter, info, prep);
 }
 
 }  // extern "C"

@@ -13,9 +13,13 @@
 //      synthetic factor is allocated and generated on the admitting slot's
 //      stream right away, and an event marks it ready for any other slot.
 //   2. without the lock: wait for the factors' events, generate the
-//      right-hand sides, run one batched launch (or the single-call recursion,
-//      or the mixed-precision refined solve), copy requested results to the
-//      host, wait for the stream.
+//      right-hand sides, run one batched launch (or, through the cached
+//      factor's factor object, the single-call recursion or the
+//      mixed-precision refined solve), copy requested results to the host,
+//      wait for the stream.  A factor object keeps what the solves against its
+//      factor share (packed diagonal blocks, the refined solve's GEMM-type copy
+//      and |op(A)|), so only the first request on a factor makes them; it is
+//      counted in the factor's memory and freed when the factor is evicted.
 //   3. under the lock: release the reservations, record the completions.
 // Several slots run at once, so requests arriving while others run are
 // admitted as slots and memory free up, and their work overlaps on the device.
@@ -54,12 +58,15 @@ struct Factor {
     bool registered = false;
     int owner = -1;               // slot whose pool and stream hold a synthetic factor
     hipEvent_t ready = nullptr;   // recorded after generation (synthetic factors)
+    rtri_factor *fo[2] = {nullptr, nullptr};   // factor objects on ptr, per diag (made at first admission)
+    size_t part_bytes = 0;        // device memory the factor objects hold (counted in used)
 };
 
 struct Work {
     std::vector<Req> reqs;
     bool batched = false;
     size_t ws_extra = 0;      // device memory reserved for the slot's workspace growth
+    size_t part_extra = 0;    // reserved for parts a factor object may make (work run alone)
     size_t tables = 0;        // upper bound of the batch tables (batched work)
 };
 
@@ -142,19 +149,18 @@ size_t alone_growth(const rtri_handle *h, const Req &q)
     // split-K partials (an upper bound: allocated once some update of the plan splits)
     if (may_split(q.ka))
         need[WS_SPLIT] = SPLIT_WS_BYTES;
+    // (the packed blocks and the refined solve's copy of A belong to the
+    // factor object: part_growth below)
+    (void)pack_bytes;
     if (r.precision == RTRI_PREC_F64) {
-        need[WS_PACK] = pack_bytes(DType::F64, r.op == 0);
         if (r.op == 1)
             need[WS_SAVE] = save_bytes();
     } else {
         // the refinement's matrices use the padded leading dimension ws_ld
         const size_t ln = (size_t)ws_ld(r.m) * (size_t)r.n;
-        need[WS_ACOPY] = (size_t)q.ka * (size_t)ws_ld(q.ka) * (r.precision == RTRI_PREC_MIXED_BF16 ? 2 : 4);
         need[WS_PANEL32] = ln * 4;
         need[WS_X] = need[WS_R0] = need[WS_R] = need[WS_W] = ln * 8;
         need[WS_SCALARS] = 64;
-        need[WS_PACK2] = pack_bytes(DType::F32, true);
-        need[WS_PACK] = pack_bytes(DType::F64, false);
         need[WS_SAVE] = save_bytes();
     }
     size_t g = 0;
@@ -162,6 +168,33 @@ size_t alone_growth(const rtri_handle *h, const Req &q)
         if (need[i] > h->ws_bytes[i])
             g += std::max(need[i], WS_MIN) - h->ws_bytes[i];
     return g;
+}
+
+// upper bound of the memory a factor object may add running q alone: the
+// packed blocks of its plans and, for a refined solve, the GEMM-type copy of A
+size_t part_growth(const rtri_handle *h, const Req &q)
+{
+    const rtri_request &r = q.r;
+    const int64_t nvec = r.side == RTRI_LEFT ? r.n : r.m;
+    auto pack_bytes = [&](DType t, bool solve) {
+        const int leaf = pick_leaf(h, t, solve, q.ka, nvec);
+        return (size_t)((q.ka + leaf - 1) / leaf) * (size_t)pack_elems(leaf) * (t == DType::F64 ? 8 : 4) + 256;
+    };
+    if (r.precision == RTRI_PREC_F64)
+        return pack_bytes(DType::F64, r.op == 0);
+    return (size_t)q.ka * (size_t)ws_ld(q.ka) * (r.precision == RTRI_PREC_MIXED_BF16 ? 2 : 4) +
+           pack_bytes(DType::F32, true) + pack_bytes(DType::F64, false);
+}
+
+size_t factor_object_bytes(const Factor &f)
+{
+    size_t b = 0;
+    for (rtri_factor *o : f.fo) {
+        int64_t v = 0;
+        if (o != nullptr && rtri_factor_bytes(o, &v) == RTRI_OK)
+            b += (size_t)v;
+    }
+    return b;
 }
 
 // upper bound of one request's share of the batch tables (instance record,
@@ -188,10 +221,15 @@ bool evict_one(rtri_server *s, hipStream_t st)
     // no request uses it and every earlier user has completed on the host
     // side; the memory goes back to its owner's pool in the owner's stream order
     (void)st;
+    for (rtri_factor *&o : f.fo)
+        if (o != nullptr) {
+            (void)rtri_factor_destroy(o);   // its parts go back to the pools of the slots that made them
+            o = nullptr;
+        }
     (void)hipFreeAsync(f.ptr, s->slots[f.owner].stream);
     if (f.ready != nullptr)
         (void)hipEventDestroy(f.ready);
-    s->used -= (int64_t)f.bytes;
+    s->used -= (int64_t)(f.bytes + f.part_bytes);
     s->factors.erase(victim);
     s->st.evictions += 1;
     return true;
@@ -220,15 +258,16 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool 
     const size_t fbytes = have ? 0 : (size_t)q.ka * q.ka * 8;
     // workspace growth: exact for the handle, bounded for the batch tables
     // (the batched launch grows its scratch to twice the tables' size)
-    size_t ws_extra = 0, tables = w.tables;
+    size_t ws_extra = 0, tables = w.tables, part_extra = 0;
     if (batched) {
         tables += batch_entry_bound(q) + (w.reqs.empty() ? 1024 : 0);
         const size_t grow = 2 * tables > slot.sc.dev_bytes ? 2 * tables - slot.sc.dev_bytes : 0;
         ws_extra = grow > w.ws_extra ? grow - w.ws_extra : 0;
     } else {
         ws_extra = alone_growth(slot.h, q);
+        part_extra = part_growth(slot.h, q);
     }
-    const int64_t need = (int64_t)(fbytes + q.rhs_bytes + ws_extra);
+    const int64_t need = (int64_t)(fbytes + q.rhs_bytes + ws_extra + part_extra);
     while (s->used + need > s->cfg.hbm_budget)
         if (!evict_one(s, slot.stream))
             return false;
@@ -260,10 +299,19 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool 
         s->st.factor_hits += 1;
     }
     f = &it->second;
+    if (!batched && f->fo[q.r.diag] == nullptr) {
+        // no device work: the object reads the factor in place
+        if (rtri_factor_create(slot.h, f->uplo, q.r.diag, f->ka, RTRI_F64, f->ptr, f->lda, 0, &f->fo[q.r.diag]) !=
+            RTRI_OK) {
+            f->fo[q.r.diag] = nullptr;
+            return false;
+        }
+    }
     f->refs += 1;
     f->last_use = ++s->use_clock;
-    s->used += (int64_t)(q.rhs_bytes + ws_extra);
+    s->used += (int64_t)(q.rhs_bytes + ws_extra + part_extra);
     w.ws_extra += ws_extra;
+    w.part_extra += part_extra;
     w.tables = tables;
     s->st.hbm_in_use = s->used;
     s->st.hbm_peak = std::max(s->st.hbm_peak, s->used);
@@ -355,18 +403,14 @@ void execute(rtri_server *s, rtri_server::Slot &slot, Work &w, std::vector<rtri_
                 x = rc;
         } else {
             const rtri_request &r = w.reqs[0].r;
+            rtri_factor *fo = fac[0]->fo[r.diag];
             int rc;
-            if (r.precision == RTRI_PREC_F64)
-                rc = r.op == 0 ? rtri_dtrsm(h, r.side, r.uplo, r.trans, r.diag, r.m, r.n, r.alpha, fac[0]->ptr,
-                                            fac[0]->lda, rhs[0], r.m)
-                               : rtri_dtrmm(h, r.side, r.uplo, r.trans, r.diag, r.m, r.n, r.alpha, fac[0]->ptr,
-                                            fac[0]->lda, rhs[0], r.m);
-            else if (r.op != 0)
-                rc = RTRI_ERR_UNSUPPORTED;
+            if (r.op == 1)
+                rc = r.precision == RTRI_PREC_F64 ? rtri_factor_trmm(h, fo, r.side, r.trans, r.m, r.n, r.alpha, rhs[0], r.m)
+                                                  : RTRI_ERR_UNSUPPORTED;
             else
-                rc = rtri_dtrsm_mixed(h, r.side, r.uplo, r.trans, r.diag, r.m, r.n, r.alpha, fac[0]->ptr, fac[0]->lda,
-                                      rhs[0], r.m, r.precision == RTRI_PREC_MIXED_BF16 ? RTRI_BF16 : RTRI_F32, 1e-12,
-                                      30, &info[0]);
+                rc = rtri_factor_trsm(h, fo, r.side, r.trans, r.m, r.n, r.alpha, rhs[0], r.m, r.precision, 1e-12, 30,
+                                      &info[0]);
             status[0] = rc;
         }
         for (size_t i = 0; i < w.reqs.size() && e == hipSuccess; ++i)
@@ -437,6 +481,13 @@ void worker(rtri_server *s, int idx)
             const size_t held = handle_ws_bytes(slot.h) + slot.sc.dev_bytes;
             s->used += (int64_t)held - (int64_t)(slot.ws_held + w.ws_extra);
             slot.ws_held = held;
+            // parts the factor objects made replace the reservation for them
+            if (!w.batched) {
+                Factor &f = s->factors.at(w.reqs[0].r.factor_id);
+                const size_t now = factor_object_bytes(f);
+                s->used += (int64_t)now - (int64_t)f.part_bytes - (int64_t)w.part_extra;
+                f.part_bytes = now;
+            }
             s->st.completed += (int64_t)w.reqs.size();
             s->st.launches += 1;
             if (w.batched) {
@@ -493,6 +544,8 @@ int rtri_server_create(const rtri_server_cfg *cfg, rtri_server **out)
             e = hipMemPoolSetAttribute(sl.pool, hipMemPoolReuseAllowOpportunistic, &off);
         if (e == hipSuccess)
             e = hipMemPoolSetAttribute(sl.pool, hipMemPoolReuseAllowInternalDependencies, &off);
+        if (e == hipSuccess)
+            sl.h->mem_pool = sl.pool;   // factor objects' parts made by this slot come from its pool
     }
     if (e != hipSuccess) {
         for (auto &sl : s->slots) {
@@ -625,6 +678,9 @@ int rtri_server_destroy(rtri_server *s)
         if (sl.th.joinable())
             sl.th.join();
     for (auto &kv : s->factors) {
+        for (rtri_factor *o : kv.second.fo)
+            if (o != nullptr)
+                (void)rtri_factor_destroy(o);
         if (!kv.second.registered && kv.second.ptr != nullptr)
             (void)hipFreeAsync(kv.second.ptr, s->slots[kv.second.owner].stream);
         if (kv.second.ready != nullptr)

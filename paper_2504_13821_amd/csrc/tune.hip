@@ -439,12 +439,17 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
     (void)hipFree(A);
     (void)hipFree(B);
     (void)hipFree(C);
-    delete old;
-    if (rc != RTRI_OK)
+    if (rc != RTRI_OK) {
+        h->tune = old;   // a failed sweep leaves the rules the handle had
         return rc;
-    h->tune = new (std::nothrow) TuneDB(db);
-    if (h->tune == nullptr)
+    }
+    TuneDB *fresh = new (std::nothrow) TuneDB(db);
+    if (fresh == nullptr) {
+        h->tune = old;
         return RTRI_ERR_NOMEM;
+    }
+    delete old;
+    h->tune = fresh;
     if (db_path != nullptr && !write_db(db_path, db))
         return RTRI_ERR_INVALID;
     return RTRI_OK;

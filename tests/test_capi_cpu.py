@@ -150,3 +150,135 @@ def test_shipped_tuning_rules_load(rt, handle):
     for dt in (rt.F64, rt.F32):
         for op in (0, 1):
             assert _leaf(rt, handle, dt, op, 16384, 16384) in (16, 32, 64, 128, 256)
+
+
+# ---- the Python wrappers reject undersized operands before any C call --------
+
+class _NoCall:
+    """Stands in for every C entry point: a wrapper that reaches it fails the test."""
+
+    def __init__(self, name):
+        self.__name__ = name
+
+    def __call__(self, *a):
+        raise AssertionError(f"{self.__name__} was called")
+
+
+@pytest.fixture()
+def guarded(rt, monkeypatch):
+    for name in ("rtri_dtrsm", "rtri_dtrmm", "rtri_strsm", "rtri_strmm", "rtri_trmm_ex", "rtri_dtrsm_mixed",
+                 "rtri_gemm_update"):
+        monkeypatch.setattr(rt, name, _NoCall(name))
+    return rt
+
+
+def _cm(torch, rows, cols, dtype=None):
+    """A column-major (stride(0) == 1) CPU tensor of shape (rows, cols)."""
+    return torch.zeros((cols, rows), dtype=dtype or torch.float64).t()
+
+
+def test_wrappers_reject_bad_shapes(guarded):
+    rt = guarded
+    torch = pytest.importorskip("torch")
+    h = None   # never reached
+    A_small = _cm(torch, 8, 4)          # lda >= 8 but only 4 columns: an order-8 factor would be read past its end
+    B = _cm(torch, 8, 5)
+    for fn in (rt.trsm, rt.trmm):
+        with pytest.raises(ValueError, match="A has shape"):
+            fn(h, "L", "L", "N", "N", 1.0, A_small, B)
+        with pytest.raises(ValueError, match="A has shape"):
+            fn(h, "R", "L", "N", "N", 1.0, _cm(torch, 5, 4), B)
+    with pytest.raises(ValueError, match="A has shape"):
+        rt.trsm_mixed(h, "L", "L", "N", "N", 1.0, A_small, B)
+    A16 = _cm(torch, 8, 8, torch.bfloat16)
+    with pytest.raises(ValueError, match="B has shape"):
+        rt.trmm_ex(h, "L", "L", "N", "N", 1.0, A16, _cm(torch, 8, 4, torch.bfloat16), _cm(torch, 8, 5, torch.float32))
+    with pytest.raises(ValueError, match="A has shape"):
+        rt.trmm_ex(h, "L", "L", "N", "N", 1.0, _cm(torch, 8, 7, torch.bfloat16), _cm(torch, 8, 5, torch.bfloat16),
+                   _cm(torch, 8, 5, torch.float32))
+    # GEMM update: C (M x N) = op(P) (M x K) op(Q) (K x N)
+    C = _cm(torch, 6, 5)
+    with pytest.raises(ValueError, match="Q has shape"):
+        rt.gemm_update(h, "N", "N", 1.0, _cm(torch, 6, 4), _cm(torch, 3, 5), 0.0, C)
+    with pytest.raises(ValueError, match="P has shape"):
+        rt.gemm_update(h, "T", "N", 1.0, _cm(torch, 4, 5), _cm(torch, 4, 5), 0.0, C)
+    # well-shaped host tensors pass the shape checks and stop at the device check
+    with pytest.raises(ValueError, match="device tensor"):
+        rt.trsm(h, "L", "L", "N", "N", 1.0, _cm(torch, 8, 8), B)
+
+
+# ---- factor objects: argument codes (no device work is reached) -----------------
+
+def test_factor_argument_codes(rt, handle):
+    f = ctypes.c_void_p()
+    create = rt.rtri_factor_create
+    assert create(handle, 2, 0, 8, rt.F64, FAKE, 8, 0, ctypes.byref(f)) == -2
+    assert create(handle, 0, 5, 8, rt.F64, FAKE, 8, 0, ctypes.byref(f)) == -3
+    assert create(handle, 0, 0, -1, rt.F64, FAKE, 8, 0, ctypes.byref(f)) == -4
+    assert create(handle, 0, 0, 8, rt.BF16, FAKE, 8, 0, ctypes.byref(f)) == -5
+    assert create(handle, 0, 0, 8, rt.F64, None, 8, 0, ctypes.byref(f)) == -6
+    assert create(handle, 0, 0, 8, rt.F64, FAKE, 7, 0, ctypes.byref(f)) == -7
+    assert create(handle, 0, 0, 8, rt.F64, FAKE, 8, 4, ctypes.byref(f)) == -8
+    assert create(handle, 0, 0, 8, rt.F64, FAKE, 8, 0, None) == -9
+    assert create(None, 0, 0, 8, rt.F64, FAKE, 8, 0, ctypes.byref(f)) == rt.ERR_HANDLE
+    # without the copy flag, creation does no device work
+    assert create(handle, 0, 0, 8, rt.F64, FAKE, 8, 0, ctypes.byref(f)) == rt.OK
+    trsm, trmm = rt.rtri_factor_trsm, rt.rtri_factor_trmm
+    ok = (0, 0, 8, 3, 1.0, FAKE, 8)
+    cases = [((2, 0, 8, 3, 1.0, FAKE, 8), -3), ((0, 3, 8, 3, 1.0, FAKE, 8), -4), ((0, 0, 7, 3, 1.0, FAKE, 8), -5),
+             ((0, 0, -1, 3, 1.0, FAKE, 8), -5), ((1, 0, 3, 7, 1.0, FAKE, 3), -6), ((0, 0, 8, -1, 1.0, FAKE, 8), -6),
+             ((0, 0, 8, 3, 1.0, None, 8), -8), ((0, 0, 8, 3, 1.0, FAKE, 7), -9)]
+    for args, code in cases:
+        assert trsm(handle, f, *args, 0, 1e-12, 10, None) == code, (args, code)
+        assert trmm(handle, f, *args) == code, (args, code)
+    assert trsm(handle, f, *ok, 7, 1e-12, 10, None) == -10
+    assert trsm(handle, f, *ok, 2, -1.0, 10, None) == -11
+    assert trsm(handle, f, *ok, 2, 1e-12, 0, None) == -12
+    assert trsm(handle, None, *ok, 0, 1e-12, 10, None) == -2
+    # quick returns: no vectors
+    assert trsm(handle, f, 0, 0, 8, 0, 1.0, None, 8, 2, 1e-12, 10, None) == rt.OK
+    assert trmm(handle, f, 1, 0, 0, 8, 1.0, None, 1) == rt.OK
+    nb = ctypes.c_int64(-1)
+    assert rt.rtri_factor_bytes(f, ctypes.byref(nb)) == rt.OK and nb.value == 0
+    assert rt.rtri_factor_destroy(f) == rt.OK
+    f32 = ctypes.c_void_p()
+    assert create(handle, 1, 1, 8, rt.F32, FAKE, 8, 0, ctypes.byref(f32)) == rt.OK
+    # a refined solve needs an FP64 factor
+    assert trsm(handle, f32, *ok, 1, 1e-12, 10, None) == rt.ERR_UNSUPPORTED
+    assert rt.rtri_factor_destroy(f32) == rt.OK
+
+
+def test_solver_argument_codes(rt, handle):
+    """TRTRI / POTRS / GETRS reject bad arguments (and bad pivots) before any
+    device work; empty problems return at once."""
+    for fn in (rt.rtri_dtrtri, rt.rtri_strtri):
+        assert fn(handle, 2, 0, 4, FAKE, 4) == -2
+        assert fn(handle, 0, 2, 4, FAKE, 4) == -3
+        assert fn(handle, 0, 0, -1, FAKE, 4) == -4
+        assert fn(handle, 0, 0, 4, None, 4) == -5
+        assert fn(handle, 0, 0, 4, FAKE, 3) == -6
+        assert fn(handle, 1, 1, 0, None, 1) == rt.OK
+    for fn in (rt.rtri_dpotrs, rt.rtri_spotrs):
+        assert fn(handle, 3, 4, 2, FAKE, 4, FAKE, 4) == -2
+        assert fn(handle, 0, -1, 2, FAKE, 4, FAKE, 4) == -3
+        assert fn(handle, 0, 4, -2, FAKE, 4, FAKE, 4) == -4
+        assert fn(handle, 0, 4, 2, None, 4, FAKE, 4) == -5
+        assert fn(handle, 0, 4, 2, FAKE, 3, FAKE, 4) == -6
+        assert fn(handle, 0, 4, 2, FAKE, 4, None, 4) == -7
+        assert fn(handle, 0, 4, 2, FAKE, 4, FAKE, 3) == -8
+        assert fn(handle, 0, 4, 0, FAKE, 4, None, 4) == rt.OK
+    piv = (ctypes.c_int32 * 4)(1, 2, 3, 4)
+    badpiv = (ctypes.c_int32 * 4)(1, 5, 3, 4)
+    zeropiv = (ctypes.c_int32 * 4)(0, 2, 3, 4)
+    for fn in (rt.rtri_dgetrs, rt.rtri_sgetrs):
+        assert fn(handle, 4, 4, 2, FAKE, 4, piv, FAKE, 4) == -2
+        assert fn(handle, 0, -1, 2, FAKE, 4, piv, FAKE, 4) == -3
+        assert fn(handle, 0, 4, -1, FAKE, 4, piv, FAKE, 4) == -4
+        assert fn(handle, 0, 4, 2, None, 4, piv, FAKE, 4) == -5
+        assert fn(handle, 0, 4, 2, FAKE, 3, piv, FAKE, 4) == -6
+        assert fn(handle, 0, 4, 2, FAKE, 4, None, FAKE, 4) == -7
+        assert fn(handle, 0, 4, 2, FAKE, 4, badpiv, FAKE, 4) == -7
+        assert fn(handle, 1, 4, 2, FAKE, 4, zeropiv, FAKE, 4) == -7
+        assert fn(handle, 0, 4, 2, FAKE, 4, piv, None, 4) == -8
+        assert fn(handle, 0, 4, 2, FAKE, 4, piv, FAKE, 3) == -9
+        assert fn(handle, 0, 4, 0, FAKE, 4, piv, None, 4) == rt.OK

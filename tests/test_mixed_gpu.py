@@ -202,3 +202,73 @@ def test_mixed_8192_sampled(rt, h, orc):
     Xs = np.asfortranarray(Bd[:, torch.as_tensor(idx, device="cuda")].cpu().numpy())
     e = orc.trsm_eta("L", "L", "N", "N", 1.0, A, np.asfortranarray(B[:, idx]), Xs)
     assert info["converged"] and e <= 1e-12, (info, e)
+
+
+# ---- the mixed-precision workload: m = n = 8192, three condition classes ---------
+
+C3_OFFSETS = (450.0, 45.0, 17.0)   # diagonal c + U(0,1): cond_1 ~ 1e2, 1e4, 1e6 (tests/golden/c3_cond.json)
+
+
+@pytest.mark.parametrize("gemm", ["bf16", "f32"])
+@pytest.mark.parametrize("c", C3_OFFSETS)
+def test_mixed_8192_classes(rt, h, orc, gemm, c):
+    """The benchmark's refined solves, on its device-drawn inputs (Philox fill,
+    the host twin of which is pinned bit for bit elsewhere): every condition
+    class with BF16 and with FP32 GEMM updates, checked on sampled columns
+    against the oracle's compensated backward error (<= 1e-12) and against the
+    oracle's own solution (forward error within cond_1 * 1e-12)."""
+    import json
+    import os
+    m = n = 8192
+    say("mixed 8192", gemm, c)
+    Ad = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
+    Bd = torch.empty((m, m), dtype=torch.float64, device="cuda").t()
+    rt.synth_fill(h, 1, synth.SEED, synth.W_MIXED, 1, Ad, param=c)
+    rt.synth_fill(h, 0, synth.SEED, synth.W_MIXED, 2, Bd)
+    idx = np.sort(synth.rng(synth.W_MIXED, 2, int(c)).choice(n, 8, replace=False))
+    tidx = torch.as_tensor(idx, device="cuda")
+    Bs = np.asfortranarray(Bd[:, tidx].cpu().numpy())
+    info = rt.trsm_mixed(h, "L", "L", "N", "N", 1.0, Ad, Bd, gemm=gemm, tol=1e-12, max_iter=30)
+    torch.cuda.synchronize()
+    Xs = np.asfortranarray(Bd[:, tidx].cpu().numpy())
+    A = rt.to_host(Ad)
+    del Ad, Bd
+    e = orc.trsm_eta("L", "L", "N", "N", 1.0, A, Bs, Xs)
+    Xo = orc.trsm("L", "L", "N", "N", 1.0, A, Bs)
+    fwd = float(np.max(np.abs(Xs - Xo)) / np.max(np.abs(Xo)))
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_cond.json")) as f:
+        kappa = {case["c"]: case["cond1"] for case in json.load(f)["cases"]}[c]
+    say("  iters", info["iters"], "lib eta", info["eta"], "oracle eta", e, "fwd", fwd, "cond1", kappa)
+    assert info["converged"] and e <= 1e-12, (info, e)
+    assert e <= 4 * max(info["eta"], 1e-16)
+    assert fwd <= kappa * 1e-12, (fwd, kappa)
+
+
+# ---- the 16-bit TRMM on its full-tile path ---------------------------------------
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("side,uplo,trans", [("L", "L", "N"), ("L", "U", "T"), ("R", "U", "N"), ("R", "L", "T")])
+def test_trmm_ex_full_tiles(rt, h, orc, dt, side, uplo, trans):
+    """Orders and leading dimensions that are multiples of 8 with updates of at
+    least 128 x 128 (the 16-bit GEMM's 16-byte full-tile loads with both
+    operands 16-bit, the path of the benchmark's TRMM at 8192): both leaf
+    schedules bit-identical, against the oracle on the rounded inputs, and bit
+    for bit on small integers (every partial sum an integer below 2^24)."""
+    m, n = (1024, 512) if side == "L" else (512, 1024)
+    ka = m if side == "L" else n
+    say("trmm_ex full tiles", dt, side, uplo, trans)
+    g = G(6, ka)
+    A = rounded(synth.tri(ka, uplo, g, "stress"), dt)
+    B = rounded(synth.dense(m, n, g), dt)
+    out = []
+    for mode in (1, 2):
+        h.set_option(rt.OPT_TRMM_LEAVES, mode)
+        out.append(_run_trmm_ex(rt, h, side, uplo, trans, "N", 0.5, A, B, dt))
+    h.set_option(rt.OPT_TRMM_LEAVES, 0)
+    assert np.array_equal(out[0], out[1])
+    e = orc.trmm_eta(side, uplo, trans, "N", 0.5, A, B, out[0])
+    assert e <= 7 * np.sqrt(ka) * 2.0 ** -24, e
+    Ai = synth.exact_tri(ka, uplo, g, offdiag=(-1, 0, 1), diag=(1.0, -1.0, 2.0, -2.0))
+    Bi = synth.exact_dense(m, n, g)
+    Ci = _run_trmm_ex(rt, h, side, uplo, trans, "N", 1.0, Ai, Bi, dt)
+    assert np.array_equal(Ci, orc.trmm(side, uplo, trans, "N", 1.0, Ai, Bi))
