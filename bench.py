@@ -27,7 +27,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}   # MI355X dense MFMA, TFLOP/s
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0, "i8": 5000.0}   # MI355X dense MFMA, TFLOP/s (TOP/s for i8)
 HBM_PEAK = 8000.0                                                    # GB/s
 
 # HBM-side bytes per FP64 GEMM-update launch of this step, from two rocprofv3
@@ -376,22 +376,56 @@ def bench_mixed(rt, torch, h, m=8192, ns=8):
         case = {"m": mm, "c": c, "cond1": kappa, "fp64_ms": round(t_plain, 3),
                 "fp64_tflops": round(mm ** 3 / (t_plain * 1e-3) / 1e12, 3)}
         smp["fp64"] = np.asfortranarray(Bd[:, tidx].cpu().numpy())
-        for gemm in (("bf16", "f32") if mm == m else ("f32",)):
+        variants = [("bf16", 0), ("f32", 0), ("bf16", 1), ("f32", 1)] if mm == m else [("f32", 0), ("f32", 1)]
+        for gemm, resid in variants:
             info = {}
+            key = gemm if resid == 0 else f"{gemm}_int8res"
 
             def run():
                 info.update(rt.trsm_mixed(h, "L", "L", "N", "N", 1.0, Ad, Bd, gemm=gemm, tol=1e-12, max_iter=30,
                                           allow_not_converged=True))
+            h.set_option(rt.OPT_RESIDUAL, resid)
             t = _event_ms(torch, run, lambda: Bd.copy_(B0))
-            case[gemm] = {"ms": round(t, 3), "speedup_vs_fp64": round(t_plain / t, 3), "iters": info["iters"],
-                          "eta_library": info["eta"], "converged": info["converged"],
-                          "useful_tflops": round(mm ** 3 / (t * 1e-3) / 1e12, 3)}
-            smp[gemm] = np.asfortranarray(Bd[:, tidx].cpu().numpy())
+            h.set_option(rt.OPT_RESIDUAL, 0)
+            case[key] = {"ms": round(t, 3), "speedup_vs_fp64": round(t_plain / t, 3), "iters": info["iters"],
+                         "eta_library": info["eta"], "converged": info["converged"],
+                         "residual_product": "INT8 (Ozaki scheme)" if resid else "FP64 MFMA",
+                         "useful_tflops": round(mm ** 3 / (t * 1e-3) / 1e12, 3)}
+            smp[key] = np.asfortranarray(Bd[:, tidx].cpu().numpy())
+        if mm == m:
+            case["residual_product"] = bench_residual_product(rt, torch, h, Ad, B0)
         res["cases"].append(case)
         samples.append(smp)
         del Ad, B0, Bd
         torch.cuda.empty_cache()
     return res, samples
+
+
+def bench_residual_product(rt, torch, h, Ad, B0):
+    """The refined solve's residual product op(A) X on its own (FP64 accuracy
+    both ways): the FP64 recursive TRMM against the INT8-product TRMM (modular
+    Ozaki scheme), with the latter's per-class kernel profile; the INT8 GEMM
+    class is reported against the dense INT8 MFMA peak (ops = 2 m n K per
+    modulus, K over the triangle's half: m^2 n per modulus)."""
+    mm = Ad.shape[0]
+    W = B0.clone()
+    out = {"m": mm, "n": B0.shape[1]}
+    for name, fn in (("fp64_trmm", rt.trmm), ("int8_trmm", rt.trmm_ozaki)):
+        t = _event_ms(torch, lambda: fn(h, "L", "L", "N", "N", 1.0, Ad, W), lambda: W.copy_(B0))
+        out[name + "_ms"] = round(t, 3)
+    W.copy_(B0)
+    h.profile_begin()
+    rt.trmm_ozaki(h, "L", "L", "N", "N", 1.0, Ad, W)
+    prof = h.profile_end()
+    out["int8_kernels"] = {f"{x['kclass']}_{x['dtype']}": {"launches": x["launches"], "ms": round(x["ms"], 4)}
+                           for x in prof}
+    g = [x for x in prof if x["kclass"] == "gemm" and x["dtype"] == "i8"]
+    if g:
+        tops = g[0]["flops"] / (g[0]["ms"] * 1e-3) / 1e12
+        out["int8_gemm"] = {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK["i8"], "unit": "TOP/s",
+                            "frac": round(tops / PEAK["i8"], 4), "moduli": int(round(g[0]["flops"] / (mm ** 2 * W.shape[1])))}
+    del W
+    return out
 
 
 def cpu_check_mixed(res, samples):
@@ -401,7 +435,7 @@ def cpu_check_mixed(res, samples):
     import oracle
     for case, smp in zip(res["cases"], samples):
         Xo = oracle.trsm("L", "L", "N", "N", 1.0, smp["A"], smp["B"])
-        for key in ("fp64", "bf16", "f32"):
+        for key in ("fp64", "bf16", "f32", "bf16_int8res", "f32_int8res"):
             if key not in smp:
                 continue
             X = smp[key]

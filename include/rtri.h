@@ -56,7 +56,8 @@ enum { RTRI_LEFT = 0, RTRI_RIGHT = 1 };
 enum { RTRI_LOWER = 0, RTRI_UPPER = 1 };
 enum { RTRI_NOTRANS = 0, RTRI_TRANS = 1, RTRI_CONJTRANS = 2 };
 enum { RTRI_NONUNIT = 0, RTRI_UNIT = 1 };
-enum { RTRI_F64 = 0, RTRI_F32 = 1, RTRI_BF16 = 2, RTRI_F16 = 3 };
+enum { RTRI_F64 = 0, RTRI_F32 = 1, RTRI_BF16 = 2, RTRI_F16 = 3,
+       RTRI_I8 = 4 /* profile records only: the INT8 matrix-core product of rtri_dtrmm_ozaki */ };
 
 enum {
     RTRI_OK = 0,
@@ -76,10 +77,18 @@ enum {
     RTRI_OPT_LEAF_F32 = 2,   /* leaf size for FP32 (same values) */
     RTRI_OPT_GEMM_TILE = 3,  /* GEMM tile choice: 0 = automatic, 1 = 128x128 (4 wavefronts), 2 = 64x64,
                                 3 = 128x128 (8 wavefronts) */
-    RTRI_OPT_TRMM_LEAVES = 4 /* TRMM leaf schedule (leaves of 64 rows and more): 0 = automatic (all in one
+    RTRI_OPT_TRMM_LEAVES = 4, /* TRMM leaf schedule (leaves of 64 rows and more): 0 = automatic (all in one
                                 launch below 8192 vectors), 1 = one launch per leaf, in recursion order,
                                 2 = the panel is copied to workspace, all leaves run in one launch, then the
                                 GEMM updates read the copy.  Both give bit-identical results. */
+    RTRI_OPT_GEMM16_TILE = 5, /* 16-bit GEMM tiles: 0 = automatic, 1 = 128x128 (4 wavefronts, 16x16x32 MFMA),
+                                2 = 256x256 (8 wavefronts, 32x32x16 MFMA) wherever both operands are
+                                k-contiguous and 16-byte aligned (else 128x128).  Results may differ in the
+                                last bits between the two (another accumulation order). */
+    RTRI_OPT_RESIDUAL = 6     /* residual product of the refined solves (rtri_dtrsm_mixed, factor solves):
+                                0 = FP64 matrix cores (the FP64 recursive TRMM), 1 = exact INT8 products
+                                (the method of rtri_dtrmm_ozaki; op(A)'s residue planes made once per call,
+                                or kept by a factor) */
 };
 
 typedef struct rtri_handle rtri_handle;
@@ -144,6 +153,28 @@ int rtri_ztrsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t 
 int rtri_ztrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, const double *alpha,
                const void *A, int64_t lda, void *B, int64_t ldb);
 
+/* FP64 TRMM from exact INT8 matrix-core products (the refined solve's residual
+ * product, available on its own): B := alpha op(A) B (LEFT) or alpha B op(A)
+ * (RIGHT), eqs. (1)/(2), in place, FP64-accurate.  Method: the modular form
+ * of the Ozaki scheme.  Each line of op(A) and of B (rows of the left
+ * operand, columns of the right one) is scaled by a power of two and rounded
+ * to an integer of at most beta bits, beta = min(55, floor((125.19 - 2 -
+ * log2 K) / 2)) for the order K (55 up to K = 8192, 54 up to 16384); the
+ * exact integer product is formed from its residues modulo 16 pairwise
+ * coprime moduli <= 256, each residue one INT8 GEMM with exact INT32
+ * accumulation over op(A)'s triangle, and recovered by the Chinese remainder
+ * theorem (Garner's algorithm, 128-bit integer evaluation, one rounding).
+ * Error per entry: at most |alpha| (2^(e_i-beta-1) ||right_j||_1 +
+ * 2^(f_j-beta-1) ||left_i||_1 + K 2^(e_i+f_j-2 beta-2)) plus two roundings,
+ * where 2^e_i, 2^f_j bound the largest magnitude of row i of the left and
+ * column j of the right operand; exact when the scaled entries are integers
+ * and the result is representable.  Workspace (handle-owned, grown on
+ * demand): 16 (ka' k' + n' k' + m' n') bytes (' = rounded up to 256 lines /
+ * 128 entries).  Codes as rtri_dtrmm, and RTRI_ERR_UNSUPPORTED for an order
+ * of 131072 or more. */
+int rtri_dtrmm_ozaki(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                     double alpha, const double *A, int64_t lda, double *B, int64_t ldb);
+
 /* Per-kernel profile: while a profile is open, every kernel the handle
  * launches is bracketed by two HIP events recorded on the handle's stream, and
  * its algorithmic work is attributed to a kernel class.  rtri_profile_end waits
@@ -174,7 +205,9 @@ int rtri_profile_end(rtri_handle *h, rtri_kernel_stat *out, int max_out, int *n_
  *     C := beta * C + s * op(P) * op(Q),   op(P) M-by-K, op(Q) K-by-N, C M-by-N
  * op(P) = P (trans_p = RTRI_NOTRANS) or P^T (RTRI_TRANS); likewise op(Q).
  * dtype is RTRI_F64 or RTRI_F32 (all of P, Q, C; alpha-like scalars passed as
- * double and rounded to the element type).  beta == 0 writes C without reading
+ * double and rounded to the element type), or RTRI_BF16 / RTRI_F16 (P and Q
+ * 16-bit, C FP32, FP32 accumulation: the matrix-core tiles of the 16-bit and
+ * mixed-precision paths, RTRI_OPT_GEMM16_TILE).  beta == 0 writes C without reading
  * it.  Device pointers; C must not overlap P or Q.  Asynchronous on the
  * handle's stream.
  * Argument codes: -2 dtype, -3 trans_p, -4 trans_q, -5 M < 0, -6 N < 0,
@@ -217,7 +250,10 @@ typedef struct {
  * FP32 accumulation and FP32 leaves, and the residual
  *     R = alpha B - op(A) X   (or alpha B - X op(A))
  * and the update X += s D are formed in FP64 (s is a power of two scaling R
- * into range).  Stops when the normwise backward error
+ * into range).  The product op(A) X of the residual runs on the FP64 matrix
+ * cores (the FP64 recursive TRMM) or, with RTRI_OPT_RESIDUAL = 1, from exact
+ * INT8 products (the method of rtri_dtrmm_ozaki, FP64-accurate; its residue
+ * planes of op(A) are made once per call).  Stops when the normwise backward error
  *     eta = max_v |R_v|inf / (anorm |X_v|inf + |alpha B_v|inf)
  * (v over columns for LEFT, rows for RIGHT) is <= tol, when eta fails to halve
  * from one correction to the next, or after max_iter (<= 32) corrections; B
@@ -277,7 +313,9 @@ int rtri_sgetrs(rtri_handle *h, int trans, int64_t n, int64_t nrhs, const float 
  *     leaf size and precision), so later calls skip the pack pass;
  *   - for refined solves: the copy of A in the GEMM type (BF16 or FP32,
  *     transposed where the 16-bit GEMM wants it) and |op(A)| (per side and
- *     trans), so later calls skip the conversion and the norm.
+ *     trans), so later calls skip the conversion and the norm; with
+ *     RTRI_OPT_RESIDUAL = 1 also op(A)'s INT8 residue planes (per side and
+ *     trans).
  * Results are bit for bit those of rtri_dtrsm / rtri_strsm / rtri_dtrmm /
  * rtri_strmm / rtri_dtrsm_mixed with the same handle options.
  * Parts are made on the calling handle's stream; a call on another stream

@@ -36,7 +36,7 @@ NOTRANS, TRANS, CONJTRANS = 0, 1, 2
 NONUNIT, UNIT = 0, 1
 F64, F32, BF16, F16 = 0, 1, 2, 3
 OK, ERR_HANDLE, ERR_HIP, ERR_NOMEM, ERR_UNSUPPORTED, NOT_CONVERGED, ERR_INVALID = range(7)
-OPT_LEAF_F64, OPT_LEAF_F32, OPT_GEMM_TILE, OPT_TRMM_LEAVES = 1, 2, 3, 4
+OPT_LEAF_F64, OPT_LEAF_F32, OPT_GEMM_TILE, OPT_TRMM_LEAVES, OPT_GEMM16_TILE, OPT_RESIDUAL = 1, 2, 3, 4, 5, 6
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -63,6 +63,7 @@ rtri_dtrsm = _sig("rtri_dtrsm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp,
 rtri_strsm = _sig("rtri_strsm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
 rtri_dtrmm = _sig("rtri_dtrmm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
 rtri_strmm = _sig("rtri_strmm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
+rtri_dtrmm_ozaki = _sig("rtri_dtrmm_ozaki", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
 rtri_trmm_ex = _sig("rtri_trmm_ex", _int, *_OPARGS, ctypes.c_float, _vp, _int, _i64, _vp, _int, _i64, _vp, _int, _i64)
 
 
@@ -154,7 +155,7 @@ class KernelStat(ctypes.Structure):
 
 
 KCLASS_NAMES = {0: "gemm", 1: "leaf_solve", 2: "leaf_mult", 3: "other", 4: "batched"}
-DTYPE_NAMES = {0: "f64", 1: "f32", 2: "bf16", 3: "f16"}
+DTYPE_NAMES = {0: "f64", 1: "f32", 2: "bf16", 3: "f16", 4: "i8"}
 rtri_profile_begin = _sig("rtri_profile_begin", _int, _vp)
 rtri_profile_end = _sig("rtri_profile_end", _int, _vp, ctypes.POINTER(KernelStat), _int, ctypes.POINTER(_int))
 
@@ -310,6 +311,24 @@ def trmm(h: Handle, side, uplo, trans, diag, alpha, A, B):
     return _call(h, False, side, uplo, trans, diag, alpha, A, B)
 
 
+def trmm_ozaki(h: Handle, side, uplo, trans, diag, alpha, A, B):
+    """As trmm for FP64, through rtri_dtrmm_ozaki: the product from exact INT8 matrix-core products
+    (modular Ozaki scheme), FP64-accurate."""
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
+    m, n = B.shape
+    ka = _factor_order(side, B)
+    _need_shape(A, "A", ka, ka)
+    _same_device(A=A, B=B)
+    lda = _colmajor(A, "A")
+    ldb = _colmajor(B, "B")
+    if A.dtype != torch.float64 or B.dtype != torch.float64:
+        raise TypeError("trmm_ozaki takes float64 A and B")
+    rc = rtri_dtrmm_ozaki(h.ptr, *codes(side, uplo, trans, diag), m, n, alpha, A.data_ptr(), lda, B.data_ptr(), ldb)
+    check(rc, "rtri_dtrmm_ozaki")
+    return B
+
+
 def gemm_update(h: Handle, trans_p: str, trans_q: str, s, P, Q, beta, C):
     """In place: C := beta C + s op(P) op(Q) (the recursion's GEMM update on its own)."""
     tp, tq = _TRANS[trans_p.upper()], _TRANS[trans_q.upper()]
@@ -321,7 +340,15 @@ def gemm_update(h: Handle, trans_p: str, trans_q: str, s, P, Q, beta, C):
     _need_shape(Q, "Q", N if tq else K, K if tq else N)
     _same_device(P=P, Q=Q, C=C)
     ldp, ldq, ldc = _colmajor(P, "P"), _colmajor(Q, "Q"), _colmajor(C, "C")
-    dt = {torch.float64: F64, torch.float32: F32}[C.dtype]
+    if P.dtype in (torch.bfloat16, torch.float16):
+        # 16-bit P and Q, FP32 C (FP32 accumulation)
+        if Q.dtype != P.dtype or C.dtype != torch.float32:
+            raise TypeError("16-bit P needs Q of the same type and a float32 C")
+        dt = BF16 if P.dtype == torch.bfloat16 else F16
+    else:
+        if not (P.dtype == Q.dtype == C.dtype):
+            raise TypeError("P, Q and C must have the same dtype")
+        dt = {torch.float64: F64, torch.float32: F32}[C.dtype]
     check(rtri_gemm_update(h.ptr, dt, tp, tq, M, N, K, s, P.data_ptr(), ldp, Q.data_ptr(), ldq, beta,
                            C.data_ptr(), ldc), "rtri_gemm_update")
     return C

@@ -94,9 +94,24 @@ constexpr int64_t SPLIT_MIN_K = 1024;   // shorter updates never split
 // whose partials fit in cap bytes (slices = 0: none); part is left unset
 Split plan_split(DType t, const GemmDesc &g, int tile, size_t cap);
 hipError_t launch_gemm(DType t, const GemmDesc &g, int tile, hipStream_t st, const Split &sp = Split{});
+// Several updates in one launch: workgroup b owns the 64x64 output tile
+// tiles[b] and applies its entries (update desc, tile origin m0, n0 inside that
+// update) in order, each exactly as a 64x64-tile launch of that update would.
+// All updates share op flags (tp, tq); vec: every operand 16-byte aligned with
+// leading dimensions a multiple of 16 bytes.  descs / ents / tiles in device memory.
+struct GroupEntry {
+    int desc;
+    int m0, n0;
+};
+struct GroupTile {
+    int first, count;
+};
+hipError_t launch_gemm_grouped(DType t, const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles,
+                               int ntiles, bool tp, bool tq, bool vec, hipStream_t st);
 // 16-bit GEMM: P is 16-bit when p16 (else FP32), Q when q16 (at least one of
-// them); C is FP32
-hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st);
+// them); C is FP32.  tile: 0 automatic, 1 128x128 tiles, 2 256x256 tiles where
+// both operands are k-contiguous (tp && !tq) and 16-byte aligned
+hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st, int tile = 0);
 // pack diagonal blocks read from A of type src into packed triangles of type dst
 hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);

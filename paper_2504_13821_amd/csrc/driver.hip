@@ -24,7 +24,9 @@
 // so every leaf but the last one is full and GEMM operands stay aligned.  The
 // plan is a flat list of launches; one pack pass before it writes every
 // diagonal block in the canonical form the leaf kernel reads.
+#include <algorithm>
 #include <cstdlib>
+#include <map>
 #include <cstring>
 
 #include "handle.h"
@@ -337,6 +339,86 @@ hipError_t run_gemms_concurrent(rtri_handle *h, const std::vector<const GemmDesc
     return e;
 }
 
+// All GEMM updates of a one-launch TRMM plan (FP64 / FP32 panel) in one
+// grouped launch: the tables are built on the host, copied to the handle's
+// workspace and read by the kernel.  Sets h->last on failure.
+static hipError_t run_grouped(rtri_handle *h, const PlanIn &p, const std::vector<Op> &ops, DType bt)
+{
+    const size_t es = bt == DType::F64 ? 8 : 4;
+    int maxd = -1;
+    for (const Op &op : ops)
+        if (op.gemm)
+            maxd = std::max(maxd, op.depth);
+    if (maxd < 0)
+        return hipSuccess;
+    std::vector<GemmDesc> descs;
+    // tile key (row tile, column tile of the panel) -> entries in order
+    std::map<std::pair<int64_t, int64_t>, std::vector<GroupEntry>> per;
+    std::map<std::pair<int64_t, int64_t>, double> work;
+    bool vec = true;
+    bool tp = false, tq = false;
+    double flops = 0.0, bytes = 0.0;
+    for (int d = maxd; d >= 0; --d)
+        for (const Op &op : ops) {
+            if (!op.gemm || op.depth != d || op.g.M <= 0 || op.g.N <= 0)
+                continue;
+            const GemmDesc &g = op.g;
+            const int idx = (int)descs.size();
+            descs.push_back(g);
+            tp = g.tp;
+            tq = g.tq;
+            const int64_t w = (int64_t)(16 / es);
+            vec = vec && (reinterpret_cast<uintptr_t>(g.P) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.Q) % 16 == 0) &&
+                  g.ldp % w == 0 && g.ldq % w == 0;
+            flops += gemm_flops(g);
+            bytes += gemm_bytes(g, es, es, es);
+            // origin of this update's C inside the panel
+            const int64_t off = (static_cast<const char *>(g.C) - p.B) / (int64_t)es;
+            const int64_t r0 = off % p.ldb, c0 = off / p.ldb;
+            for (int64_t m0 = 0; m0 < g.M; m0 += 64)
+                for (int64_t n0 = 0; n0 < g.N; n0 += 64) {
+                    const auto key = std::make_pair((r0 + m0) / 64, (c0 + n0) / 64);
+                    per[key].push_back(GroupEntry{idx, (int)m0, (int)n0});
+                    work[key] += (double)g.K;
+                }
+        }
+    std::vector<std::pair<double, std::pair<int64_t, int64_t>>> order;
+    for (const auto &kv : work)
+        order.push_back({kv.second, kv.first});
+    std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    std::vector<GroupEntry> ents;
+    std::vector<GroupTile> tiles;
+    for (const auto &o : order) {
+        const auto &v = per[o.second];
+        tiles.push_back(GroupTile{(int)ents.size(), (int)v.size()});
+        ents.insert(ents.end(), v.begin(), v.end());
+    }
+    const size_t bd = descs.size() * sizeof(GemmDesc), be = ents.size() * sizeof(GroupEntry),
+                 bti = tiles.size() * sizeof(GroupTile);
+    const size_t oe = (bd + 255) / 256 * 256, ot = oe + (be + 255) / 256 * 256;
+    std::vector<char> host(ot + bti);
+    std::memcpy(host.data(), descs.data(), bd);
+    std::memcpy(host.data() + oe, ents.data(), be);
+    std::memcpy(host.data() + ot, tiles.data(), bti);
+    hipError_t e = ensure_ws(h, WS_GROUP, host.size());
+    // pageable source: the copy is staged before the call returns, so the
+    // host vector may go away at once
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->ws[WS_GROUP], host.data(), host.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+        char *dev = static_cast<char *>(h->ws[WS_GROUP]);
+        e = timed(h, RTRI_KCLASS_GEMM, bt == DType::F64 ? RTRI_F64 : RTRI_F32, flops, bytes, [&] {
+            return launch_gemm_grouped(bt, reinterpret_cast<const GemmDesc *>(dev),
+                                       reinterpret_cast<const GroupEntry *>(dev + oe),
+                                       reinterpret_cast<const GroupTile *>(dev + ot), (int)tiles.size(), tp, tq, vec,
+                                       h->stream);
+        });
+    }
+    if (e != hipSuccess)
+        h->last = e;
+    return e;
+}
+
 bool trmm_one_launch(const rtri_handle *h, int leaf, int64_t ka, int64_t nvec)
 {
     if (leaf < 64 || ka <= leaf)   // matrix-core leaves; a single leaf has no schedule to choose
@@ -476,7 +558,7 @@ int run_plan(rtri_handle *h, const PlanIn &p)
             // the factor's block is 16-bit; the panel operand too when a TRMM reads the 16-bit original
             const bool panel16 = !p.solve && p.Bsrc16 != nullptr;
             const bool left = p.side == RTRI_LEFT;
-            return launch_gemm16(p.gt == ElemT::BF16, left || panel16, !left || panel16, g, st);
+            return launch_gemm16(p.gt == ElemT::BF16, left || panel16, !left || panel16, g, st, h->gemm16_tile);
         }
         const int tile = pick_tile(h, pcode, g.M, g.N);
         Split sp{};
@@ -512,6 +594,13 @@ int run_plan(rtri_handle *h, const PlanIn &p)
         e = timed(h, RTRI_KCLASS_LEAF_MULT, pcode, fl, by, [&] { return launch_leaf(bt, false, p.leaf, all, h->stream); });
         if (e != hipSuccess)
             return hip_fail(h, e);
+    }
+    if (one && !g16) {
+        // The updates read only the saved panel, and each 64x64 tile of the
+        // panel gets at most one update per depth, deepest first in recursion
+        // order: one launch in which a workgroup owns a tile and applies its
+        // updates in that order (tiles with the most work first).
+        return run_grouped(h, p, pl.ops, bt) == hipSuccess ? RTRI_OK : hip_fail(h, h->last);
     }
     if (one && !h->profiling) {
         // The updates read only the saved panel and each writes one row block,
@@ -610,6 +699,8 @@ int rtri_create(rtri_handle **out, void *stream)
     h->leaf_f32 = 0;
     h->gemm_tile = 0;
     h->trmm_leaves = 0;
+    h->gemm16_tile = 0;
+    h->residual = 0;
     h->tune = nullptr;
     h->last = hipSuccess;
     for (int i = 0; i < WS_COUNT; ++i) {
@@ -692,6 +783,14 @@ int rtri_set_option(rtri_handle *h, int option, int64_t value)
         if (value < 0 || value > 2) return -3;
         h->trmm_leaves = (int)value;
         return RTRI_OK;
+    case RTRI_OPT_GEMM16_TILE:
+        if (value < 0 || value > 2) return -3;
+        h->gemm16_tile = (int)value;
+        return RTRI_OK;
+    case RTRI_OPT_RESIDUAL:
+        if (value < 0 || value > 1) return -3;
+        h->residual = (int)value;
+        return RTRI_OK;
     default:
         return -2;
     }
@@ -708,6 +807,8 @@ int rtri_get_option(rtri_handle *h, int option, int64_t *value)
     case RTRI_OPT_LEAF_F32: *value = h->leaf_f32; return RTRI_OK;
     case RTRI_OPT_GEMM_TILE: *value = h->gemm_tile; return RTRI_OK;
     case RTRI_OPT_TRMM_LEAVES: *value = h->trmm_leaves; return RTRI_OK;
+    case RTRI_OPT_GEMM16_TILE: *value = h->gemm16_tile; return RTRI_OK;
+    case RTRI_OPT_RESIDUAL: *value = h->residual; return RTRI_OK;
     default: return -2;
     }
 }
@@ -819,7 +920,7 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
 {
     if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
-    if (dtype != RTRI_F64 && dtype != RTRI_F32) return -2;
+    if (dtype != RTRI_F64 && dtype != RTRI_F32 && dtype != RTRI_BF16 && dtype != RTRI_F16) return -2;
     if (trans_p != RTRI_NOTRANS && trans_p != RTRI_TRANS && trans_p != RTRI_CONJTRANS) return -3;
     if (trans_q != RTRI_NOTRANS && trans_q != RTRI_TRANS && trans_q != RTRI_CONJTRANS) return -4;
     if (M < 0) return -5;
@@ -849,6 +950,13 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
     g.tq = tq;
     g.C = C;
     g.ldc = ldc;
+    if (dtype == RTRI_BF16 || dtype == RTRI_F16) {
+        // 16-bit P and Q, FP32 C: the matrix-core tiles of the low-precision paths
+        hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, 2, 2, 4), [&] {
+            return launch_gemm16(dtype == RTRI_BF16, true, true, g, h->stream, h->gemm16_tile);
+        });
+        return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
+    }
     const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
     const size_t es = t == DType::F64 ? 8 : 4;
     hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, es, es, es), [&] {

@@ -8,7 +8,8 @@
 //     panel type: the leaves read them, the pack pass is skipped);
 //   - for the refined solve, the copy of A in the GEMM type (BF16 or FP32,
 //     transposed where the 16-bit GEMM wants it) and |op(A)| for the
-//     backward error (per side and trans).
+//     backward error (per side and trans), and with the INT8 residual product
+//     op(A)'s residue planes (per side and trans).
 // Results are bit for bit those of the plain entry points with the same
 // handle options: the same plans run on the same packed blocks.
 //
@@ -27,7 +28,7 @@ namespace {
 
 constexpr uint32_t FMAGIC = 0x72666163u;   // 'rfac'
 
-enum PartKind { PART_PACK = 0, PART_COPY = 1, PART_NORM = 2 };
+enum PartKind { PART_PACK = 0, PART_COPY = 1, PART_NORM = 2, PART_OZAKI = 3 };
 
 struct Part {
     int kind;
@@ -333,6 +334,17 @@ int rtri_factor_trsm(rtri_handle *h, rtri_factor *f, int side, int trans, int64_
             return hip_fail(h, e);
         prep.have_anorm = true;
         prep.anorm = part->value;
+        if (h->residual == 1 && ozaki_nmod(f->ka) > 0) {
+            const int koz[6] = {side, tr, 0, 0, 0, 0};
+            e = get_part(h, f, PART_OZAKI, koz, [&](Part &p) {
+                hipError_t e2 = part_alloc(h, p, ozaki_factor_bytes(side, f->ka));
+                return e2 == hipSuccess ? ozaki_split_factor(h, side, f->uplo, tr, f->diag, f->ka, A, f->lda, p.mem)
+                                        : e2;
+            }, &part);
+            if (e != hipSuccess)
+                return hip_fail(h, e);
+            prep.oz_planes = part->mem;
+        }
     }
     return mixed_core(h, side, f->uplo, tr, f->diag, m, n, alpha, A, f->lda, static_cast<double *>(B), ldb, gt, tol,
                       max_iter, info, prep);

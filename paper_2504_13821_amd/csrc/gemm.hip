@@ -73,6 +73,47 @@ gemm_kernel(GemmDesc g, int tiles_m, int tiles_n, int64_t kslice, T *part, int64
                                                                            As, Bs);
 }
 
+// Grouped updates (launch_gemm_grouped): the workgroup's tile takes its
+// updates one after another.  Each update's epilogue reads and writes the C
+// entries its own lanes wrote in the previous update (same tile shape and
+// origin), so no barrier beyond gemm_tile's own is needed between them.
+template <typename T, bool TP, bool TQ, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void grouped_kernel(
+    const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles)
+{
+    __shared__ __attribute__((aligned(16))) T As[2 * lds_elems<T, 64, TP>()];
+    __shared__ __attribute__((aligned(16))) T Bs[2 * lds_elems<T, 64, !TQ>()];
+    const GroupTile tl = tiles[blockIdx.x];
+    for (int e = tl.first; e < tl.first + tl.count; ++e) {
+        const GroupEntry en = ents[e];
+        const GemmDesc g = descs[en.desc];
+        gemm_tile<T, 64, 64, TP, TQ, VEC, 2, 2, sizeof(T) == 8>(g, en.m0, en.n0, As, Bs);
+    }
+}
+
+template <typename T, bool TP, bool TQ>
+hipError_t launch_grouped_t(const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles, int ntiles,
+                            bool vec, hipStream_t st)
+{
+    if (vec)
+        hipLaunchKernelGGL((grouped_kernel<T, TP, TQ, true>), dim3((unsigned)ntiles), dim3(256), 0, st, descs, ents,
+                           tiles);
+    else
+        hipLaunchKernelGGL((grouped_kernel<T, TP, TQ, false>), dim3((unsigned)ntiles), dim3(256), 0, st, descs, ents,
+                           tiles);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_grouped_typed(const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles, int ntiles,
+                                bool tp, bool tq, bool vec, hipStream_t st)
+{
+    if (!tp && !tq) return launch_grouped_t<T, false, false>(descs, ents, tiles, ntiles, vec, st);
+    if (tp && !tq) return launch_grouped_t<T, true, false>(descs, ents, tiles, ntiles, vec, st);
+    if (!tp && tq) return launch_grouped_t<T, false, true>(descs, ents, tiles, ntiles, vec, st);
+    return launch_grouped_t<T, true, true>(descs, ents, tiles, ntiles, vec, st);
+}
+
 // C = beta*C + s*(part_0 + part_1 + ... + part_{S-1}), partials added in order
 template <typename T>
 __global__ __launch_bounds__(256) void split_reduce_kernel(const T *part, int S, int64_t ldpart, int64_t M, int64_t N,
@@ -175,6 +216,15 @@ hipError_t launch_typed(const GemmDesc &g, int tile, bool vec, const Split &sp, 
 }
 
 }  // namespace
+
+hipError_t launch_gemm_grouped(DType t, const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles,
+                               int ntiles, bool tp, bool tq, bool vec, hipStream_t st)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    return t == DType::F64 ? launch_grouped_typed<double>(descs, ents, tiles, ntiles, tp, tq, vec, st)
+                           : launch_grouped_typed<float>(descs, ents, tiles, ntiles, tp, tq, vec, st);
+}
 
 // tile: 1 = 128x128 (4 wavefronts), 2 = 64x64, 3 = 128x128 (8 wavefronts of
 // 64x32), 0 = pick by problem size.  A split (from plan_split, with sp.part

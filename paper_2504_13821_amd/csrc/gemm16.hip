@@ -61,6 +61,23 @@ template <> __device__ __forceinline__ float4_t mfma16<false>(u16x8 a, u16x8 b, 
                                                   0, 0, 0);
 }
 
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+// 32x32x16 MFMA (gfx950).  Lane l, h = l/32, c = l%32: A operand row c,
+// k = 8h..8h+7; B operand column c, k = 8h..8h+7; D: slot 4q + r holds
+// D[8q + 4h + r][c] (q, r = 0..3).
+template <bool BF> __device__ __forceinline__ float16_t mfma32(u16x8 a, u16x8 b, float16_t c);
+template <> __device__ __forceinline__ float16_t mfma32<true>(u16x8 a, u16x8 b, float16_t c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+template <> __device__ __forceinline__ float16_t mfma32<false>(u16x8 a, u16x8 b, float16_t c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                  0, 0, 0);
+}
+
 // One R x BK operand tile: global -> registers (load), registers -> LDS as
 // Ls[row * SK + k] (store).
 //   SRC16: source is 16-bit (P); else FP32, rounded with to16 at the store (Q).
@@ -287,16 +304,242 @@ __global__ __launch_bounds__(NT, 2) void gemm16_kernel(GemmDesc g, int tiles_m, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wide tiles for large updates whose operands are both k-contiguous (op(P) =
+// P^T, op(Q) = Q; the orientation the library's 16-bit copies are made in):
+// 256x256 tiles of eight wavefronts (2 x 4, each a 128x64 tile of 32x32x16
+// MFMA blocks), BK = 64, two LDS stages and one register stage (the loads of
+// step k + 1 are in flight while step k multiplies; a step is 32 MFMAs per
+// wavefront, long enough to cover an L2 round trip).  Each wavefront reads
+// (128 + 64) x 16 operand elements from LDS per 8 MFMAs of 32x32x16, 1.5x
+// fewer bytes per flop than the 64x64 wavefront tiles of the 128x128 kernel.
+// The epilogue writes four consecutive rows of C per lane (16 bytes).
+namespace wide {
+
+constexpr int NTW = 512;
+constexpr int TW = 256;   // tile rows and columns
+
+// 256 x BK tile of a k-contiguous operand (element (row, k) at base[k + row*ld]):
+// each thread moves 4 chunks of 8 consecutive k
+template <bool SRC16, bool BF>
+struct Loader {
+    static constexpr int NCH = TW * BK / NTW / 8;   // 4
+    u16x8 h[SRC16 ? NCH : 1];
+    float4_t f[SRC16 ? 1 : 2 * NCH];
+
+    __device__ inline void load(const void *base_, int64_t ld, int tid, int rlim, int klim, bool full)
+    {
+#pragma unroll
+        for (int v = 0; v < NCH; ++v) {
+            const int e = v * NTW + tid;
+            const int row = e >> 3, k = (e & 7) * 8;
+            const int64_t off = k + (int64_t)row * ld;
+            if (full || (row < rlim && k + 8 <= klim)) {
+                if constexpr (SRC16) {
+                    h[v] = *reinterpret_cast<const u16x8 *>(static_cast<const unsigned short *>(base_) + off);
+                } else {
+                    const float *fp = static_cast<const float *>(base_) + off;
+                    f[2 * v] = *reinterpret_cast<const float4_t *>(fp);
+                    f[2 * v + 1] = *reinterpret_cast<const float4_t *>(fp + 4);
+                }
+            } else {
+#pragma unroll
+                for (int w = 0; w < 8; ++w) {
+                    const bool in = row < rlim && k + w < klim;
+                    if constexpr (SRC16)
+                        h[v][w] = in ? static_cast<const unsigned short *>(base_)[off + w] : (unsigned short)0;
+                    else
+                        f[2 * v + w / 4][w % 4] = in ? static_cast<const float *>(base_)[off + w] : 0.0f;
+                }
+            }
+        }
+    }
+
+    __device__ inline void store(unsigned short *lds, int tid) const
+    {
+#pragma unroll
+        for (int v = 0; v < NCH; ++v) {
+            const int e = v * NTW + tid;
+            const int row = e >> 3, k = (e & 7) * 8;
+            u16x8 x;
+            if constexpr (SRC16) {
+                x = h[v];
+            } else {
+#pragma unroll
+                for (int w = 0; w < 8; ++w)
+                    x[w] = to16<BF>(f[2 * v + w / 4][w % 4]);
+            }
+            *reinterpret_cast<u16x8 *>(lds + row * SK + k) = x;
+        }
+    }
+};
+
+template <bool BF, bool P16, bool Q16>
+__global__ __launch_bounds__(NTW, 1) void gemm16w_kernel(GemmDesc g, int tiles_m, int tiles_n)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][TW * SK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][TW * SK];
+
+    // blocks go round robin over the eight XCDs: give each XCD a contiguous
+    // range of tiles, then walk the tiles in bands of GROUP tile rows so that
+    // blocks in flight together share operand panels in L2
+    const int ntiles = tiles_m * tiles_n;
+    int bid = blockIdx.x;
+    if ((ntiles & 7) == 0) {
+        const int per = ntiles >> 3;
+        bid = (bid & 7) * per + (bid >> 3);
+    }
+    constexpr int GROUP = 4;
+    const int band = bid / (GROUP * tiles_n);
+    const int first_m = band * GROUP;
+    const int gsize = min(tiles_m - first_m, GROUP);
+    const int in_band = bid - band * GROUP * tiles_n;
+    const int tm = first_m + in_band % gsize;
+    const int tn = in_band / gsize;
+
+    const int64_t m0 = (int64_t)tm * TW, n0 = (int64_t)tn * TW;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lr = lane & 31, lh = lane >> 5;
+
+    using PT = typename std::conditional<P16, unsigned short, float>::type;
+    using QT = typename std::conditional<Q16, unsigned short, float>::type;
+    const PT *Pt = static_cast<const PT *>(g.P) + m0 * g.ldp;   // op(P) = P^T: row m at P + m*ldp
+    const QT *Qt = static_cast<const QT *>(g.Q) + n0 * g.ldq;   // column n at Q + n*ldq
+    const int rlim_m = (int)min<int64_t>(TW, g.M - m0);
+    const int rlim_n = (int)min<int64_t>(TW, g.N - n0);
+    const bool full_mn = rlim_m == TW && rlim_n == TW;
+
+    Loader<P16, BF> la;
+    Loader<Q16, BF> lb;
+    float16_t acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                acc[i][j][r] = 0.0f;
+
+    const int64_t K = g.K;
+    const int nk = (int)((K + BK - 1) / BK);
+    auto load_step = [&](int kt) {
+        const int64_t k0 = (int64_t)kt * BK;
+        const int klim = (int)min<int64_t>(BK, K - k0);
+        const bool full = full_mn && klim == BK;
+        la.load(Pt + k0, g.ldp, tid, rlim_m, klim, full);
+        lb.load(Qt + k0, g.ldq, tid, rlim_n, klim, full);
+    };
+
+    if (nk > 0) {
+        load_step(0);
+        la.store(As[0], tid);
+        lb.store(Bs[0], tid);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk)
+            load_step(kt + 1);
+        const unsigned short *as = &As[buf][(wm * 128 + lr) * SK + 8 * lh];
+        const unsigned short *bs = &Bs[buf][(wn * 64 + lr) * SK + 8 * lh];
+#pragma unroll
+        for (int ks = 0; ks < BK / 16; ++ks) {
+            u16x8 fa[4], fb[2];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                fa[i] = *reinterpret_cast<const u16x8 *>(as + i * 32 * SK + ks * 16);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                fb[j] = *reinterpret_cast<const u16x8 *>(bs + j * 32 * SK + ks * 16);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = mfma32<BF>(fa[i], fb[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) {
+            la.store(As[buf ^ 1], tid);
+            lb.store(Bs[buf ^ 1], tid);
+        }
+        __syncthreads();
+    }
+
+    float *C = static_cast<float *>(g.C);
+    const int64_t ldc = g.ldc;
+    const float beta = (float)g.beta, s = (float)g.s;
+    const bool zero_beta = g.beta == 0.0;
+    const bool cvec = full_mn && (reinterpret_cast<uintptr_t>(C) & 15) == 0 && (ldc & 3) == 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int cl = wn * 64 + j * 32 + lr;
+            float *cp = C + m0 + (n0 + cl) * ldc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int rb = wm * 128 + i * 32 + 8 * q + 4 * lh;   // four consecutive rows rb..rb+3
+                if (cvec) {
+                    float4_t v;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        v[r] = s * acc[i][j][4 * q + r];
+                    float4_t *c4 = reinterpret_cast<float4_t *>(cp + rb);
+                    if (!zero_beta) {
+                        const float4_t o = *c4;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            v[r] = fmat(beta, o[r], v[r]);
+                    }
+                    *c4 = v;
+                } else if (cl < rlim_n) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        if (rb + r < rlim_m) {
+                            const float v = s * acc[i][j][4 * q + r];
+                            cp[rb + r] = zero_beta ? v : fmat(beta, cp[rb + r], v);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace wide
+
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
+// whether an update takes the wide tiles (tile: 0 automatic, 1 128x128, 2 wide
+// where the operand layout allows): enough 256x256 tiles to keep most CUs
+// busy, and a K long enough for the deeper tile to pay off
+bool use_wide(const GemmDesc &g, int tile)
+{
+    if (tile == 1)
+        return false;
+    if (tile == 2)
+        return true;
+    const int64_t tw = ((g.M + 255) / 256) * ((g.N + 255) / 256);
+    return tw >= 96 && g.K >= 256;
+}
+
 template <bool TP, bool TQ, bool BF, bool P16, bool Q16>
-hipError_t launch_t16(const GemmDesc &g, hipStream_t st)
+hipError_t launch_t16(const GemmDesc &g, hipStream_t st, int tile)
 {
     constexpr int BM = 128, BN = 128;
     const int tm = (int)((g.M + BM - 1) / BM), tn = (int)((g.N + BN - 1) / BN);
     // 16-byte chunks: 8 elements of a 16-bit operand, 4 of an FP32 one
     const int64_t lp = P16 ? 8 : 4, lq = Q16 ? 8 : 4;
     const bool vec = aligned16(g.P) && aligned16(g.Q) && g.ldp % lp == 0 && g.ldq % lq == 0;
+    if constexpr (TP && !TQ) {
+        if (vec && use_wide(g, tile)) {
+            const int wm = (int)((g.M + 255) / 256), wn = (int)((g.N + 255) / 256);
+            hipLaunchKernelGGL((wide::gemm16w_kernel<BF, P16, Q16>), dim3((unsigned)(wm * wn)), dim3(wide::NTW), 0,
+                               st, g, wm, wn);
+            return hipGetLastError();
+        }
+    }
     if (vec)
         hipLaunchKernelGGL((gemm16_kernel<BM, BN, TP, TQ, BF, P16, Q16, true>), dim3((unsigned)(tm * tn)), dim3(NT),
                            0, st, g, tm, tn);
@@ -307,31 +550,31 @@ hipError_t launch_t16(const GemmDesc &g, hipStream_t st)
 }
 
 template <bool BF, bool P16, bool Q16>
-hipError_t launch_bf(const GemmDesc &g, hipStream_t st)
+hipError_t launch_bf(const GemmDesc &g, hipStream_t st, int tile)
 {
-    if (!g.tp && !g.tq) return launch_t16<false, false, BF, P16, Q16>(g, st);
-    if (g.tp && !g.tq) return launch_t16<true, false, BF, P16, Q16>(g, st);
-    if (!g.tp && g.tq) return launch_t16<false, true, BF, P16, Q16>(g, st);
-    return launch_t16<true, true, BF, P16, Q16>(g, st);
+    if (!g.tp && !g.tq) return launch_t16<false, false, BF, P16, Q16>(g, st, tile);
+    if (g.tp && !g.tq) return launch_t16<true, false, BF, P16, Q16>(g, st, tile);
+    if (!g.tp && g.tq) return launch_t16<false, true, BF, P16, Q16>(g, st, tile);
+    return launch_t16<true, true, BF, P16, Q16>(g, st, tile);
 }
 
 template <bool BF>
-hipError_t launch_types(bool p16, bool q16, const GemmDesc &g, hipStream_t st)
+hipError_t launch_types(bool p16, bool q16, const GemmDesc &g, hipStream_t st, int tile)
 {
     if (p16 && q16)
-        return launch_bf<BF, true, true>(g, st);
-    return p16 ? launch_bf<BF, true, false>(g, st) : launch_bf<BF, false, true>(g, st);
+        return launch_bf<BF, true, true>(g, st, tile);
+    return p16 ? launch_bf<BF, true, false>(g, st, tile) : launch_bf<BF, false, true>(g, st, tile);
 }
 
 }  // namespace
 
-hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st)
+hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st, int tile)
 {
     if (!p16 && !q16)
         return hipErrorInvalidValue;
     if (g.M <= 0 || g.N <= 0)
         return hipSuccess;
-    return bf16 ? launch_types<true>(p16, q16, g, st) : launch_types<false>(p16, q16, g, st);
+    return bf16 ? launch_types<true>(p16, q16, g, st, tile) : launch_types<false>(p16, q16, g, st, tile);
 }
 
 }  // namespace rtri

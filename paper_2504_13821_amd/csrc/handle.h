@@ -39,6 +39,10 @@ enum WsSlot {
     WS_PERM,         // the row permutation of those interchanges
     WS_ZEMB,         // real embedding of a complex op(A) (2 ka x 2 ka)
     WS_ZT,           // transposed complex right-hand side (side R)
+    WS_OZA,          // INT8 residue planes of op(A) (Ozaki-scheme product)
+    WS_OZX,          // INT8 residue planes of the panel
+    WS_OZR,          // residues of the integer product, one byte plane per modulus
+    WS_GROUP,        // tables of a grouped update launch (descs, entries, tiles)
     WS_COUNT
 };
 
@@ -80,6 +84,8 @@ struct rtri_handle {
     hipStream_t stream;
     int leaf_f64, leaf_f32, gemm_tile;
     int trmm_leaves;   // RTRI_OPT_TRMM_LEAVES: 0 automatic, 1 one launch per leaf, 2 all leaves in one launch
+    int gemm16_tile;   // RTRI_OPT_GEMM16_TILE: 0 automatic, 1 128x128, 2 256x256 where the layout allows
+    int residual;      // RTRI_OPT_RESIDUAL: refined solve's residual product, 0 FP64 MFMA, 1 INT8 (Ozaki)
     rtri::TuneDB *tune;
     hipError_t last;
     void *ws[rtri::WS_COUNT];
@@ -147,6 +153,7 @@ struct MixedPrep {
     const void *lo_pack = nullptr;  // packed FP32 solve blocks for leaf lo_leaf; nullptr: packed on first use
     const void *mul_pack = nullptr; // packed FP64 multiply blocks for leaf mul_leaf; nullptr: likewise
     int lo_leaf = 0, mul_leaf = 0;
+    const void *oz_planes = nullptr; // op(A)'s INT8 residue planes (INT8-product residual); nullptr: made by the call
     bool have_anorm = false;        // anorm known (else computed by the call)
     double anorm = 0.0;             // |op(A)|_inf (side L) or |op(A)|_1 (side R)
 };
@@ -172,6 +179,21 @@ PlanIn mixed_lo_plan(rtri_handle *h, int side, int uplo, int tr, int diag, int64
                      const double *A, int64_t lda);
 PlanIn mixed_mul_plan(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, const double *A,
                       int64_t lda);
+
+// FP64-accurate triangular product from INT8 matrix-core products (ozaki.hip):
+// moduli used for inner dimension K (0: K beyond the method's range), and
+// the bits beta kept of each scaled operand entry
+int ozaki_nmod(int64_t K);
+int ozaki_beta(int64_t K);
+// device bytes of op(A)'s residue planes (and line exponents) for order ka
+size_t ozaki_factor_bytes(int side, int64_t ka);
+// op(A)'s planes into mem (ozaki_factor_bytes), on the handle's stream
+hipError_t ozaki_split_factor(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t ka, const double *A,
+                              int64_t lda, void *mem);
+// W := alpha op(A) X (side L) or alpha X op(A) (side R), m x n, from op(A)'s
+// planes; X may equal W (its planes are made first).  RTRI_* status.
+int ozaki_product(rtri_handle *h, int side, int uplo, int tr, int64_t m, int64_t n, double alpha, const void *Aplanes,
+                  const double *X, int64_t ldx, double *W, int64_t ldw);
 
 // Reusable staging for batched launches issued by a long-lived caller (a
 // serving slot): pinned host tables and their device copy, grown on demand.

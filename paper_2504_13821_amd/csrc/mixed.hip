@@ -167,6 +167,17 @@ int mixed_core(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, 
     mul.ldb = ld;
     if (prep.mul_pack != nullptr && prep.mul_leaf == mul.leaf)
         mul.packed = prep.mul_pack;
+    // residual product from exact INT8 products: op(A)'s residue planes once
+    const bool int8_resid = h->residual == 1 && ozaki_nmod(ka) > 0;
+    const void *oz_planes = prep.oz_planes;
+    if (int8_resid && oz_planes == nullptr) {
+        e = ensure_ws(h, WS_OZA, ozaki_factor_bytes(side, ka));
+        if (e == hipSuccess)
+            e = ozaki_split_factor(h, side, uplo, tr, diag, ka, A, lda, h->ws[WS_OZA]);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        oz_planes = h->ws[WS_OZA];
+    }
 
     double eta = rmax == 0.0 ? 0.0 : INFINITY, eta_prev = INFINITY;
     int iters = 0;
@@ -187,10 +198,14 @@ int mixed_core(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, 
                   [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, assign, W, ld, st); });
         if (e != hipSuccess)
             return hip_fail(h, e);
-        rc = run_plan(h, mul);
+        if (int8_resid) {
+            rc = ozaki_product(h, side, uplo, tr, m, n, 1.0, oz_planes, W, ld, W, ld);
+        } else {
+            rc = run_plan(h, mul);
+            mul.skip_pack = true;
+        }
         if (rc != RTRI_OK)
             return rc;
-        mul.skip_pack = true;
         e = launch_zero_u64(sc, 2, st);
         if (e == hipSuccess)
             e = other(32.0 * mn, [&] {

@@ -68,7 +68,7 @@ BAD_ARGS = [
 ]
 
 
-@pytest.mark.parametrize("fname", ["rtri_dtrsm", "rtri_strsm", "rtri_dtrmm", "rtri_strmm"])
+@pytest.mark.parametrize("fname", ["rtri_dtrsm", "rtri_strsm", "rtri_dtrmm", "rtri_strmm", "rtri_dtrmm_ozaki"])
 @pytest.mark.parametrize("args,code", BAD_ARGS)
 def test_argument_codes(rt, handle, fname, args, code):
     side, uplo, trans, diag, m, n, A, lda, B, ldb = args
@@ -94,6 +94,13 @@ def test_options(rt, handle):
         assert rt.rtri_set_option(handle, rt.OPT_TRMM_LEAVES, mode) == rt.OK
         assert rt.rtri_get_option(handle, rt.OPT_TRMM_LEAVES, ctypes.byref(v)) == rt.OK and v.value == mode
     assert rt.rtri_set_option(handle, rt.OPT_TRMM_LEAVES, 3) == -3
+    for opt, top in ((rt.OPT_GEMM16_TILE, 2), (rt.OPT_RESIDUAL, 1)):
+        assert rt.rtri_get_option(handle, opt, ctypes.byref(v)) == rt.OK and v.value == 0
+        for mode in range(top + 1):
+            assert rt.rtri_set_option(handle, opt, mode) == rt.OK
+            assert rt.rtri_get_option(handle, opt, ctypes.byref(v)) == rt.OK and v.value == mode
+        assert rt.rtri_set_option(handle, opt, top + 1) == -3
+        assert rt.rtri_set_option(handle, opt, -1) == -3
     assert rt.rtri_set_option(handle, 999, 1) == -2
 
 
@@ -282,3 +289,10 @@ def test_solver_argument_codes(rt, handle):
         assert fn(handle, 0, 4, 2, FAKE, 4, piv, None, 4) == -8
         assert fn(handle, 0, 4, 2, FAKE, 4, piv, FAKE, 3) == -9
         assert fn(handle, 0, 4, 0, FAKE, 4, piv, None, 4) == rt.OK
+
+
+def test_ozaki_order_limit(rt, handle):
+    """The INT8-product TRMM refuses orders whose exact INT32 sums could
+    overflow (K > 2^17) before any device work."""
+    big = (1 << 17) + 1
+    assert rt.rtri_dtrmm_ozaki(handle, 0, 0, 0, 0, big, 1, 1.0, FAKE, big, FAKE, big) == rt.ERR_UNSUPPORTED

@@ -248,8 +248,10 @@ def test_vector_and_element_paths_agree(rt, h, orc, dt, leaf, op, uplo, m):
 @pytest.mark.parametrize("shape", [(600, 130), (1000, 257), (301, 70)])
 def test_trmm_leaf_schedules_agree(rt, h, orc, dt, leaf, side, uplo, trans, shape):
     """TRMM with one launch per leaf (recursion order) and with every leaf in
-    one launch after saving the panel: the GEMM updates see the same operands,
-    so the results agree bit for bit; both pass the oracle's bound."""
+    one launch after saving the panel, then all updates in one grouped launch:
+    the GEMM updates see the same operands and every entry the same MFMA
+    sequence (no update of these orders splits K), so the results agree bit
+    for bit; both pass the oracle's bound."""
     m, n = shape if side == "L" else shape[::-1]
     say("trmm schedules", dt, leaf, side, uplo, trans, m, n)
     A, B = _inputs(side, uplo, "N", m, n, dt, G(17, m, n))

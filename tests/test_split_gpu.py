@@ -48,8 +48,10 @@ def test_split_narrow_parity(rt, h, orc, dt, op, side, uplo, trans):
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_split_trmm_concurrent_schedules(rt, h, orc, dt):
-    """m = 8192, 128 vectors: the depth-1 updates (2048 x 128 x 2048, over
-    1 GFLOP each) run on two streams at once and both split K."""
+    """m = 8192, 128 vectors: one launch per leaf, whose long updates split K,
+    against every leaf in one launch followed by one grouped launch of all
+    updates (no split): the same sums in another order, so both must meet the
+    oracle's bound and agree to within it."""
     m, n = 8192, 128
     say("split trmm schedules", dt)
     g = G(2, m)
@@ -61,7 +63,9 @@ def test_split_trmm_concurrent_schedules(rt, h, orc, dt):
         h.set_option(rt.OPT_TRMM_LEAVES, mode)
         out.append(run_op(rt, h, "trmm", "L", "L", "N", "N", 1.0, A, B, dt))
     h.set_option(rt.OPT_TRMM_LEAVES, 0)
-    assert np.array_equal(out[0], out[1])
     idx = np.sort(G(3).choice(n, 8, replace=False))
-    e = orc.trmm_eta("L", "L", "N", "N", 1.0, A, np.asfortranarray(B[:, idx]), np.asfortranarray(out[1][:, idx]))
-    assert e <= TOL[dt], e
+    for X in out:
+        e = orc.trmm_eta("L", "L", "N", "N", 1.0, A, np.asfortranarray(B[:, idx]), np.asfortranarray(X[:, idx]))
+        assert e <= TOL[dt], e
+    scale = np.max(np.abs(out[0]))
+    assert np.max(np.abs(out[0] - out[1])) <= 64 * TOL[dt] * scale
