@@ -42,6 +42,8 @@
  *   RTRI_ERR_HIP      a HIP runtime call failed (rtri_last_hip_error gives it)
  *   RTRI_ERR_NOMEM    device workspace could not be allocated
  *   RTRI_ERR_UNSUPPORTED  option or type combination not supported
+ *   RTRI_ERR_TOO_LARGE    the problem does not fit the fixed scratch of
+ *                         rtri_dtrsm_noalloc
  */
 #ifndef RTRI_H
 #define RTRI_H
@@ -66,7 +68,8 @@ enum {
     RTRI_ERR_NOMEM = 3,
     RTRI_ERR_UNSUPPORTED = 4,
     RTRI_NOT_CONVERGED = 5,
-    RTRI_ERR_INVALID = 6
+    RTRI_ERR_INVALID = 6,
+    RTRI_ERR_TOO_LARGE = 7
 };
 
 /* Tunable options (rtri_set_option / rtri_get_option). */
@@ -174,6 +177,27 @@ int rtri_ztrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t 
  * of 131072 or more. */
 int rtri_dtrmm_ozaki(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
                      double alpha, const double *A, int64_t lda, double *B, int64_t ldb);
+
+/* FP64 TRSM that allocates nothing, for callers that cannot call hipMalloc
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, codes and results as rtri_dtrsm (bit for bit,
+ * with the same handle options); the handle must have been created outside
+ * such a region (rtri_create allocates no device memory).
+ * Its workspace (the packed diagonal blocks and one region of split-K partial
+ * products) is a fixed array of RTRI_NOALLOC_SCRATCH_MIB MiB of device memory
+ * defined by the library: each GPU the library runs on holds one copy, from
+ * the first rtri_create (or call) on that device until the process ends.  No
+ * memory is allocated by the call, and nothing in the array needs clearing.
+ * Limits and rules:
+ *   - the packed blocks must fit 32 MiB (plan size: ka/leaf blocks of
+ *     128 (leaf/16)(leaf/16 + 1) doubles, e.g. ka <= 29000 with 256-row
+ *     leaves); larger problems return RTRI_ERR_TOO_LARGE without touching B;
+ *   - calls that overlap in time on one GPU (on different streams or
+ *     handles) share the array and race: serialise them;
+ *   - a handle with an open profile returns RTRI_ERR_UNSUPPORTED. */
+#define RTRI_NOALLOC_SCRATCH_MIB 48
+int rtri_dtrsm_noalloc(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n,
+                       double alpha, const double *A, int64_t lda, double *B, int64_t ldb);
 
 /* Per-kernel profile: while a profile is open, every kernel the handle
  * launches is bracketed by two HIP events recorded on the handle's stream, and

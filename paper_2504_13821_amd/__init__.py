@@ -35,7 +35,7 @@ LOWER, UPPER = 0, 1
 NOTRANS, TRANS, CONJTRANS = 0, 1, 2
 NONUNIT, UNIT = 0, 1
 F64, F32, BF16, F16 = 0, 1, 2, 3
-OK, ERR_HANDLE, ERR_HIP, ERR_NOMEM, ERR_UNSUPPORTED, NOT_CONVERGED, ERR_INVALID = range(7)
+OK, ERR_HANDLE, ERR_HIP, ERR_NOMEM, ERR_UNSUPPORTED, NOT_CONVERGED, ERR_INVALID, ERR_TOO_LARGE = range(8)
 OPT_LEAF_F64, OPT_LEAF_F32, OPT_GEMM_TILE, OPT_TRMM_LEAVES, OPT_GEMM16_TILE, OPT_RESIDUAL = 1, 2, 3, 4, 5, 6
 
 _vp = ctypes.c_void_p
@@ -63,6 +63,7 @@ rtri_dtrsm = _sig("rtri_dtrsm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp,
 rtri_strsm = _sig("rtri_strsm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
 rtri_dtrmm = _sig("rtri_dtrmm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
 rtri_strmm = _sig("rtri_strmm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
+rtri_dtrsm_noalloc = _sig("rtri_dtrsm_noalloc", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
 rtri_dtrmm_ozaki = _sig("rtri_dtrmm_ozaki", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
 rtri_trmm_ex = _sig("rtri_trmm_ex", _int, *_OPARGS, ctypes.c_float, _vp, _int, _i64, _vp, _int, _i64, _vp, _int, _i64)
 
@@ -309,6 +310,25 @@ def trsm(h: Handle, side, uplo, trans, diag, alpha, A, B):
 def trmm(h: Handle, side, uplo, trans, diag, alpha, A, B):
     """In place: B := alpha op(A) B (side 'L') or alpha B op(A) (side 'R')."""
     return _call(h, False, side, uplo, trans, diag, alpha, A, B)
+
+
+def trsm_noalloc(h: Handle, side, uplo, trans, diag, alpha, A, B):
+    """As trsm for FP64, through rtri_dtrsm_noalloc: no device memory is allocated by the call (its
+    workspace is the library's fixed device array)."""
+    if B.dim() != 2:
+        raise ValueError("B must be 2-D")
+    m, n = B.shape
+    ka = _factor_order(side, B)
+    _need_shape(A, "A", ka, ka)
+    _same_device(A=A, B=B)
+    lda = _colmajor(A, "A")
+    ldb = _colmajor(B, "B")
+    if A.dtype != torch.float64 or B.dtype != torch.float64:
+        raise TypeError("trsm_noalloc takes float64 A and B")
+    rc = rtri_dtrsm_noalloc(h.ptr, *codes(side, uplo, trans, diag), m, n, alpha, A.data_ptr(), lda, B.data_ptr(),
+                            ldb)
+    check(rc, "rtri_dtrsm_noalloc")
+    return B
 
 
 def trmm_ozaki(h: Handle, side, uplo, trans, diag, alpha, A, B):

@@ -502,7 +502,7 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     // panel from a copy (m x n, leading dimension m), so the leaves may all run
     // first; every update sees the same operands as in recursion order
     const int64_t nvec_all = p.side == RTRI_LEFT ? p.n : p.m;
-    const bool one = !p.solve && trmm_one_launch(h, p.leaf, ka, nvec_all);
+    const bool one = !p.solve && p.ext_split == nullptr && trmm_one_launch(h, p.leaf, ka, nvec_all);
     // a TRMM whose updates read the 16-bit original needs no saved copy
     const bool save = one && p.Bsrc16 == nullptr;
     if (save) {
@@ -517,13 +517,16 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     // pack every diagonal block once into the canonical form the leaves read
     // (unless the plan brings its blocks packed already)
     if (p.packed == nullptr && !p.skip_pack) {
-        hipError_t e0 = ensure_ws(h, p.pack_slot, plan_pack_bytes(p));
+        hipError_t e0 = hipSuccess;
+        if (p.ext_pack == nullptr)
+            e0 = ensure_ws(h, p.pack_slot, plan_pack_bytes(p));
         if (e0 == hipSuccess)
-            e0 = pack_plan(h, p, h->ws[p.pack_slot]);
+            e0 = pack_plan(h, p, p.ext_pack != nullptr ? p.ext_pack : h->ws[p.pack_slot]);
         if (e0 != hipSuccess)
             return hip_fail(h, e0);
     }
-    const char *pack_base = static_cast<const char *>(p.packed != nullptr ? p.packed : h->ws[p.pack_slot]);
+    const char *pack_base = static_cast<const char *>(
+        p.packed != nullptr ? p.packed : (p.ext_pack != nullptr ? p.ext_pack : h->ws[p.pack_slot]));
     for (Op &op : pl.ops)
         if (!op.gemm)
             op.l.Lp = pack_base + reinterpret_cast<intptr_t>(op.l.Lp);
@@ -537,12 +540,14 @@ int run_plan(rtri_handle *h, const PlanIn &p)
         for (const Op &op : pl.ops)
             if (op.gemm && plan_split(bt, op.g, pick_tile(h, pcode, op.g.M, op.g.N), SPLIT_REGION_BYTES).slices >= 2)
                 any_split = true;
-    if (any_split) {
+    if (any_split && p.ext_split == nullptr) {
         hipError_t e0 = ensure_ws(h, WS_SPLIT, SPLIT_WS_BYTES);
         if (e0 != hipSuccess)
             return hip_fail(h, e0);
     }
     auto split_region = [&](hipStream_t st) -> void * {
+        if (p.ext_split != nullptr)
+            return st == h->stream ? p.ext_split : nullptr;
         int r = 0;
         if (st != h->stream)
             for (int i = 0; i < 4; ++i)
@@ -709,6 +714,7 @@ int rtri_create(rtri_handle **out, void *stream)
     }
     h->profiling = false;
     h->pool_used = 0;
+    noalloc_prepare();   // the no-allocation entry point's scratch address on this device
     h->aux_ready = false;
     h->mem_pool = nullptr;
     // a tuning database named by the environment applies to every new handle
@@ -831,6 +837,7 @@ const char *rtri_status_string(int s)
     case RTRI_ERR_UNSUPPORTED: return "unsupported option or type combination";
     case RTRI_NOT_CONVERGED: return "iterative refinement did not converge";
     case RTRI_ERR_INVALID: return "invalid input";
+    case RTRI_ERR_TOO_LARGE: return "problem exceeds the fixed scratch of the no-allocation entry point";
     default: return "unknown status";
     }
 }

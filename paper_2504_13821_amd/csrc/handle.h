@@ -75,6 +75,13 @@ struct PlanIn {
     // panel or its saved copy; nullptr otherwise
     const char *Bsrc16;
     int64_t ldbsrc16;
+    // caller-supplied device workspace in place of the handle's slots (both
+    // nullptr: the handle's own, grown on demand).  ext_pack receives the
+    // packed blocks (plan_pack_bytes); ext_split is the split-K region of the
+    // handle's stream (SPLIT_REGION_BYTES).  With ext_split set, updates on
+    // other streams do not split, and a TRMM plan never saves its panel.
+    void *ext_pack;
+    void *ext_split;
 };
 
 }  // namespace rtri
@@ -108,6 +115,9 @@ struct rtri_handle {
 namespace rtri {
 
 bool handle_valid(const rtri_handle *h);
+// takes the device address of the no-allocation entry point's scratch on the
+// current device (once per device; failures are left to that entry point)
+void noalloc_prepare();
 int hip_fail(rtri_handle *h, hipError_t e);
 hipError_t ensure_ws(rtri_handle *h, int slot, size_t bytes);
 // leaf size: the handle's option, else the tuning database, else 64

@@ -68,7 +68,8 @@ BAD_ARGS = [
 ]
 
 
-@pytest.mark.parametrize("fname", ["rtri_dtrsm", "rtri_strsm", "rtri_dtrmm", "rtri_strmm", "rtri_dtrmm_ozaki"])
+@pytest.mark.parametrize("fname", ["rtri_dtrsm", "rtri_strsm", "rtri_dtrmm", "rtri_strmm", "rtri_dtrsm_noalloc",
+                                   "rtri_dtrmm_ozaki"])
 @pytest.mark.parametrize("args,code", BAD_ARGS)
 def test_argument_codes(rt, handle, fname, args, code):
     side, uplo, trans, diag, m, n, A, lda, B, ldb = args
@@ -289,6 +290,20 @@ def test_solver_argument_codes(rt, handle):
         assert fn(handle, 0, 4, 2, FAKE, 4, piv, None, 4) == -8
         assert fn(handle, 0, 4, 2, FAKE, 4, piv, FAKE, 3) == -9
         assert fn(handle, 0, 4, 0, FAKE, 4, piv, None, 4) == rt.OK
+
+
+def test_noalloc_rejects_problems_beyond_its_scratch(rt, handle):
+    """rtri_dtrsm_noalloc refuses a factor whose packed blocks exceed its fixed
+    array (ka = 40000 with 256-row leaves: 157 blocks of 278528 bytes) before
+    any device work; the allocating entry point has no such limit."""
+    assert rt.rtri_set_option(handle, rt.OPT_LEAF_F64, 256) == rt.OK
+    big = 40000
+    assert rt.rtri_dtrsm_noalloc(handle, 0, 0, 0, 0, big, 1, 1.0, FAKE, big, FAKE, big) == rt.ERR_TOO_LARGE
+    assert rt.rtri_dtrsm_noalloc(handle, 1, 0, 0, 0, 1, big, 1.0, FAKE, big, FAKE, 1) == rt.ERR_TOO_LARGE
+    assert b"scratch" in rt.rtri_status_string(rt.ERR_TOO_LARGE)
+    # an open profile is refused (it would create events on demand)
+    assert rt.rtri_profile_begin(handle) == rt.OK
+    assert rt.rtri_dtrsm_noalloc(handle, 0, 0, 0, 0, 4, 4, 1.0, FAKE, 4, FAKE, 4) == rt.ERR_UNSUPPORTED
 
 
 def test_ozaki_order_limit(rt, handle):
