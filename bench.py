@@ -34,7 +34,7 @@ HBM_PEAK = 8000.0                                                    # GB/s
 # PMC passes (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 2 GiB copy in the
 # same process; profiles/gemm_f64_16384_traffic.txt).  Valid only for the GEMM
 # sources they were taken on: reported as null once those change.
-GEMM_TRAFFIC = {"bytes_per_launch": 1.0347e9, "sources_sha256_16": "b190c45f11c15130"}
+GEMM_TRAFFIC = {"bytes_per_launch": 1.0388e9, "sources_sha256_16": "95fce603c9305e4d"}
 
 
 def gemm_sources_digest():
@@ -59,6 +59,8 @@ def parse():
                     help="comma-separated extra sections to run (default: all but 'vendor', the rocBLAS "
                          "comparison, which runs only when named)")
     ap.add_argument("--serve-requests", type=int, default=5000)
+    ap.add_argument("--serve-rates", default="0.1,0.25,0.5,0.75,0.9,1.0,1.2",
+                    help="open-loop arrival rates as fractions of the measured saturation throughput")
     ap.add_argument("--tuning", default="", help="tuning database (default: the package's, if present)")
     return ap.parse_args()
 
@@ -214,7 +216,8 @@ def main():
         out["batched"] = bench_batched(rt, torch, h)
         progress("batched done")
     if "serving" in extras:
-        out["serving"] = bench_serving(rt, args.serve_requests)
+        out["serving"] = bench_serving(rt, args.serve_requests,
+                                       [float(x) for x in args.serve_rates.split(",") if x.strip()])
         progress("serving done")
     if "vendor" in extras:
         out["vendor_context"] = bench_vendor(rt, torch, h, m)
@@ -721,7 +724,7 @@ def serving_stream(count, seed_key=0):
     return reqs
 
 
-def bench_serving(rt, count):
+def bench_serving(rt, count, rates=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
     """Closed-loop saturation, then open-loop Poisson arrivals at fractions of
     it.  Latency = completion seen on the host minus the scheduled arrival (no
     coordinated omission), overall and per tag (FP64 TRSM, FP64 TRMM, refined
@@ -791,7 +794,7 @@ def bench_serving(rt, count):
     res["saturation"] = sat
     mu = sat["solves_per_s"]
     res["rates"] = {}
-    for frac in (0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+    for frac in rates:
         r, _ = run(frac * mu)
         res["rates"][str(frac)] = dict(r, rate_per_s=round(frac * mu, 1))
         progress("serving rate", frac)

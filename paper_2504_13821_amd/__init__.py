@@ -216,7 +216,7 @@ class Handle:
 
     def tune(self, dtype="f64", max_order=16384, db_path=None):
         """Run the tuning sweep (blocking) and keep its rules; optionally write them as JSON."""
-        check(rtri_tune(self._h, {"f64": F64, "f32": F32}[dtype], max_order,
+        check(rtri_tune(self._h, {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}[dtype], max_order,
                         db_path.encode() if db_path else None), "rtri_tune")
 
     def load_tuning(self, path=TUNING_DB):

@@ -108,9 +108,13 @@ int build_tables(rtri_handle *h, int dtype, int count, const rtri_batch_entry *e
     if (dtype != RTRI_F64 && dtype != RTRI_F32)
         return RTRI_ERR_UNSUPPORTED;
     const DType t = dtype == RTRI_F64 ? DType::F64 : DType::F32;
-    // one leaf size per batch: 32 if the handle would pick at most 32 for an
-    // order-1024, 64-vector problem, else the 64-row matrix-core leaf
-    const int nb = pick_leaf(h, t, true, 1024, 64) <= 32 ? 32 : 64;
+    // one leaf size per batch: the handle's leaf option decides if set (32 if
+    // it picks at most 32 for an order-1024, 64-vector problem, else the
+    // 64-row matrix-core leaf), else the tuning database's batched rule, else
+    // the same choice from the handle's single-call policy
+    const int opt = t == DType::F64 ? h->leaf_f64 : h->leaf_f32;
+    const int tuned = opt == 0 ? tuned_batch_leaf(h->tune, dtype) : 0;
+    const int nb = tuned != 0 ? tuned : (pick_leaf(h, t, true, 1024, 64) <= 32 ? 32 : 64);
     std::vector<BInst> &insts = tb.insts;
     std::vector<BItem> items;
     std::vector<BOp> &ops = tb.ops;

@@ -26,7 +26,6 @@
 // diagonal block in the canonical form the leaf kernel reads.
 #include <algorithm>
 #include <cstdlib>
-#include <map>
 #include <cstring>
 
 #include "handle.h"
@@ -339,12 +338,17 @@ hipError_t run_gemms_concurrent(rtri_handle *h, const std::vector<const GemmDesc
     return e;
 }
 
-// All GEMM updates of a one-launch TRMM plan (FP64 / FP32 panel) in one
-// grouped launch: the tables are built on the host, copied to the handle's
-// workspace and read by the kernel.  Sets h->last on failure.
+// All GEMM updates of a one-launch TRMM plan in one grouped launch: FP64 /
+// FP32 panels in 64x64 tiles, 16-bit updates (both operands 16-bit) in
+// 256x256 tiles.  The tables are built on the host, copied to the handle's
+// workspace and read by the kernel.  Returns hipErrorNotSupported, with
+// nothing launched, when 16-bit updates do not fit the 256x256 tiles (then
+// the caller runs them depth by depth); sets h->last on other failures.
 static hipError_t run_grouped(rtri_handle *h, const PlanIn &p, const std::vector<Op> &ops, DType bt)
 {
     const size_t es = bt == DType::F64 ? 8 : 4;
+    const bool g16 = p.gt == ElemT::BF16 || p.gt == ElemT::F16;
+    const int64_t TS = g16 ? 256 : 64;   // output tile
     int maxd = -1;
     for (const Op &op : ops)
         if (op.gemm)
@@ -352,9 +356,16 @@ static hipError_t run_grouped(rtri_handle *h, const PlanIn &p, const std::vector
     if (maxd < 0)
         return hipSuccess;
     std::vector<GemmDesc> descs;
-    // tile key (row tile, column tile of the panel) -> entries in order
-    std::map<std::pair<int64_t, int64_t>, std::vector<GroupEntry>> per;
-    std::map<std::pair<int64_t, int64_t>, double> work;
+    // the panel's TS x TS tiles, row tile r and column tile c at r + c * trows;
+    // entries are collected per tile in the order the updates are visited
+    const int64_t trows = (p.m + TS - 1) / TS, tcols = (p.n + TS - 1) / TS;
+    std::vector<int> count((size_t)(trows * tcols), 0);
+    std::vector<double> work((size_t)(trows * tcols), 0.0);
+    struct Raw {
+        int tile;
+        GroupEntry e;
+    };
+    std::vector<Raw> raw;
     bool vec = true;
     bool tp = false, tq = false;
     double flops = 0.0, bytes = 0.0;
@@ -367,32 +378,48 @@ static hipError_t run_grouped(rtri_handle *h, const PlanIn &p, const std::vector
             descs.push_back(g);
             tp = g.tp;
             tq = g.tq;
-            const int64_t w = (int64_t)(16 / es);
+            const int64_t w = (int64_t)(16 / (g16 ? 2 : es));
             vec = vec && (reinterpret_cast<uintptr_t>(g.P) % 16 == 0) && (reinterpret_cast<uintptr_t>(g.Q) % 16 == 0) &&
                   g.ldp % w == 0 && g.ldq % w == 0;
             flops += gemm_flops(g);
-            bytes += gemm_bytes(g, es, es, es);
-            // origin of this update's C inside the panel
+            bytes += g16 ? gemm_bytes(g, 2, 2, 4) : gemm_bytes(g, es, es, es);
+            // origin of this update's C inside the panel (a multiple of 64 in
+            // both directions: leaf boundaries and the vector tiles; of 256 for
+            // the 16-bit tiles, else they are not used)
             const int64_t off = (static_cast<const char *>(g.C) - p.B) / (int64_t)es;
             const int64_t r0 = off % p.ldb, c0 = off / p.ldb;
-            for (int64_t m0 = 0; m0 < g.M; m0 += 64)
-                for (int64_t n0 = 0; n0 < g.N; n0 += 64) {
-                    const auto key = std::make_pair((r0 + m0) / 64, (c0 + n0) / 64);
-                    per[key].push_back(GroupEntry{idx, (int)m0, (int)n0});
-                    work[key] += (double)g.K;
+            if (g16 && (r0 % TS != 0 || c0 % TS != 0 || !g.tp || g.tq))
+                return hipErrorNotSupported;
+            for (int64_t n0 = 0; n0 < g.N; n0 += TS)
+                for (int64_t m0 = 0; m0 < g.M; m0 += TS) {
+                    const int t = (int)((r0 + m0) / TS + ((c0 + n0) / TS) * trows);
+                    raw.push_back(Raw{t, GroupEntry{idx, (int)m0, (int)n0}});
+                    ++count[(size_t)t];
+                    work[(size_t)t] += (double)g.K;
                 }
         }
-    std::vector<std::pair<double, std::pair<int64_t, int64_t>>> order;
-    for (const auto &kv : work)
-        order.push_back({kv.second, kv.first});
-    std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
-    std::vector<GroupEntry> ents;
+    // tiles with updates, most work first; entries grouped per tile, in
+    // visiting order (a counting sort keeps it)
+    std::vector<int> order;
+    for (int t = 0; t < (int)count.size(); ++t)
+        if (count[(size_t)t] > 0)
+            order.push_back(t);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return work[(size_t)x] > work[(size_t)y]; });
+    std::vector<int> start(count.size(), 0);
     std::vector<GroupTile> tiles;
-    for (const auto &o : order) {
-        const auto &v = per[o.second];
-        tiles.push_back(GroupTile{(int)ents.size(), (int)v.size()});
-        ents.insert(ents.end(), v.begin(), v.end());
+    tiles.reserve(order.size());
+    int pos = 0;
+    for (int t : order) {
+        start[(size_t)t] = pos;
+        tiles.push_back(GroupTile{pos, count[(size_t)t]});
+        pos += count[(size_t)t];
     }
+    std::vector<GroupEntry> ents((size_t)pos);
+    for (const Raw &r : raw)
+        ents[(size_t)start[(size_t)r.tile]++] = r.e;
+    if (g16 && !vec)
+        return hipErrorNotSupported;
     const size_t bd = descs.size() * sizeof(GemmDesc), be = ents.size() * sizeof(GroupEntry),
                  bti = tiles.size() * sizeof(GroupTile);
     const size_t oe = (bd + 255) / 256 * 256, ot = oe + (be + 255) / 256 * 256;
@@ -407,11 +434,13 @@ static hipError_t run_grouped(rtri_handle *h, const PlanIn &p, const std::vector
         e = hipMemcpyAsync(h->ws[WS_GROUP], host.data(), host.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
         char *dev = static_cast<char *>(h->ws[WS_GROUP]);
-        e = timed(h, RTRI_KCLASS_GEMM, bt == DType::F64 ? RTRI_F64 : RTRI_F32, flops, bytes, [&] {
-            return launch_gemm_grouped(bt, reinterpret_cast<const GemmDesc *>(dev),
-                                       reinterpret_cast<const GroupEntry *>(dev + oe),
-                                       reinterpret_cast<const GroupTile *>(dev + ot), (int)tiles.size(), tp, tq, vec,
-                                       h->stream);
+        const GemmDesc *dd = reinterpret_cast<const GemmDesc *>(dev);
+        const GroupEntry *de = reinterpret_cast<const GroupEntry *>(dev + oe);
+        const GroupTile *dt = reinterpret_cast<const GroupTile *>(dev + ot);
+        const int dcode = g16 ? dtype_code(p.gt) : bt == DType::F64 ? RTRI_F64 : RTRI_F32;
+        e = timed(h, RTRI_KCLASS_GEMM, dcode, flops, bytes, [&] {
+            return g16 ? launch_gemm16_grouped(p.gt == ElemT::BF16, dd, de, dt, (int)tiles.size(), h->stream)
+                       : launch_gemm_grouped(bt, dd, de, dt, (int)tiles.size(), tp, tq, vec, h->stream);
         });
     }
     if (e != hipSuccess)
@@ -502,7 +531,12 @@ int run_plan(rtri_handle *h, const PlanIn &p)
     // panel from a copy (m x n, leading dimension m), so the leaves may all run
     // first; every update sees the same operands as in recursion order
     const int64_t nvec_all = p.side == RTRI_LEFT ? p.n : p.m;
-    const bool one = !p.solve && p.ext_split == nullptr && trmm_one_launch(h, p.leaf, ka, nvec_all);
+    // (a 16-bit TRMM's updates read the 16-bit original, so it needs no saved
+    // copy and takes this schedule at any width: its updates then run as one
+    // grouped launch of 256x256 tiles)
+    const bool one = !p.solve && p.ext_split == nullptr &&
+                     (trmm_one_launch(h, p.leaf, ka, nvec_all) ||
+                      (p.Bsrc16 != nullptr && h->trmm_leaves != 1 && p.leaf >= 64 && ka > p.leaf));
     // a TRMM whose updates read the 16-bit original needs no saved copy
     const bool save = one && p.Bsrc16 == nullptr;
     if (save) {
@@ -563,7 +597,8 @@ int run_plan(rtri_handle *h, const PlanIn &p)
             // the factor's block is 16-bit; the panel operand too when a TRMM reads the 16-bit original
             const bool panel16 = !p.solve && p.Bsrc16 != nullptr;
             const bool left = p.side == RTRI_LEFT;
-            return launch_gemm16(p.gt == ElemT::BF16, left || panel16, !left || panel16, g, st, h->gemm16_tile);
+            const int t16 = h->gemm16_tile != 0 ? h->gemm16_tile : tuned_tile(h->tune, dtype_code(p.gt), g.M, g.N);
+            return launch_gemm16(p.gt == ElemT::BF16, left || panel16, !left || panel16, g, st, t16);
         }
         const int tile = pick_tile(h, pcode, g.M, g.N);
         Split sp{};
@@ -600,12 +635,18 @@ int run_plan(rtri_handle *h, const PlanIn &p)
         if (e != hipSuccess)
             return hip_fail(h, e);
     }
-    if (one && !g16) {
-        // The updates read only the saved panel, and each 64x64 tile of the
-        // panel gets at most one update per depth, deepest first in recursion
-        // order: one launch in which a workgroup owns a tile and applies its
-        // updates in that order (tiles with the most work first).
-        return run_grouped(h, p, pl.ops, bt) == hipSuccess ? RTRI_OK : hip_fail(h, h->last);
+    if (one && (!g16 || p.Bsrc16 != nullptr)) {
+        // The updates read only the saved panel (or the 16-bit original), and
+        // each tile of the panel gets at most one update per depth, deepest
+        // first in recursion order: one launch in which a workgroup owns a
+        // tile and applies its updates in that order (tiles with the most
+        // work first).  16-bit updates that do not fit the 256x256 tiles run
+        // depth by depth below.
+        const hipError_t e = run_grouped(h, p, pl.ops, bt);
+        if (e == hipSuccess)
+            return RTRI_OK;
+        if (e != hipErrorNotSupported)
+            return hip_fail(h, h->last);
     }
     if (one && !h->profiling) {
         // The updates read only the saved panel and each writes one row block,
@@ -960,7 +1001,8 @@ int rtri_gemm_update(rtri_handle *h, int dtype, int trans_p, int trans_q, int64_
     if (dtype == RTRI_BF16 || dtype == RTRI_F16) {
         // 16-bit P and Q, FP32 C: the matrix-core tiles of the low-precision paths
         hipError_t e = timed(h, RTRI_KCLASS_GEMM, dtype, gemm_flops(g), gemm_bytes(g, 2, 2, 4), [&] {
-            return launch_gemm16(dtype == RTRI_BF16, true, true, g, h->stream, h->gemm16_tile);
+            const int t16 = h->gemm16_tile != 0 ? h->gemm16_tile : tuned_tile(h->tune, dtype, g.M, g.N);
+            return launch_gemm16(dtype == RTRI_BF16, true, true, g, h->stream, t16);
         });
         return e == hipSuccess ? RTRI_OK : hip_fail(h, e);
     }

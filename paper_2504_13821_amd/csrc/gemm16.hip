@@ -374,30 +374,14 @@ struct Loader {
     }
 };
 
+// One 256x256 tile of C at (m0, n0) by the workgroup's eight wavefronts.
+// Ends with a barrier after the last k-step, so the LDS buffers may be
+// reused at once; the epilogue touches only C (each lane the same entries
+// for any tile at the same place).
 template <bool BF, bool P16, bool Q16>
-__global__ __launch_bounds__(NTW, 1) void gemm16w_kernel(GemmDesc g, int tiles_m, int tiles_n)
+__device__ __forceinline__ void wide_tile(const GemmDesc &g, int64_t m0, int64_t n0, unsigned short (*As)[TW * SK],
+                                          unsigned short (*Bs)[TW * SK])
 {
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][TW * SK];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][TW * SK];
-
-    // blocks go round robin over the eight XCDs: give each XCD a contiguous
-    // range of tiles, then walk the tiles in bands of GROUP tile rows so that
-    // blocks in flight together share operand panels in L2
-    const int ntiles = tiles_m * tiles_n;
-    int bid = blockIdx.x;
-    if ((ntiles & 7) == 0) {
-        const int per = ntiles >> 3;
-        bid = (bid & 7) * per + (bid >> 3);
-    }
-    constexpr int GROUP = 4;
-    const int band = bid / (GROUP * tiles_n);
-    const int first_m = band * GROUP;
-    const int gsize = min(tiles_m - first_m, GROUP);
-    const int in_band = bid - band * GROUP * tiles_n;
-    const int tm = first_m + in_band % gsize;
-    const int tn = in_band / gsize;
-
-    const int64_t m0 = (int64_t)tm * TW, n0 = (int64_t)tn * TW;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave & 1, wn = wave >> 1;
@@ -507,6 +491,46 @@ __global__ __launch_bounds__(NTW, 1) void gemm16w_kernel(GemmDesc g, int tiles_m
     }
 }
 
+template <bool BF, bool P16, bool Q16>
+__global__ __launch_bounds__(NTW, 1) void gemm16w_kernel(GemmDesc g, int tiles_m, int tiles_n)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][TW * SK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][TW * SK];
+
+    // blocks go round robin over the eight XCDs: give each XCD a contiguous
+    // range of tiles, then walk the tiles in bands of GROUP tile rows so that
+    // blocks in flight together share operand panels in L2
+    const int ntiles = tiles_m * tiles_n;
+    int bid = blockIdx.x;
+    if ((ntiles & 7) == 0) {
+        const int per = ntiles >> 3;
+        bid = (bid & 7) * per + (bid >> 3);
+    }
+    constexpr int GROUP = 4;
+    const int band = bid / (GROUP * tiles_n);
+    const int first_m = band * GROUP;
+    const int gsize = min(tiles_m - first_m, GROUP);
+    const int in_band = bid - band * GROUP * tiles_n;
+    const int tm = first_m + in_band % gsize;
+    const int tn = in_band / gsize;
+    wide_tile<BF, P16, Q16>(g, (int64_t)tm * TW, (int64_t)tn * TW, As, Bs);
+}
+
+// Several updates in one launch (launch_gemm16_grouped): workgroup b owns a
+// 256x256 tile of the output and applies its entries in order.
+template <bool BF>
+__global__ __launch_bounds__(NTW, 1) void gemm16w_grouped_kernel(const GemmDesc *descs, const GroupEntry *ents,
+                                                                 const GroupTile *tiles)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][TW * SK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][TW * SK];
+    const GroupTile tl = tiles[blockIdx.x];
+    for (int e = tl.first; e < tl.first + tl.count; ++e) {
+        const GroupEntry en = ents[e];
+        wide_tile<BF, true, true>(descs[en.desc], en.m0, en.n0, As, Bs);
+    }
+}
+
 }  // namespace wide
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -567,6 +591,20 @@ hipError_t launch_types(bool p16, bool q16, const GemmDesc &g, hipStream_t st, i
 }
 
 }  // namespace
+
+hipError_t launch_gemm16_grouped(bool bf16, const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles,
+                                 int ntiles, hipStream_t st)
+{
+    if (ntiles <= 0)
+        return hipSuccess;
+    if (bf16)
+        hipLaunchKernelGGL(wide::gemm16w_grouped_kernel<true>, dim3((unsigned)ntiles), dim3(wide::NTW), 0, st, descs,
+                           ents, tiles);
+    else
+        hipLaunchKernelGGL(wide::gemm16w_grouped_kernel<false>, dim3((unsigned)ntiles), dim3(wide::NTW), 0, st,
+                           descs, ents, tiles);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st, int tile)
 {

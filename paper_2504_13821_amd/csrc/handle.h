@@ -13,7 +13,8 @@ struct TuneDB;   // tuned leaf sizes and GEMM tiles (tune.hip)
 void tune_db_free(TuneDB *db);
 // 0 when the database has no rule for the case
 int tuned_leaf(const TuneDB *db, int dtype, bool solve, int64_t ka, int64_t nvec);
-int tuned_tile(const TuneDB *db, int dtype, int64_t M, int64_t N);
+int tuned_tile(const TuneDB *db, int dtype, int64_t M, int64_t N);   // dtype RTRI_BF16 / RTRI_F16: 16-bit tiles
+int tuned_batch_leaf(const TuneDB *db, int dtype);
 int load_tuning_file(rtri_handle *h, const char *path);
 
 struct ProfRec {

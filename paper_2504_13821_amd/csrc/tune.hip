@@ -6,11 +6,14 @@
 // Database (one file per architecture):
 //   {"arch": "gfx950", "version": 1,
 //    "leaf": [{"dtype": "f64", "op": "trsm", "ka_max": 1024, "n_max": 512, "leaf": 32}, ...],
-//    "gemm_tile": [{"dtype": "f64", "m_max": 256, "n_max": 4096, "tile": 2}, ...]}
+//    "gemm_tile": [{"dtype": "f64", "m_max": 256, "n_max": 4096, "tile": 2}, ...,
+//                  {"dtype": "bf16", "m_max": 2048, "n_max": 4096, "tile": 2}, ...],
+//    "batched": [{"dtype": "f64", "leaf": 64}, ...]}
 // A leaf rule covers factor orders up to ka_max and vector counts up to n_max
 // (the smallest covering bucket wins; beyond the largest, the largest applies).
 #include <algorithm>
 #include <cctype>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -34,8 +37,13 @@ struct TuneDB {
         int64_t m_max, n_max;
         int tile;
     };
+    struct Batch {
+        int dtype;
+        int leaf;   // 32 or 64: the batched kernel's leaf
+    };
     std::vector<Leaf> leaf;
-    std::vector<Tile> tile;
+    std::vector<Tile> tile;     // dtype F64 / F32: tiles 1..3; BF16 / F16: 16-bit tiles 1..2
+    std::vector<Batch> batch;
 };
 
 namespace {
@@ -133,8 +141,15 @@ struct JParser {
     }
 };
 
-int dtype_of(const std::string &s) { return s == "f64" ? RTRI_F64 : s == "f32" ? RTRI_F32 : -1; }
-const char *dtype_name(int d) { return d == RTRI_F64 ? "f64" : "f32"; }
+int dtype_of(const std::string &s)
+{
+    return s == "f64" ? RTRI_F64 : s == "f32" ? RTRI_F32 : s == "bf16" ? RTRI_BF16 : s == "f16" ? RTRI_F16 : -1;
+}
+const char *dtype_name(int d)
+{
+    return d == RTRI_F64 ? "f64" : d == RTRI_F32 ? "f32" : d == RTRI_BF16 ? "bf16" : "f16";
+}
+bool is16(int d) { return d == RTRI_BF16 || d == RTRI_F16; }
 
 double num_of(const JVal &o, const char *k, bool &ok)
 {
@@ -168,7 +183,7 @@ bool parse_db(const std::string &text, TuneDB &db)
             TuneDB::Leaf r{dtype_of(str_of(e, "dtype", ok)), str_of(e, "op", ok) == "trsm" ? 1 : 0,
                            (int64_t)num_of(e, "ka_max", ok), (int64_t)num_of(e, "n_max", ok),
                            (int)num_of(e, "leaf", ok)};
-            if (r.dtype < 0 || r.leaf == 0 || !valid_leaf(r.leaf))
+            if (r.dtype < 0 || is16(r.dtype) || r.leaf == 0 || !valid_leaf(r.leaf))
                 ok = false;
             db.leaf.push_back(r);
         }
@@ -177,9 +192,17 @@ bool parse_db(const std::string &text, TuneDB &db)
         for (const JVal &e : tr->second.arr) {
             TuneDB::Tile r{dtype_of(str_of(e, "dtype", ok)), (int64_t)num_of(e, "m_max", ok),
                            (int64_t)num_of(e, "n_max", ok), (int)num_of(e, "tile", ok)};
-            if (r.dtype < 0 || r.tile < 1 || r.tile > 3)
+            if (r.dtype < 0 || r.tile < 1 || r.tile > (is16(r.dtype) ? 2 : 3))
                 ok = false;
             db.tile.push_back(r);
+        }
+    auto br = root.obj.find("batched");
+    if (br != root.obj.end() && br->second.kind == JVal::ARR)
+        for (const JVal &e : br->second.arr) {
+            TuneDB::Batch r{dtype_of(str_of(e, "dtype", ok)), (int)num_of(e, "leaf", ok)};
+            if (r.dtype < 0 || is16(r.dtype) || (r.leaf != 32 && r.leaf != 64))
+                ok = false;
+            db.batch.push_back(r);
         }
     return ok;
 }
@@ -202,6 +225,10 @@ bool write_db(const char *path, const TuneDB &db)
         std::fprintf(f, "%s\n  {\"dtype\": \"%s\", \"m_max\": %lld, \"n_max\": %lld, \"tile\": %d}", i ? "," : "",
                      dtype_name(r.dtype), (long long)r.m_max, (long long)r.n_max, r.tile);
     }
+    std::fprintf(f, "],\n \"batched\": [");
+    for (size_t i = 0; i < db.batch.size(); ++i)
+        std::fprintf(f, "%s\n  {\"dtype\": \"%s\", \"leaf\": %d}", i ? "," : "", dtype_name(db.batch[i].dtype),
+                     db.batch[i].leaf);
     std::fprintf(f, "]}\n");
     return std::fclose(f) == 0;
 }
@@ -258,6 +285,16 @@ int tuned_tile(const TuneDB *db, int dtype, int64_t M, int64_t N)
         if (r->m_max == k->m_max)
             c2.push_back(r);
     return pick_bucket(c2, N, [](const TuneDB::Tile &r) { return r.n_max; })->tile;
+}
+
+int tuned_batch_leaf(const TuneDB *db, int dtype)
+{
+    if (db == nullptr)
+        return 0;
+    for (const auto &r : db->batch)
+        if (r.dtype == dtype)
+            return r.leaf;
+    return 0;
 }
 
 int load_tuning_file(rtri_handle *h, const char *path)
@@ -325,14 +362,168 @@ int rtri_load_tuning(rtri_handle *h, const char *path)
     return load_tuning_file(h, path);
 }
 
+namespace {
+
+// 16-bit GEMM tiles (128x128 / 256x256) per (M = K, N), op(P) = P^T and
+// op(Q) = Q: the layout the library's 16-bit copies are made in
+int tune16(rtri_handle *h, int dtype, int64_t max_order, TuneDB &db)
+{
+    const int64_t max_n = std::min<int64_t>(std::max<int64_t>(max_order, 512), 16384);
+    const int64_t kmax = std::min<int64_t>(std::max<int64_t>(max_order / 2, 256), 8192);
+    void *P = nullptr, *Q = nullptr, *C = nullptr;
+    hipError_t e = hipMalloc(&P, (size_t)kmax * kmax * 2);
+    if (e == hipSuccess)
+        e = hipMalloc(&Q, (size_t)kmax * max_n * 2);
+    if (e == hipSuccess)
+        e = hipMalloc(&C, (size_t)kmax * max_n * 4);
+    // operands' values do not matter for timing: zeros
+    if (e == hipSuccess)
+        e = hipMemsetAsync(P, 0, (size_t)kmax * kmax * 2, h->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(Q, 0, (size_t)kmax * max_n * 2, h->stream);
+    int rc = e == hipSuccess ? RTRI_OK : hip_fail(h, e);
+    const int saved = h->gemm16_tile;
+    for (int64_t mk = 256; mk <= kmax && rc == RTRI_OK; mk *= 2)
+        for (int64_t n : {512, 4096, 16384}) {
+            if (n > max_n || rc != RTRI_OK)
+                continue;
+            int best = 1;
+            float best_ms = 1e30f;
+            for (int tile : {1, 2}) {
+                h->gemm16_tile = tile;
+                int rr = RTRI_OK;
+                const float ms = time_median(h->stream, 3, [] {}, [&] {
+                    rr = rtri_gemm_update(h, dtype, RTRI_TRANS, RTRI_NOTRANS, mk, n, mk, 1.0, P, mk, Q, mk, 0.0, C,
+                                          mk);
+                });
+                if (rr != RTRI_OK) {
+                    rc = rr;
+                    break;
+                }
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = tile;
+                }
+            }
+            db.tile.push_back(TuneDB::Tile{dtype, mk, n, best});
+        }
+    h->gemm16_tile = saved;
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(P);
+    (void)hipFree(Q);
+    (void)hipFree(C);
+    return rc;
+}
+
+// the batched kernel's leaf (32 or 64 rows) on a mix like the batched
+// workload: 200 problems, orders log-uniform on [16, min(1024, max_order)],
+// 1..128 vectors, all on the top-left blocks of one lower factor A (lda lda),
+// right-hand sides in disjoint column ranges of B (ldb)
+int tune_batched(rtri_handle *h, int dtype, int64_t max_order, void *A, int64_t lda, void *B, int64_t ldb,
+                 int64_t bcols, TuneDB &db)
+{
+    const size_t es = dtype == RTRI_F64 ? 8 : 4;
+    std::vector<rtri_batch_entry> ents;
+    uint64_t st = 0x9e3779b97f4a7c15ull;   // fixed host sequence (splitmix64)
+    auto next = [&]() {
+        st += 0x9e3779b97f4a7c15ull;
+        uint64_t z = st;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        return (double)((z ^ (z >> 31)) >> 11) * 0x1.0p-53;
+    };
+    const double lmax = std::log((double)std::min<int64_t>(1024, max_order)), lmin = std::log(16.0);
+    int64_t col = 0;
+    for (int i = 0; i < 200; ++i) {
+        const int64_t m = (int64_t)std::llround(std::exp(lmin + (lmax - lmin) * next()));
+        const int64_t n = 1 + (int64_t)(next() * 128.0);
+        if (col + n > bcols)
+            break;
+        rtri_batch_entry b{};
+        b.op = 0;
+        b.side = RTRI_LEFT;
+        b.uplo = RTRI_LOWER;
+        b.trans = RTRI_NOTRANS;
+        b.diag = RTRI_NONUNIT;
+        b.m = m;
+        b.n = n;
+        b.alpha = 1.0;
+        b.A = A;
+        b.lda = lda;
+        b.B = static_cast<char *>(B) + (size_t)col * ldb * es;
+        b.ldb = ldb;
+        ents.push_back(b);
+        col += n;
+    }
+    TuneDB *old = h->tune;
+    TuneDB probe;
+    h->tune = &probe;
+    int best = 64, rc = RTRI_OK;
+    float best_ms = 1e30f;
+    for (int leaf : {32, 64}) {
+        probe.batch.assign(1, TuneDB::Batch{dtype, leaf});
+        rtri_batch_plan *plan = nullptr;
+        int bad = -1;
+        rc = rtri_batch_plan_create(h, dtype, (int)ents.size(), ents.data(), &plan, &bad);
+        if (rc != RTRI_OK)
+            break;
+        int rr = RTRI_OK;
+        const float ms = time_median(
+            h->stream, 3,
+            [&] {
+                if (rr == RTRI_OK)
+                    rr = rtri_synth_fill(h, dtype, 0, 77, 9, 1, max_order, bcols, 0.0, B, ldb);
+            },
+            [&] {
+                if (rr == RTRI_OK)
+                    rr = rtri_batch_plan_run(plan);
+            });
+        (void)rtri_batch_plan_destroy(plan);
+        if (rr != RTRI_OK) {
+            rc = rr;
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = leaf;
+        }
+    }
+    h->tune = old;
+    if (rc == RTRI_OK)
+        db.batch.push_back(TuneDB::Batch{dtype, best});
+    return rc;
+}
+
+}  // namespace
+
 int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
 {
     if (!handle_valid(h))
         return RTRI_ERR_HANDLE;
-    if (dtype != RTRI_F64 && dtype != RTRI_F32)
+    if (dtype != RTRI_F64 && dtype != RTRI_F32 && dtype != RTRI_BF16 && dtype != RTRI_F16)
         return -2;
     if (max_order < 256)
         return -3;
+    if (dtype == RTRI_BF16 || dtype == RTRI_F16) {
+        TuneDB db;
+        if (h->tune != nullptr) {   // keep every other rule
+            db = *h->tune;
+            db.tile.erase(std::remove_if(db.tile.begin(), db.tile.end(),
+                                         [&](const TuneDB::Tile &r) { return r.dtype == dtype; }),
+                          db.tile.end());
+        }
+        const int rc = tune16(h, dtype, max_order, db);
+        if (rc != RTRI_OK)
+            return rc;   // the handle keeps the rules it had
+        TuneDB *fresh = new (std::nothrow) TuneDB(db);
+        if (fresh == nullptr)
+            return RTRI_ERR_NOMEM;
+        delete h->tune;
+        h->tune = fresh;
+        if (db_path != nullptr && !write_db(db_path, db))
+            return RTRI_ERR_INVALID;
+        return RTRI_OK;
+    }
     const size_t es = dtype == RTRI_F64 ? 8 : 4;
     const int64_t max_n = std::min<int64_t>(max_order, 16384);
     void *A = nullptr, *B = nullptr, *C = nullptr;
@@ -359,6 +550,10 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
         for (const auto &r : old->tile)
             if (r.dtype != dtype)
                 db.tile.push_back(r);
+    if (old != nullptr)
+        for (const auto &r : old->batch)
+            if (r.dtype != dtype)
+                db.batch.push_back(r);
     int rc = RTRI_OK;
     // leaf size per (op, order, vector count)
     for (int64_t ka = 256; ka <= max_order && rc == RTRI_OK; ka *= 2) {
@@ -435,6 +630,15 @@ int rtri_tune(rtri_handle *h, int dtype, int64_t max_order, const char *db_path)
         }
     }
     h->gemm_tile = saved_tile;
+    // the batched kernel's leaf, with the single-call rules found above
+    if (rc == RTRI_OK) {
+        const int saved_leaf = dtype == RTRI_F64 ? h->leaf_f64 : h->leaf_f32;
+        (dtype == RTRI_F64 ? h->leaf_f64 : h->leaf_f32) = 0;
+        rc = rtri_synth_fill(h, dtype, 1, 77, 5, 1, max_order, max_order, (double)max_order, A, max_order);
+        if (rc == RTRI_OK)
+            rc = tune_batched(h, dtype, max_order, A, max_order, B, max_order, max_n, db);
+        (dtype == RTRI_F64 ? h->leaf_f64 : h->leaf_f32) = saved_leaf;
+    }
     (void)hipStreamSynchronize(h->stream);
     (void)hipFree(A);
     (void)hipFree(B);

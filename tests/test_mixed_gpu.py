@@ -251,24 +251,37 @@ def test_mixed_8192_classes(rt, h, orc, gemm, c):
 def test_trmm_ex_full_tiles(rt, h, orc, dt, side, uplo, trans):
     """Orders and leading dimensions that are multiples of 8 with updates of at
     least 128 x 128 (the 16-bit GEMM's 16-byte full-tile loads with both
-    operands 16-bit, the path of the benchmark's TRMM at 8192): both leaf
-    schedules bit-identical, against the oracle on the rounded inputs, and bit
-    for bit on small integers (every partial sum an integer below 2^24)."""
-    m, n = (1024, 512) if side == "L" else (512, 1024)
-    ka = m if side == "L" else n
-    say("trmm_ex full tiles", dt, side, uplo, trans)
-    g = G(6, ka)
-    A = rounded(synth.tri(ka, uplo, g, "stress"), dt)
-    B = rounded(synth.dense(m, n, g), dt)
-    out = []
-    for mode in (1, 2):
-        h.set_option(rt.OPT_TRMM_LEAVES, mode)
-        out.append(_run_trmm_ex(rt, h, side, uplo, trans, "N", 0.5, A, B, dt))
-    h.set_option(rt.OPT_TRMM_LEAVES, 0)
-    assert np.array_equal(out[0], out[1])
-    e = orc.trmm_eta(side, uplo, trans, "N", 0.5, A, B, out[0])
-    assert e <= 7 * np.sqrt(ka) * 2.0 ** -24, e
-    Ai = synth.exact_tri(ka, uplo, g, offdiag=(-1, 0, 1), diag=(1.0, -1.0, 2.0, -2.0))
-    Bi = synth.exact_dense(m, n, g)
-    Ci = _run_trmm_ex(rt, h, side, uplo, trans, "N", 1.0, Ai, Bi, dt)
-    assert np.array_equal(Ci, orc.trmm(side, uplo, trans, "N", 1.0, Ai, Bi))
+    operands 16-bit, the path of the benchmark's TRMM at 8192), with 64- and
+    256-row leaves: one launch per leaf (each update its own launch) and every
+    leaf in one launch (side L with 256-row leaves: all updates in one grouped
+    launch of 256x256 tiles, another MFMA shape, so the two agree to within
+    the bound rather than bit for bit); against the oracle on the rounded
+    inputs, and bit for bit on small integers (every partial sum an integer
+    below 2^24)."""
+    for leaf, ka in ((64, 1024), (256, 2048)):
+        m, n = (ka, 512) if side == "L" else (512, ka)
+        say("trmm_ex full tiles", dt, side, uplo, trans, leaf, ka)
+        h.set_option(rt.OPT_LEAF_F32, leaf)
+        g = G(6, ka)
+        A = rounded(synth.tri(ka, uplo, g, "stress"), dt)
+        B = rounded(synth.dense(m, n, g), dt)
+        out = []
+        for mode in (1, 2):
+            h.set_option(rt.OPT_TRMM_LEAVES, mode)
+            out.append(_run_trmm_ex(rt, h, side, uplo, trans, "N", 0.5, A, B, dt))
+        h.set_option(rt.OPT_TRMM_LEAVES, 0)
+        bound = 7 * np.sqrt(ka) * 2.0 ** -24
+        for X in out:
+            e = orc.trmm_eta(side, uplo, trans, "N", 0.5, A, B, X)
+            assert e <= bound, (leaf, e)
+        if leaf == 64:
+            assert np.array_equal(out[0], out[1])
+        Ai = synth.exact_tri(ka, uplo, g, offdiag=(-1, 0, 1), diag=(1.0, -1.0, 2.0, -2.0))
+        Bi = synth.exact_dense(m, n, g)
+        want = orc.trmm(side, uplo, trans, "N", 1.0, Ai, Bi)
+        for mode in (1, 2):
+            h.set_option(rt.OPT_TRMM_LEAVES, mode)
+            Ci = _run_trmm_ex(rt, h, side, uplo, trans, "N", 1.0, Ai, Bi, dt)
+            assert np.array_equal(Ci, want), (leaf, mode)
+        h.set_option(rt.OPT_TRMM_LEAVES, 0)
+    h.set_option(rt.OPT_LEAF_F32, 0)
