@@ -55,9 +55,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true", help="only the headline step")
-    ap.add_argument("--extras", default="mixed,rect256,solvers,trmm16,batched,serving",
+    ap.add_argument("--extras", default="mixed,rect256,solvers,small,trmm16,batched,serving",
                     help="comma-separated extra sections to run (default: all but 'vendor', the rocBLAS "
-                         "comparison, which runs only when named)")
+                         "comparison, and 'residual', the residual product alone, which run only when named)")
     ap.add_argument("--serve-requests", type=int, default=5000)
     ap.add_argument("--serve-rates", default="0.1,0.25,0.5,0.75,0.9,1.0,1.2",
                     help="open-loop arrival rates as fractions of the measured saturation throughput")
@@ -206,6 +206,19 @@ def main():
             cpu_check_solvers(out["solvers"], sample_s)
         del sample_s
         progress("solvers done")
+    if "residual" in extras:   # the residual product alone (part of "mixed" too)
+        import synth
+        mm = 8192
+        Ad = rt.synth_fill(h, 1, synth.SEED, synth.W_MIXED, 1, torch.empty((mm, mm), dtype=torch.float64,
+                                                                           device="cuda").t(), param=45.0)
+        B0 = rt.synth_fill(h, 0, synth.SEED, synth.W_MIXED, 2, torch.empty((mm, mm), dtype=torch.float64,
+                                                                           device="cuda").t())
+        out["residual_product"] = bench_residual_product(rt, torch, h, Ad, B0)
+        del Ad, B0
+        progress("residual done")
+    if "small" in extras:
+        out["small"] = bench_small(rt, torch, h)
+        progress("small done")
     if "trmm16" in extras:
         out["trmm16"], sample16 = bench_trmm16(rt, torch, h)
         if not args.no_cpu:
@@ -516,6 +529,49 @@ def cpu_check_rect256(res, samples):
         row["trmm"]["eta_oracle"] = oracle.trmm_eta("L", "L", "N", "N", 1.0, smp["A"], smp["B"], smp["trmm"])
 
 
+def bench_small(rt, torch, h, reps=100):
+    """Calls whose kernels take microseconds, where host planning and launches
+    dominate: the small parity case (FP64 L/L/N/N, m = n = 512) and the
+    narrow panel (FP32, m = 16384, n = 256), each as a plain call and as a
+    call plan (the same kernels captured once in a HIP graph and replayed).
+    Latency = host wall time from the call to the end of a stream
+    synchronisation, median of reps (B restored outside the timed region)."""
+    import time
+    import synth
+    res = {"workload": "FP64 L/L/N/N m=n=512 (base recipe); FP32 L/L/N/N m=16384, n=256", "cases": []}
+    for (label, td, mm, nn) in (("fp64_512", torch.float64, 512, 512), ("fp32_16384x256", torch.float32, 16384, 256)):
+        dcode = 0 if td == torch.float64 else 1
+        Ad = rt.synth_fill(h, 1, synth.SEED, synth.W_SWEEP, 21, torch.empty((mm, mm), dtype=td, device="cuda").t(),
+                           param=float(mm))
+        B0 = rt.synth_fill(h, 0, synth.SEED, synth.W_SWEEP, 22, torch.empty((nn, mm), dtype=td, device="cuda").t())
+        Bd = B0.clone()
+        case = {"case": label, "m": mm, "n": nn}
+        h.set_option(rt.OPT_TRMM_LEAVES, 1)   # the schedule a plan captures, for both ways of calling
+        for op in ("trsm", "trmm"):
+            fn = rt.trsm if op == "trsm" else rt.trmm
+            plan = rt.CallPlan(h, op, "L", "L", "N", "N", 1.0, Ad, Bd)
+            out = {}
+            for way, call in (("plain", lambda: fn(h, "L", "L", "N", "N", 1.0, Ad, Bd)), ("plan", plan.run)):
+                ts = []
+                for r in range(reps + 3):
+                    Bd.copy_(B0)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    call()
+                    torch.cuda.synchronize()
+                    if r >= 3:
+                        ts.append((time.perf_counter() - t0) * 1e3)
+                ms = float(np.median(ts))
+                out[way] = {"latency_ms": round(ms, 4), "tflops": round(mm * mm * nn / (ms * 1e-3) / 1e12, 3)}
+            out["speedup"] = round(out["plain"]["latency_ms"] / out["plan"]["latency_ms"], 3)
+            case[op] = out
+            plan.close()
+        h.set_option(rt.OPT_TRMM_LEAVES, 0)
+        res["cases"].append(case)
+        del Ad, B0, Bd
+    return res
+
+
 def bench_solvers(rt, torch, h, n=16384, ns=8):
     """The operations built on the recursive TRSM, FP64, order n = 16384:
     TRTRI (lower, non-unit; n^3/3 flops), POTRS (lower Cholesky-type factor,
@@ -668,13 +724,24 @@ def bench_batched(rt, torch, h, count=4096):
         peak = 78.6e12 if dt == "f64" else 157.3e12
         bound_ms = sum(max(mm * mm * nn / peak, es * (mm * (mm + 1) / 2 + 2 * mm * nn) / 8e12)
                        for (mm, nn, u) in shapes) * 1e3
+        # the longest problem alone: its chain of dependent leaves and updates
+        # bounds the whole batch from below as well
+        big = max(range(len(shapes)), key=lambda i: shapes[i][0] ** 2 * shapes[i][1])
         for op in ("trsm", "trmm"):
             plan = rt.BatchPlan(h, [(op, "L", u, "N", "N", 1.0, As[i], Bs[i]) for i, (mm, nn, u) in enumerate(shapes)])
             plan.run()
             torch.cuda.synchronize()
             t = _event_ms(torch, plan.run, reps=5)
+            one = rt.BatchPlan(h, [(op, "L", shapes[big][2], "N", "N", 1.0, As[big], Bs[big])])
+            one.run()
+            torch.cuda.synchronize()
+            t_chain = _event_ms(torch, one.run, reps=5)
+            one.close()
+            lb = max(bound_ms, t_chain)
             res[f"{op}_{dt}"] = {"ms": round(t, 4), "tflops": round(flops / (t * 1e-3) / 1e12, 3),
                                  "bound_ms": round(bound_ms, 4), "frac_of_bound": round(bound_ms / t, 3),
+                                 "longest_problem_alone_ms": round(t_chain, 4),
+                                 "frac_of_max_bound_and_longest": round(lb / t, 3),
                                  "chunks": plan.chunks(), "algorithmic_GB": round(byts / 1e9, 3)}
             plan.close()
         del As, Bs

@@ -81,9 +81,13 @@ enum {
     RTRI_OPT_GEMM_TILE = 3,  /* GEMM tile choice: 0 = automatic, 1 = 128x128 (4 wavefronts), 2 = 64x64,
                                 3 = 128x128 (8 wavefronts) */
     RTRI_OPT_TRMM_LEAVES = 4, /* TRMM leaf schedule (leaves of 64 rows and more): 0 = automatic (all in one
-                                launch below 8192 vectors), 1 = one launch per leaf, in recursion order,
-                                2 = the panel is copied to workspace, all leaves run in one launch, then the
-                                GEMM updates read the copy.  Both give bit-identical results. */
+                                launch below 8192 vectors, and always for rtri_trmm_ex), 1 = one launch per
+                                leaf, in recursion order, each GEMM update its own launch, 2 = the panel is
+                                copied to workspace (rtri_trmm_ex reads its 16-bit original instead), all
+                                leaves run in one launch, then all GEMM updates in one grouped launch that
+                                reads the copy (a workgroup owns a tile of the panel and applies its updates
+                                deepest first).  The two agree bit for bit where they use the same tiles (FP64
+                                / FP32 updates that do not split K); otherwise to within rounding. */
     RTRI_OPT_GEMM16_TILE = 5, /* 16-bit GEMM tiles: 0 = automatic, 1 = 128x128 (4 wavefronts, 16x16x32 MFMA),
                                 2 = 256x256 (8 wavefronts, 32x32x16 MFMA) wherever both operands are
                                 k-contiguous and 16-byte aligned (else 128x128).  Results may differ in the
@@ -155,6 +159,30 @@ int rtri_ztrsm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t 
                const void *A, int64_t lda, void *B, int64_t ldb);
 int rtri_ztrmm(rtri_handle *h, int side, int uplo, int trans, int diag, int64_t m, int64_t n, const double *alpha,
                const void *A, int64_t lda, void *B, int64_t ldb);
+
+/* ---- call plans: one TRSM / TRMM planned once, replayed as a HIP graph ----- */
+
+/* Plan one FP64 / FP32 TRSM (op 0, eqs. (3)/(4)) or TRMM (op 1, eqs. (1)/(2))
+ * on fixed operands: the recursion is planned once and every kernel of the
+ * call (pack pass, leaves, GEMM updates) is captured in a HIP graph with
+ * workspace the plan owns (packed blocks and one split-K region), so a replay
+ * (rtri_call_plan_run) is one graph launch on the handle's current stream,
+ * with no host planning and no allocation.  Each replay computes what the
+ * plain call (rtri_dtrsm ...) computes with the handle's options at creation
+ * (a TRMM: with RTRI_OPT_TRMM_LEAVES = 1, the schedule a plan captures), bit
+ * for bit, reading A and the current contents of B.  The handle must not have
+ * a profile open.
+ * Argument codes: -2 op, -3 dtype, then the codes of rtri_dtrsm shifted by
+ * three (-4 side ... -14 ldb), -15 out NULL.  Blocking (captures and
+ * instantiates the graph). */
+typedef struct rtri_call_plan rtri_call_plan;
+int rtri_call_plan_create(rtri_handle *h, int op, int dtype, int side, int uplo, int trans, int diag, int64_t m,
+                          int64_t n, double alpha, const void *A, int64_t lda, void *B, int64_t ldb,
+                          rtri_call_plan **plan);
+/* Replay (asynchronous on the handle's stream). */
+int rtri_call_plan_run(rtri_call_plan *plan);
+/* Free a plan (waits for the handle's stream first). */
+int rtri_call_plan_destroy(rtri_call_plan *plan);
 
 /* FP64 TRMM from exact INT8 matrix-core products (the refined solve's residual
  * product, available on its own): B := alpha op(A) B (LEFT) or alpha B op(A)
@@ -401,13 +429,17 @@ int rtri_factor_destroy(rtri_factor *f);
 int rtri_synth_fill(rtri_handle *h, int dtype, int kind, uint64_t seed, uint32_t stream, uint64_t id, int64_t m,
                     int64_t n, double param, void *X, int64_t ldx);
 
-/* Tuning: time leaf sizes (16 / 32 / 64 / 128 / 256) for TRSM and TRMM at
- * factor orders 256, 512, ... up to max_order and 64 / 512 / 4096 / 16384
- * vectors (at most max_order), and the GEMM tile (128x128 or 64x64) at M = K =
- * 64 ... min(max_order / 2, 8192) and the same vector counts, on synthetic
- * inputs in device memory the call allocates and
- * frees; keep the winners in the handle (rules for the other dtype are kept)
- * and, if db_path != NULL, write them there as JSON.  Blocking.  Options set
+/* Tuning.  dtype RTRI_F64 / RTRI_F32: time leaf sizes (16 / 32 / 64 / 128 /
+ * 256) for TRSM and TRMM at factor orders 256, 512, ... up to max_order and 64
+ * / 512 / 4096 / 16384 vectors (at most max_order); the GEMM tile (128x128 of
+ * 4 or 8 wavefronts, or 64x64) at M = K = 64 ... min(max_order / 2, 8192) and
+ * the same vector counts; and the batched kernel's leaf (32 or 64 rows) on a
+ * mix of 200 problems of orders log-uniform on [16, min(1024, max_order)] and
+ * 1..128 vectors.  dtype RTRI_BF16 / RTRI_F16: the 16-bit GEMM tile (128x128
+ * or 256x256) at M = K = 256 ... min(max_order / 2, 8192) and 512 / 4096 /
+ * 16384 vectors.  Synthetic inputs in device memory the call allocates and
+ * frees; the winners are kept in the handle (rules for other dtypes are kept)
+ * and, if db_path != NULL, written there as JSON.  Blocking.  Options set
  * with rtri_set_option still take precedence.  Codes: -2 dtype, -3 max_order
  * < 256; RTRI_ERR_INVALID if the file cannot be written.  If a timed run
  * fails, its code is returned and the handle keeps the rules it had. */
@@ -523,7 +555,10 @@ typedef struct {
     int64_t submitted, completed, failed;
     int64_t launches, batched_launches, batched_requests;
     int64_t factor_hits, factor_misses, evictions;
-    int64_t hbm_in_use, hbm_peak;
+    int64_t hbm_in_use, hbm_peak;   /* device memory the server holds (factors and their factor objects'
+                                       parts, right-hand sides, slot workspace), now and at most; admission
+                                       also counts reservations for work not yet done (workspace growth,
+                                       factor-object parts, upper bounds), which these exclude */
     double useful_flops;    /* sum of ka^2 * vectors over completed requests */
 } rtri_server_counters;
 

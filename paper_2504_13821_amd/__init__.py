@@ -65,6 +65,10 @@ rtri_dtrmm = _sig("rtri_dtrmm", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp,
 rtri_strmm = _sig("rtri_strmm", _int, *_OPARGS, ctypes.c_float, _vp, _i64, _vp, _i64)
 rtri_dtrsm_noalloc = _sig("rtri_dtrsm_noalloc", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
 rtri_dtrmm_ozaki = _sig("rtri_dtrmm_ozaki", _int, *_OPARGS, ctypes.c_double, _vp, _i64, _vp, _i64)
+rtri_call_plan_create = _sig("rtri_call_plan_create", _int, _vp, _int, _int, _int, _int, _int, _int, _i64, _i64,
+                             ctypes.c_double, _vp, _i64, _vp, _i64, ctypes.POINTER(_vp))
+rtri_call_plan_run = _sig("rtri_call_plan_run", _int, _vp)
+rtri_call_plan_destroy = _sig("rtri_call_plan_destroy", _int, _vp)
 rtri_trmm_ex = _sig("rtri_trmm_ex", _int, *_OPARGS, ctypes.c_float, _vp, _int, _i64, _vp, _int, _i64, _vp, _int, _i64)
 
 
@@ -329,6 +333,45 @@ def trsm_noalloc(h: Handle, side, uplo, trans, diag, alpha, A, B):
                             ldb)
     check(rc, "rtri_dtrsm_noalloc")
     return B
+
+
+class CallPlan:
+    """One TRSM ('trsm') or TRMM ('trmm') on fixed tensors A and B (FP64 or FP32), planned once and
+    captured in a HIP graph; run() replays it on the handle's stream (rtri_call_plan_*)."""
+
+    def __init__(self, h: Handle, op, side, uplo, trans, diag, alpha, A, B):
+        if B.dim() != 2:
+            raise ValueError("B must be 2-D")
+        m, n = B.shape
+        ka = _factor_order(side, B)
+        _need_shape(A, "A", ka, ka)
+        _same_device(A=A, B=B)
+        lda, ldb = _colmajor(A, "A"), _colmajor(B, "B")
+        if A.dtype != B.dtype:
+            raise TypeError("A and B must have the same dtype")
+        dt = {torch.float64: F64, torch.float32: F32}.get(B.dtype)
+        if dt is None:
+            raise TypeError(f"unsupported dtype {B.dtype}")
+        p = _vp()
+        check(rtri_call_plan_create(h.ptr, {"trsm": 0, "trmm": 1}[op], dt, *codes(side, uplo, trans, diag), m, n,
+                                    alpha, A.data_ptr(), lda, B.data_ptr(), ldb, ctypes.byref(p)),
+              "rtri_call_plan_create")
+        self._p = p
+        self._keep = (A, B)
+
+    def run(self):
+        check(rtri_call_plan_run(self._p), "rtri_call_plan_run")
+
+    def close(self):
+        if self._p:
+            rtri_call_plan_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def trmm_ozaki(h: Handle, side, uplo, trans, diag, alpha, A, B):

@@ -205,9 +205,12 @@ __device__ __forceinline__ void run_leaf(const BInst &in, const BOp &op, int v0,
     __syncthreads();
 }
 
+// Three workgroups per CU (12 wavefronts): every op of an item is a chain of
+// dependent memory round trips, so more resident items hide more latency
+// (measured on the 4096-problem FP64 mix: 2.73 -> 2.57 ms).
 template <typename T, int NB>
-__global__ __launch_bounds__(NT) void batched_kernel(const BInst *insts, const BItem *items, int nitems,
-                                                     const BOp *ops, unsigned *counter)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void batched_kernel(
+    const BInst *insts, const BItem *items, int nitems, const BOp *ops, unsigned *counter)
 {
     __shared__ __attribute__((aligned(16))) T smem[Smem<T, NB>::N];
     __shared__ double Dg[NB == 64 ? 4 * 16 * 17 : 1];

@@ -80,7 +80,8 @@ struct rtri_server {
     std::deque<Req> pending;
     std::unordered_map<uint64_t, Factor> factors;
     std::vector<rtri_completion> done;
-    int64_t used = 0;
+    int64_t used = 0;       // held + reserved: what admission checks against the budget
+    int64_t reserved = 0;   // reservations of work not yet done (workspace growth, factor-object parts)
     uint64_t next_ticket = 1, use_clock = 0;
     int64_t outstanding = 0;
     rtri_server_counters st{};
@@ -310,11 +311,12 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool 
     f->refs += 1;
     f->last_use = ++s->use_clock;
     s->used += (int64_t)(q.rhs_bytes + ws_extra + part_extra);
+    s->reserved += (int64_t)(ws_extra + part_extra);
     w.ws_extra += ws_extra;
     w.part_extra += part_extra;
     w.tables = tables;
-    s->st.hbm_in_use = s->used;
-    s->st.hbm_peak = std::max(s->st.hbm_peak, s->used);
+    s->st.hbm_in_use = s->used - s->reserved;
+    s->st.hbm_peak = std::max(s->st.hbm_peak, s->st.hbm_in_use);
     w.reqs.push_back(q);
     return true;
 }
@@ -494,8 +496,9 @@ void worker(rtri_server *s, int idx)
                 s->st.batched_launches += 1;
                 s->st.batched_requests += (int64_t)w.reqs.size();
             }
-            s->st.hbm_in_use = s->used;
-            s->st.hbm_peak = std::max(s->st.hbm_peak, s->used);
+            s->reserved -= (int64_t)(w.ws_extra + w.part_extra);
+            s->st.hbm_in_use = s->used - s->reserved;
+            s->st.hbm_peak = std::max(s->st.hbm_peak, s->st.hbm_in_use);
             s->done.insert(s->done.end(), out.begin(), out.end());
             s->outstanding -= (int64_t)w.reqs.size();
         }

@@ -311,3 +311,21 @@ def test_ozaki_order_limit(rt, handle):
     overflow (K > 2^17) before any device work."""
     big = (1 << 17) + 1
     assert rt.rtri_dtrmm_ozaki(handle, 0, 0, 0, 0, big, 1, 1.0, FAKE, big, FAKE, big) == rt.ERR_UNSUPPORTED
+
+
+def test_call_plan_argument_codes(rt, handle):
+    """rtri_call_plan_create rejects bad arguments before any device work: op,
+    dtype, then the BLAS-list codes shifted by three, and a NULL out."""
+    p = ctypes.c_void_p()
+    make = rt.rtri_call_plan_create
+    ok = (0, 0, 0, 0, 8, 4, 1.0, FAKE, 8, FAKE, 8)
+    assert make(handle, 2, rt.F64, *ok, ctypes.byref(p)) == -2
+    assert make(handle, 0, rt.BF16, *ok, ctypes.byref(p)) == -3
+    assert make(handle, 0, rt.F64, 2, 0, 0, 0, 8, 4, 1.0, FAKE, 8, FAKE, 8, ctypes.byref(p)) == -4
+    assert make(handle, 1, rt.F32, 0, 0, 0, 0, -1, 4, 1.0, FAKE, 8, FAKE, 8, ctypes.byref(p)) == -8
+    assert make(handle, 0, rt.F64, 0, 0, 0, 0, 8, 4, 1.0, FAKE, 7, FAKE, 8, ctypes.byref(p)) == -12
+    assert make(handle, 0, rt.F64, 0, 0, 0, 0, 8, 4, 1.0, FAKE, 8, FAKE, 7, ctypes.byref(p)) == -14
+    assert make(handle, 0, rt.F64, *ok, None) == -15
+    assert make(None, 0, rt.F64, *ok, ctypes.byref(p)) == rt.ERR_HANDLE
+    assert rt.rtri_call_plan_run(None) == rt.ERR_HANDLE
+    assert rt.rtri_call_plan_destroy(None) == -1
