@@ -374,13 +374,21 @@ struct Loader {
     }
 };
 
-// One 256x256 tile of C at (m0, n0) by the workgroup's eight wavefronts.
-// Ends with a barrier after the last k-step, so the LDS buffers may be
-// reused at once; the epilogue touches only C (each lane the same entries
-// for any tile at the same place).
-template <bool BF, bool P16, bool Q16>
-__device__ __forceinline__ void wide_tile(const GemmDesc &g, int64_t m0, int64_t n0, unsigned short (*As)[TW * SK],
-                                          unsigned short (*Bs)[TW * SK])
+// The operand tiles of one K segment: op(P) rows from P (= P^T: row m at
+// P + m*ldp) and op(Q) columns from Q (column n at Q + n*ldq), K values.
+struct WSeg {
+    const void *P, *Q;
+    int64_t ldp, ldq, K;
+};
+
+// The K loop of one 256x256 output tile by the workgroup's eight wavefronts:
+// acc += op(P) op(Q) summed over a sequence of K segments, nk k-steps in all.
+// next(sg) fills in the next segment; it is called in order, once per
+// segment, when the segment's first k-step is loaded.  Ends with a barrier
+// after the last k-step, so the LDS buffers may be reused at once.
+template <bool BF, bool P16, bool Q16, class Next>
+__device__ __forceinline__ void wide_k(Next &&next, int nk, int rlim_m, int rlim_n, float16_t (&acc)[4][2],
+                                       unsigned short (*As)[TW * SK], unsigned short (*Bs)[TW * SK])
 {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -389,31 +397,23 @@ __device__ __forceinline__ void wide_tile(const GemmDesc &g, int64_t m0, int64_t
 
     using PT = typename std::conditional<P16, unsigned short, float>::type;
     using QT = typename std::conditional<Q16, unsigned short, float>::type;
-    const PT *Pt = static_cast<const PT *>(g.P) + m0 * g.ldp;   // op(P) = P^T: row m at P + m*ldp
-    const QT *Qt = static_cast<const QT *>(g.Q) + n0 * g.ldq;   // column n at Q + n*ldq
-    const int rlim_m = (int)min<int64_t>(TW, g.M - m0);
-    const int rlim_n = (int)min<int64_t>(TW, g.N - n0);
     const bool full_mn = rlim_m == TW && rlim_n == TW;
 
     Loader<P16, BF> la;
     Loader<Q16, BF> lb;
-    float16_t acc[4][2];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                acc[i][j][r] = 0.0f;
-
-    const int64_t K = g.K;
-    const int nk = (int)((K + BK - 1) / BK);
+    WSeg sg{};
+    int sg_first = 0, sg_nk = 0;   // the segment being loaded: its first k-step and k-steps
     auto load_step = [&](int kt) {
-        const int64_t k0 = (int64_t)kt * BK;
-        const int klim = (int)min<int64_t>(BK, K - k0);
+        while (kt - sg_first >= sg_nk) {
+            sg_first += sg_nk;
+            next(sg);
+            sg_nk = (int)((sg.K + BK - 1) / BK);
+        }
+        const int64_t k0 = (int64_t)(kt - sg_first) * BK;
+        const int klim = (int)min<int64_t>(BK, sg.K - k0);
         const bool full = full_mn && klim == BK;
-        la.load(Pt + k0, g.ldp, tid, rlim_m, klim, full);
-        lb.load(Qt + k0, g.ldq, tid, rlim_n, klim, full);
+        la.load(static_cast<const PT *>(sg.P) + k0, sg.ldp, tid, rlim_m, klim, full);
+        lb.load(static_cast<const QT *>(sg.Q) + k0, sg.ldq, tid, rlim_n, klim, full);
     };
 
     if (nk > 0) {
@@ -449,35 +449,55 @@ __device__ __forceinline__ void wide_tile(const GemmDesc &g, int64_t m0, int64_t
         }
         __syncthreads();
     }
+}
 
-    float *C = static_cast<float *>(g.C);
-    const int64_t ldc = g.ldc;
-    const float beta = (float)g.beta, s = (float)g.s;
-    const bool zero_beta = g.beta == 0.0;
-    const bool cvec = full_mn && (reinterpret_cast<uintptr_t>(C) & 15) == 0 && (ldc & 3) == 0;
+// C = beta C + s acc on a 256x256 tile at C (column-major, ldc) of which
+// rlim_m x rlim_n entries exist; beta == 0: C is not read.  Each lane writes
+// four consecutive rows of a column per 16 bytes (one access when aligned);
+// the C reads of a row block are issued together, ahead of its stores.
+__device__ __forceinline__ void wide_epilogue(const float16_t (&acc)[4][2], float *C, int64_t ldc, int rlim_m,
+                                              int rlim_n, double beta_d, double s_d)
+{
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int lr = lane & 31, lh = lane >> 5;
+    const float beta = (float)beta_d, s = (float)s_d;
+    const bool zero_beta = beta_d == 0.0;
+    const bool cvec = rlim_m == TW && rlim_n == TW && (reinterpret_cast<uintptr_t>(C) & 15) == 0 && (ldc & 3) == 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+        if (cvec) {
+            float4_t o[2][4];
+            if (!zero_beta) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int cl = wn * 64 + j * 32 + lr;
-            float *cp = C + m0 + (n0 + cl) * ldc;
+                for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int rb = wm * 128 + i * 32 + 8 * q + 4 * lh;   // four consecutive rows rb..rb+3
-                if (cvec) {
+                    for (int q = 0; q < 4; ++q)
+                        o[j][q] = *reinterpret_cast<const float4_t *>(
+                            C + (wm * 128 + i * 32 + 8 * q + 4 * lh) + (wn * 64 + j * 32 + lr) * ldc);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
                     float4_t v;
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        v[r] = s * acc[i][j][4 * q + r];
-                    float4_t *c4 = reinterpret_cast<float4_t *>(cp + rb);
-                    if (!zero_beta) {
-                        const float4_t o = *c4;
+                        v[r] = zero_beta ? s * acc[i][j][4 * q + r] : fmat(beta, o[j][q][r], s * acc[i][j][4 * q + r]);
+                    *reinterpret_cast<float4_t *>(C + (wm * 128 + i * 32 + 8 * q + 4 * lh) +
+                                                  (wn * 64 + j * 32 + lr) * ldc) = v;
+                }
+        } else {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            v[r] = fmat(beta, o[r], v[r]);
-                    }
-                    *c4 = v;
-                } else if (cl < rlim_n) {
+            for (int j = 0; j < 2; ++j) {
+                const int cl = wn * 64 + j * 32 + lr;
+                if (cl >= rlim_n)
+                    continue;
+                float *cp = C + cl * ldc;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int rb = wm * 128 + i * 32 + 8 * q + 4 * lh;   // rows rb..rb+3
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         if (rb + r < rlim_m) {
@@ -489,6 +509,31 @@ __device__ __forceinline__ void wide_tile(const GemmDesc &g, int64_t m0, int64_t
             }
         }
     }
+}
+
+// One update on the 256x256 tile of C at (m0, n0).
+template <bool BF, bool P16, bool Q16>
+__device__ __forceinline__ void wide_tile(const GemmDesc &g, int64_t m0, int64_t n0, unsigned short (*As)[TW * SK],
+                                          unsigned short (*Bs)[TW * SK])
+{
+    using PT = typename std::conditional<P16, unsigned short, float>::type;
+    using QT = typename std::conditional<Q16, unsigned short, float>::type;
+    const int rlim_m = (int)min<int64_t>(TW, g.M - m0);
+    const int rlim_n = (int)min<int64_t>(TW, g.N - n0);
+    float16_t acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                acc[i][j][r] = 0.0f;
+    auto next = [&](WSeg &sg) {
+        sg = WSeg{static_cast<const PT *>(g.P) + m0 * g.ldp, static_cast<const QT *>(g.Q) + n0 * g.ldq, g.ldp, g.ldq,
+                  g.K};
+    };
+    wide_k<BF, P16, Q16>(next, (int)((g.K + BK - 1) / BK), rlim_m, rlim_n, acc, As, Bs);
+    wide_epilogue(acc, static_cast<float *>(g.C) + m0 + n0 * g.ldc, g.ldc, rlim_m, rlim_n, g.beta, g.s);
 }
 
 template <bool BF, bool P16, bool Q16>
@@ -517,7 +562,13 @@ __global__ __launch_bounds__(NTW, 1) void gemm16w_kernel(GemmDesc g, int tiles_m
 }
 
 // Several updates in one launch (launch_gemm16_grouped): workgroup b owns a
-// 256x256 tile of the output and applies its entries in order.
+// 256x256 tile of the output and applies its entries in order.  When every
+// entry adds to the tile (beta = 1) with the same scale s, and all address the
+// same C entries, the entries' products go into one accumulator, their K
+// segments walked back to back, and C is read and written once:
+//     C := C + s * sum_e op(P_e) op(Q_e)
+// (rounded once instead of once per entry).  Otherwise each entry is applied
+// as a launch of that update alone would.
 template <bool BF>
 __global__ __launch_bounds__(NTW, 1) void gemm16w_grouped_kernel(const GemmDesc *descs, const GroupEntry *ents,
                                                                  const GroupTile *tiles)
@@ -525,6 +576,42 @@ __global__ __launch_bounds__(NTW, 1) void gemm16w_grouped_kernel(const GemmDesc 
     __shared__ __attribute__((aligned(16))) unsigned short As[2][TW * SK];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][TW * SK];
     const GroupTile tl = tiles[blockIdx.x];
+    if (tl.count <= 0)
+        return;
+    const GroupEntry e0 = ents[tl.first];
+    const GemmDesc &g0 = descs[e0.desc];
+    float *c0 = static_cast<float *>(g0.C) + e0.m0 + (int64_t)e0.n0 * g0.ldc;
+    const int rm = (int)min<int64_t>(TW, g0.M - e0.m0), rn = (int)min<int64_t>(TW, g0.N - e0.n0);
+    bool merge = g0.beta == 1.0;
+    int64_t nk = 0;
+    for (int e = tl.first; e < tl.first + tl.count; ++e) {
+        const GroupEntry en = ents[e];
+        const GemmDesc &g = descs[en.desc];
+        merge = merge && g.beta == 1.0 && g.s == g0.s && g.ldc == g0.ldc &&
+                static_cast<float *>(g.C) + en.m0 + (int64_t)en.n0 * g.ldc == c0 &&
+                min<int64_t>(TW, g.M - en.m0) == rm && min<int64_t>(TW, g.N - en.n0) == rn;
+        nk += (g.K + BK - 1) / BK;
+    }
+    if (merge) {
+        float16_t acc[4][2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    acc[i][j][r] = 0.0f;
+        int idx = tl.first;
+        auto next = [&](WSeg &sg) {
+            const GroupEntry en = ents[idx++];
+            const GemmDesc &g = descs[en.desc];
+            sg = WSeg{static_cast<const unsigned short *>(g.P) + en.m0 * g.ldp,
+                      static_cast<const unsigned short *>(g.Q) + en.n0 * g.ldq, g.ldp, g.ldq, g.K};
+        };
+        wide_k<BF, true, true>(next, (int)nk, rm, rn, acc, As, Bs);
+        wide_epilogue(acc, c0, g0.ldc, rm, rn, 1.0, g0.s);
+        return;
+    }
     for (int e = tl.first; e < tl.first + tl.count; ++e) {
         const GroupEntry en = ents[e];
         wide_tile<BF, true, true>(descs[en.desc], en.m0, en.n0, As, Bs);

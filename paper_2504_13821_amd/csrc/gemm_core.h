@@ -296,6 +296,31 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
     const int lane_e = te % 64, wave_e = te / 64;
     const int wm_e = wave_e % WM, wn_e = wave_e / WM, lc_e = lane_e % 16, lg_e = lane_e / 16;
     const T beta = T(g.beta), s = T(g.s);
+    // A lane with few blocks (64x64 tiles) reads all its C blocks before the
+    // first store: one memory round trip instead of one per block (the stores
+    // could alias the later reads as far as the compiler knows, so it would
+    // not reorder them itself).  Same arithmetic as the general loop below.
+    if constexpr (FM * FN <= 4) {
+        if (cvec && full_mn && g.beta != 0.0 && !(CPF && pre)) {
+            V cb[FM][FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    cb[i][j] = ld4(cptr(i, j, wm_e, wn_e, lc_e, lg_e));
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    V v = s * acc[i][j];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        v[r] = fmat(beta, cb[i][j][r], v[r]);
+                    st4(cptr(i, j, wm_e, wn_e, lc_e, lg_e), v);
+                }
+            return;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
