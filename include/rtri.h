@@ -90,8 +90,11 @@ enum {
                                 / FP32 updates that do not split K); otherwise to within rounding. */
     RTRI_OPT_GEMM16_TILE = 5, /* 16-bit GEMM tiles: 0 = automatic, 1 = 128x128 (4 wavefronts, 16x16x32 MFMA),
                                 2 = 256x256 (8 wavefronts, 32x32x16 MFMA) wherever both operands are
-                                k-contiguous and 16-byte aligned (else 128x128).  Results may differ in the
-                                last bits between the two (another accumulation order). */
+                                k-contiguous and 16-byte aligned (else 128x128), with both operands 16-bit,
+                                M and N multiples of 256 and K of 32 loaded straight into LDS; 3 = the
+                                256x256 tiles with register-staged loads only (bit for bit the results of 2).
+                                Results may differ in the last bits between 1 and 2 (another accumulation
+                                order). */
     RTRI_OPT_RESIDUAL = 6     /* residual product of the refined solves (rtri_dtrsm_mixed, factor solves):
                                 0 = FP64 matrix cores (the FP64 recursive TRMM), 1 = exact INT8 products
                                 (the method of rtri_dtrmm_ozaki; op(A)'s residue planes made once per call,

@@ -110,13 +110,18 @@ hipError_t launch_gemm_grouped(DType t, const GemmDesc *descs, const GroupEntry 
                                int ntiles, bool tp, bool tq, bool vec, hipStream_t st);
 // 16-bit GEMM: P is 16-bit when p16 (else FP32), Q when q16 (at least one of
 // them); C is FP32.  tile: 0 automatic, 1 128x128 tiles, 2 256x256 tiles where
-// both operands are k-contiguous (tp && !tq) and 16-byte aligned
+// both operands are k-contiguous (tp && !tq) and 16-byte aligned (loaded
+// straight into LDS when both are 16-bit, M and N are multiples of 256 and K
+// of 32), 3 the 256x256 tiles with register-staged loads only
 hipError_t launch_gemm16(bool bf16, bool p16, bool q16, const GemmDesc &g, hipStream_t st, int tile = 0);
 // 16-bit updates in one launch, as launch_gemm_grouped with 256x256 tiles:
 // every update 16-bit in both operands, tp && !tq, 16-byte aligned operands
-// with leading dimensions a multiple of 8, tile origins multiples of 256
-hipError_t launch_gemm16_grouped(bool bf16, const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles,
-                                 int ntiles, hipStream_t st);
+// with leading dimensions a multiple of 8, tile origins multiples of 256.
+// tiles_dma: full tiles whose entries all have beta = 1, one scale s and K a
+// multiple of 32 (one accumulator, operands loaded straight into LDS); tiles:
+// the rest (a launch of its own after the first)
+hipError_t launch_gemm16_grouped(bool bf16, const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles_dma,
+                                 int n_dma, const GroupTile *tiles, int ntiles, hipStream_t st);
 // pack diagonal blocks read from A of type src into packed triangles of type dst
 hipError_t launch_pack(ElemT src, DType dst, bool solve, int nbmax, const PackDesc &p, hipStream_t st);
 hipError_t launch_leaf(DType t, bool solve, int nbmax, const LeafDesc &l, hipStream_t st);

@@ -398,22 +398,43 @@ static hipError_t run_grouped(rtri_handle *h, const PlanIn &p, const std::vector
                     work[(size_t)t] += (double)g.K;
                 }
         }
-    // tiles with updates, most work first; entries grouped per tile, in
-    // visiting order (a counting sort keeps it)
+    // 16-bit tiles whose updates can be loaded straight into LDS and share one
+    // accumulator: full 256x256 tiles, every update adding (beta = 1) with
+    // one scale, K a multiple of 32 (launch_gemm16_grouped)
+    std::vector<char> dma(count.size(), g16 && h->gemm16_tile != 3 ? 1 : 0);
+    std::vector<double> scale(count.size(), 0.0);
+    std::vector<char> seen(count.size(), 0);
+    if (g16)
+        for (const Raw &r : raw) {
+            const GemmDesc &g = descs[(size_t)r.e.desc];
+            const size_t t = (size_t)r.tile;
+            if (!seen[t]) {
+                seen[t] = 1;
+                scale[t] = g.s;
+            }
+            if (g.M - r.e.m0 < TS || g.N - r.e.n0 < TS || g.K % 32 != 0 || g.beta != 1.0 || g.s != scale[t])
+                dma[t] = 0;
+        }
+    // tiles with updates, most work first (the direct-to-LDS ones before the
+    // rest); entries grouped per tile, in visiting order (a counting sort keeps it)
     std::vector<int> order;
     for (int t = 0; t < (int)count.size(); ++t)
         if (count[(size_t)t] > 0)
             order.push_back(t);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return work[(size_t)x] > work[(size_t)y]; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        if (dma[(size_t)x] != dma[(size_t)y])
+            return dma[(size_t)x] > dma[(size_t)y];
+        return work[(size_t)x] > work[(size_t)y];
+    });
     std::vector<int> start(count.size(), 0);
     std::vector<GroupTile> tiles;
     tiles.reserve(order.size());
-    int pos = 0;
+    int pos = 0, n_dma = 0;
     for (int t : order) {
         start[(size_t)t] = pos;
         tiles.push_back(GroupTile{pos, count[(size_t)t]});
         pos += count[(size_t)t];
+        n_dma += dma[(size_t)t];
     }
     std::vector<GroupEntry> ents((size_t)pos);
     for (const Raw &r : raw)
@@ -439,7 +460,8 @@ static hipError_t run_grouped(rtri_handle *h, const PlanIn &p, const std::vector
         const GroupTile *dt = reinterpret_cast<const GroupTile *>(dev + ot);
         const int dcode = g16 ? dtype_code(p.gt) : bt == DType::F64 ? RTRI_F64 : RTRI_F32;
         e = timed(h, RTRI_KCLASS_GEMM, dcode, flops, bytes, [&] {
-            return g16 ? launch_gemm16_grouped(p.gt == ElemT::BF16, dd, de, dt, (int)tiles.size(), h->stream)
+            return g16 ? launch_gemm16_grouped(p.gt == ElemT::BF16, dd, de, dt, n_dma, dt + n_dma,
+                                               (int)tiles.size() - n_dma, h->stream)
                        : launch_gemm_grouped(bt, dd, de, dt, (int)tiles.size(), tp, tq, vec, h->stream);
         });
     }
@@ -831,7 +853,7 @@ int rtri_set_option(rtri_handle *h, int option, int64_t value)
         h->trmm_leaves = (int)value;
         return RTRI_OK;
     case RTRI_OPT_GEMM16_TILE:
-        if (value < 0 || value > 2) return -3;
+        if (value < 0 || value > 3) return -3;
         h->gemm16_tile = (int)value;
         return RTRI_OK;
     case RTRI_OPT_RESIDUAL:

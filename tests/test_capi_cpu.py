@@ -95,7 +95,7 @@ def test_options(rt, handle):
         assert rt.rtri_set_option(handle, rt.OPT_TRMM_LEAVES, mode) == rt.OK
         assert rt.rtri_get_option(handle, rt.OPT_TRMM_LEAVES, ctypes.byref(v)) == rt.OK and v.value == mode
     assert rt.rtri_set_option(handle, rt.OPT_TRMM_LEAVES, 3) == -3
-    for opt, top in ((rt.OPT_GEMM16_TILE, 2), (rt.OPT_RESIDUAL, 1)):
+    for opt, top in ((rt.OPT_GEMM16_TILE, 3), (rt.OPT_RESIDUAL, 1)):
         assert rt.rtri_get_option(handle, opt, ctypes.byref(v)) == rt.OK and v.value == 0
         for mode in range(top + 1):
             assert rt.rtri_set_option(handle, opt, mode) == rt.OK

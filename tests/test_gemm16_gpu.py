@@ -60,7 +60,7 @@ SHAPES = [(1, 1, 1), (37, 50, 19), (256, 256, 64), (300, 520, 77), (777, 515, 13
 @pytest.mark.parametrize("t16", ["bf16", "f16"])
 @pytest.mark.parametrize("tp,tq", [("T", "N"), ("N", "N"), ("T", "T"), ("N", "T")])
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("tile", [0, 1, 2])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3])
 def test_gemm16_random(rt, h, t16, tp, tq, shape, tile):
     M, N, K = shape
     if max(shape) > 1024 and (tp, tq) != ("T", "N"):
@@ -103,3 +103,30 @@ def test_gemm16_tiles_exact_integers(rt, h, t16, shape):
         outs.append(rt.to_host(Cd).astype(np.float64))
     assert np.array_equal(outs[0], want)
     assert np.array_equal(outs[1], want)
+
+
+@pytest.mark.parametrize("t16", ["bf16", "f16"])
+@pytest.mark.parametrize("shape", [(256, 256, 32), (512, 768, 96), (1024, 1024, 1024), (768, 512, 4000)])
+def test_gemm16_direct_lds_matches_register_staged(rt, h, t16, shape):
+    """Full 256x256 tiles with both operands 16-bit and K a multiple of 32 go
+    through the direct-to-LDS pipeline (OPT_GEMM16_TILE 2); 3 keeps the
+    register-staged loads.  Same MFMA sequence per accumulator, so the results
+    agree bit for bit (and meet the bound)."""
+    M, N, K = shape
+    say("gemm16 direct-to-LDS vs register-staged", t16, shape)
+    g = synth.rng(synth.W_TEST, 7301, M, N, K)
+    P, Q, C = _operands(M, N, K, "T", "N", g, "rand", t16)
+    td = torch.bfloat16 if t16 == "bf16" else torch.float16
+    out = []
+    for tile in (2, 3):
+        h.set_option(rt.OPT_GEMM16_TILE, tile)
+        Pd, Qd, Cd = _dev(rt, P, td), _dev(rt, Q, td), _dev(rt, C, torch.float32)
+        rt.gemm_update(h, "T", "N", 0.5, Pd, Qd, 1.25, Cd)
+        torch.cuda.synchronize()
+        out.append(rt.to_host(Cd).astype(np.float64))
+    h.set_option(rt.OPT_GEMM16_TILE, 0)
+    assert np.array_equal(out[0], out[1])
+    want = 1.25 * C + 0.5 * (P.T @ Q)
+    bound = 2 * (K + 2) * 2.0 ** -24 * (1.25 * np.abs(C) + 0.5 * (np.abs(P.T) @ np.abs(Q)))
+    assert np.all(np.abs(out[0] - want) <= bound)
+

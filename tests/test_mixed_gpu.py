@@ -285,3 +285,63 @@ def test_trmm_ex_full_tiles(rt, h, orc, dt, side, uplo, trans):
             assert np.array_equal(Ci, want), (leaf, mode)
         h.set_option(rt.OPT_TRMM_LEAVES, 0)
     h.set_option(rt.OPT_LEAF_F32, 0)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+@pytest.mark.parametrize("uplo,trans,diag", [("L", "N", "N"), ("L", "T", "U"), ("U", "N", "U"), ("U", "T", "N")])
+def test_trmm_ex_grouped_ragged(rt, h, orc, dt, uplo, trans, diag):
+    """Side L with 256-row leaves and every leaf in one launch: the updates of
+    an output tile go into one FP32 accumulator when their origins fall on
+    256-row boundaries (else the updates run depth by depth).  Orders and
+    panel widths that are not multiples of 256 (ragged last tiles, ragged K
+    segments for the upper / transposed factors), against the oracle on the
+    rounded inputs (both schedules) within the FP32-accumulation bound, and
+    bit for bit on small integers."""
+    ka, n = 1500, 700
+    say("trmm_ex grouped ragged", dt, uplo, trans, diag)
+    h.set_option(rt.OPT_LEAF_F32, 256)
+    g = G(7, ka, ord(uplo), ord(trans), ord(diag))
+    A = rounded(synth.tri(ka, uplo, g, "unit" if diag == "U" else "stress"), dt)
+    B = rounded(synth.dense(ka, n, g), dt)
+    out = []
+    for mode in (1, 2):
+        h.set_option(rt.OPT_TRMM_LEAVES, mode)
+        out.append(_run_trmm_ex(rt, h, "L", uplo, trans, diag, -0.75, A, B, dt))
+    h.set_option(rt.OPT_TRMM_LEAVES, 0)
+    bound = 7 * np.sqrt(ka) * 2.0 ** -24
+    for X in out:
+        e = orc.trmm_eta("L", uplo, trans, diag, -0.75, A, B, X)
+        assert e <= bound, e
+    Ai = synth.exact_tri(ka, uplo, g, offdiag=(-1, 0, 1), diag=(1.0, -1.0, 2.0, -2.0))
+    Bi = synth.exact_dense(ka, n, g)
+    want = orc.trmm("L", uplo, trans, diag, 1.0, Ai, Bi)
+    h.set_option(rt.OPT_TRMM_LEAVES, 2)
+    Ci = _run_trmm_ex(rt, h, "L", uplo, trans, diag, 1.0, Ai, Bi, dt)
+    h.set_option(rt.OPT_TRMM_LEAVES, 0)
+    h.set_option(rt.OPT_LEAF_F32, 0)
+    assert np.array_equal(Ci, want)
+
+
+@pytest.mark.parametrize("dt", ["bf16", "f16"])
+def test_trmm_ex_grouped_direct_lds(rt, h, orc, dt):
+    """The grouped launch of a 16-bit TRMM whose tiles are all full (order and
+    width multiples of 256): the direct-to-LDS kernel (OPT_GEMM16_TILE 0)
+    against the register-staged grouped kernel (3), bit for bit (same
+    segments in the same order, same MFMA sequence), and against the oracle."""
+    ka, n = 2048, 768
+    say("trmm_ex grouped direct-to-LDS", dt)
+    h.set_option(rt.OPT_LEAF_F32, 256)
+    h.set_option(rt.OPT_TRMM_LEAVES, 2)
+    g = G(8, ka)
+    A = rounded(synth.tri(ka, "L", g, "stress"), dt)
+    B = rounded(synth.dense(ka, n, g), dt)
+    out = []
+    for tile in (0, 3):
+        h.set_option(rt.OPT_GEMM16_TILE, tile)
+        out.append(_run_trmm_ex(rt, h, "L", "L", "N", "N", 1.5, A, B, dt))
+    h.set_option(rt.OPT_GEMM16_TILE, 0)
+    h.set_option(rt.OPT_TRMM_LEAVES, 0)
+    h.set_option(rt.OPT_LEAF_F32, 0)
+    assert np.array_equal(out[0], out[1])
+    assert orc.trmm_eta("L", "L", "N", "N", 1.5, A, B, out[0]) <= 7 * np.sqrt(ka) * 2.0 ** -24
+
