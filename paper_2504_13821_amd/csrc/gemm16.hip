@@ -25,6 +25,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "dma_tile.h"
 
 namespace rtri {
 
@@ -626,120 +627,22 @@ __global__ __launch_bounds__(NTW, 1) void gemm16w_grouped_kernel(const GemmDesc 
 }
 
 // ---------------------------------------------------------------------------
-// Direct-to-LDS pipeline for full 256x256 tiles whose operands are both 16-bit
-// (k-contiguous, 16-byte aligned, leading dimensions multiples of 8) with K a
-// multiple of 32 in every segment.  The operand tiles go from memory straight
-// into LDS (global_load_lds, 16 bytes per lane: a wavefront's instruction
-// fills 1 KB of LDS, lane l at byte 16 l), with no register stage and no LDS
-// store instructions, in four LDS stages of BKD = 32 k: the loads of k-step
-// kt + 3 are issued while step kt multiplies.  A stage row is 64 bytes (four
-// 16-byte chunks); chunk c of row r sits at slot c ^ ((r >> 1) & 3), so the
-// fragment reads of 8 consecutive rows fall into distinct bank groups (each
-// lane loads the chunk that belongs at its slot).  Past the last k-step the
-// last stage is loaded again into the stage just freed (never read), so
-// every step waits for the same count of loads; the compiler's wait-count
-// pass then keeps the three younger stages in flight (with a count that
-// depended on the step, or a segment switch inside the pipeline, it waited
-// for all of them).  Each step reads all its fragments first, then
-// multiplies.  Several K segments into one accumulator run one pipeline
-// each, one after another.
-constexpr int BKD = 32;
-constexpr int STG = TW * BKD;   // elements per operand and stage
+// Full 256x256 tiles whose operands are both 16-bit (k-contiguous, 16-byte
+// aligned, leading dimensions multiples of 8) with K a multiple of 32 in every
+// segment: the operands go straight into LDS (dma_tile.h), 32 values of k
+// per step.  Same MFMA sequence per accumulator as the register-staged
+// tiles above.
+constexpr int BKD = dma::LINE / 2;   // k per step
 
-typedef __attribute__((address_space(3))) void lds_t;
-typedef const __attribute__((address_space(1))) void gbl_t;
-
-// acc += op(P) op(Q) over nk k-steps of BKD for one K segment: P, Q the tile
-// origins (op(P) rows, op(Q) columns, k contiguous), ldp, ldq their leading
-// dimensions.  S0..S3: the four stages (A at [0, STG), B at [STG, 2 STG)),
-// distinct LDS arrays so the compiler's wait-count pass can tell them apart.
-// Steps go in straight-line groups of four (a remainder of up to three
-// after them).  Ends with no load in flight and a barrier, so the stages may
-// be refilled at once.
 template <bool BF>
-__device__ __forceinline__ void dma_seg(const unsigned short *P, const unsigned short *Q, int64_t ldp, int64_t ldq,
-                                        int nk, float16_t (&acc)[4][2], unsigned short *S0, unsigned short *S1,
-                                        unsigned short *S2, unsigned short *S3)
+__device__ __forceinline__ void dma_seg16(const unsigned short *P, const unsigned short *Q, int64_t ldp, int64_t ldq,
+                                          int nk, float16_t (&acc)[4][2], char *S0, char *S1, char *S2, char *S3)
 {
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int wm = wave & 1, wn = wave >> 1;
-    const int lr = lane & 31, lh = lane >> 5;
-    if (nk <= 0)
-        return;
-    // this lane's loads: instruction i fills LDS rows 16 (8 i + wave) ..+15,
-    // lane l row 16 (8 i + wave) + l / 4, slot l % 4
-    const unsigned short *pa[2], *pb[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int row = 16 * (8 * i + wave) + (lane >> 2);
-        const int chk = ((lane & 3) ^ ((row >> 1) & 3)) * 8;
-        pa[i] = P + row * ldp + chk;
-        pb[i] = Q + row * ldq + chk;
-    }
-    auto issue = [&](int kt, unsigned short *S) {
-        const int64_t k0 = (int64_t)kt * BKD;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int seg = 8 * i + wave;
-            __builtin_amdgcn_global_load_lds((gbl_t *)(pa[i] + k0), (lds_t *)(S + seg * 512), 16, 0, 0);
-            __builtin_amdgcn_global_load_lds((gbl_t *)(pb[i] + k0), (lds_t *)(S + STG + seg * 512), 16, 0, 0);
-        }
-    };
-    const int sw = (lr >> 1) & 3;
-    auto compute = [&](const unsigned short *S) {
-        u16x8 fa[BKD / 16][4], fb[BKD / 16][2];
-#pragma unroll
-        for (int ks = 0; ks < BKD / 16; ++ks) {
-            const int ch = ((2 * ks + lh) ^ sw) * 8;
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                fa[ks][i] = *reinterpret_cast<const u16x8 *>(S + (wm * 128 + i * 32 + lr) * BKD + ch);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                fb[ks][j] = *reinterpret_cast<const u16x8 *>(S + STG + (wn * 64 + j * 32 + lr) * BKD + ch);
-        }
-#pragma unroll
-        for (int ks = 0; ks < BKD / 16; ++ks)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = mfma32<BF>(fa[ks][i], fb[ks][j], acc[i][j]);
-        __builtin_amdgcn_sched_group_barrier(0x100, (BKD / 16) * 6, 0);   // the LDS reads first
-        __builtin_amdgcn_sched_group_barrier(0x008, (BKD / 16) * 8, 0);   // then the MFMAs
-    };
-    // step kt: its stage has landed (the three younger ones may be in flight),
-    // every wavefront is done with the stage refilled now (step kt - 1's)
-    auto step = [&](int kt, const unsigned short *Sc, unsigned short *Sn) {
-        __builtin_amdgcn_s_waitcnt(0x0F78);   // vmcnt(8): 4 loads per stage per lane
-        __builtin_amdgcn_s_barrier();
-        issue(min(kt + 3, nk - 1), Sn);
-        compute(Sc);
-    };
-    issue(0, S0);
-    issue(min(1, nk - 1), S1);
-    issue(min(2, nk - 1), S2);
-    const int n4 = nk & ~3;
-    for (int kt = 0; kt < n4; kt += 4) {
-        step(kt, S0, S3);
-        step(kt + 1, S1, S0);
-        step(kt + 2, S2, S1);
-        step(kt + 3, S3, S2);
-    }
-    if (n4 < nk)
-        step(n4, S0, S3);
-    if (n4 + 1 < nk)
-        step(n4 + 1, S1, S0);
-    if (n4 + 2 < nk)
-        step(n4 + 2, S2, S1);
-    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): no LDS write in flight past this point
-    __builtin_amdgcn_s_barrier();
+    dma::k_seg(reinterpret_cast<const char *>(P), reinterpret_cast<const char *>(Q), 2 * ldp, 2 * ldq, nk, acc, S0,
+               S1, S2, S3, [](dma::v4i a, dma::v4i b, float16_t c) {
+                   return mfma32<BF>(__builtin_bit_cast(u16x8, a), __builtin_bit_cast(u16x8, b), c);
+               });
 }
-
-#define RTRI_DMA_STAGES                                                                  \
-    __shared__ __attribute__((aligned(1024))) unsigned short S0[2 * STG], S1[2 * STG];     \
-    __shared__ __attribute__((aligned(1024))) unsigned short S2[2 * STG], S3[2 * STG]
 
 // one update of full tiles: M, N multiples of 256, K a multiple of BKD
 template <bool BF>
@@ -757,9 +660,9 @@ __global__ __launch_bounds__(NTW, 1) void gemm16d_kernel(GemmDesc g, int tiles_m
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 acc[i][j][r] = 0.0f;
-    dma_seg<BF>(static_cast<const unsigned short *>(g.P) + m0 * g.ldp,
-                static_cast<const unsigned short *>(g.Q) + n0 * g.ldq, g.ldp, g.ldq, (int)(g.K / BKD), acc, S0, S1,
-                S2, S3);
+    dma_seg16<BF>(static_cast<const unsigned short *>(g.P) + m0 * g.ldp,
+                  static_cast<const unsigned short *>(g.Q) + n0 * g.ldq, g.ldp, g.ldq, (int)(g.K / BKD), acc, S0, S1,
+                  S2, S3);
     wide_epilogue(acc, static_cast<float *>(g.C) + m0 + n0 * g.ldc, g.ldc, TW, TW, g.beta, g.s);
 }
 
@@ -787,9 +690,9 @@ __global__ __launch_bounds__(NTW, 1) void gemm16d_grouped_kernel(const GemmDesc 
     for (int e = tl.first; e < tl.first + tl.count; ++e) {
         const GroupEntry en = ents[e];
         const GemmDesc &g = descs[en.desc];
-        dma_seg<BF>(static_cast<const unsigned short *>(g.P) + en.m0 * g.ldp,
-                    static_cast<const unsigned short *>(g.Q) + en.n0 * g.ldq, g.ldp, g.ldq, (int)(g.K / BKD), acc, S0,
-                    S1, S2, S3);
+        dma_seg16<BF>(static_cast<const unsigned short *>(g.P) + en.m0 * g.ldp,
+                      static_cast<const unsigned short *>(g.Q) + en.n0 * g.ldq, g.ldp, g.ldq, (int)(g.K / BKD), acc,
+                      S0, S1, S2, S3);
     }
     wide_epilogue(acc, static_cast<float *>(g0.C) + e0.m0 + (int64_t)e0.n0 * g0.ldc, g0.ldc, TW, TW, 1.0, g0.s);
 }

@@ -33,6 +33,7 @@
 #include <cmath>
 #include <cstdint>
 
+#include "dma_tile.h"
 #include "handle.h"
 
 namespace rtri {
@@ -195,8 +196,7 @@ typedef int int16v __attribute__((ext_vector_type(16)));
 
 constexpr int NTG = 512;
 constexpr int TG = 256;              // tile lines (rows and columns of Z)
-constexpr int BKB = 128;             // k bytes per stage
-constexpr int SKB = BKB + 16;        // padded LDS line (bytes)
+constexpr int BKB = 128;             // plane lines are zero-padded to a multiple of BKB bytes
 
 struct GemmI8Desc {
     const int8_t *P, *Q;             // planes, lines k-contiguous, ldk bytes per line
@@ -215,8 +215,7 @@ __device__ __forceinline__ int16v mfma_i8(int4_t a, int4_t b, int16v c)
 
 __global__ __launch_bounds__(NTG, 1) void gemm_i8_kernel(GemmI8Desc g, int tiles_m, int tiles_n)
 {
-    __shared__ __attribute__((aligned(16))) int8_t As[2][TG * SKB];
-    __shared__ __attribute__((aligned(16))) int8_t Bs[2][TG * SKB];
+    RTRI_DMA_STAGES;
 
     const int ntiles = tiles_m * tiles_n;
     int bid = blockIdx.x;
@@ -234,41 +233,20 @@ __global__ __launch_bounds__(NTG, 1) void gemm_i8_kernel(GemmI8Desc g, int tiles
     const int t = blockIdx.y;   // modulus
 
     const int64_t m0 = (int64_t)tm * TG, n0 = (int64_t)tn * TG;
-    // k range of this tile (the rest of the product is zero)
+    // k range of this tile (the rest of the product is zero), in steps of
+    // dma::LINE bytes; the planes' lines are zero-padded to a multiple of
+    // BKB, so the last step may run past K
     int64_t kb = 0, ke = g.K;
     if (g.tri == 1) ke = min<int64_t>(g.K, m0 + TG);
     if (g.tri == 2) kb = m0;
     if (g.tri == 3) ke = min<int64_t>(g.K, n0 + TG);
     if (g.tri == 4) kb = n0;
-    const int sb = (int)(kb / BKB), se = (int)((ke + BKB - 1) / BKB);
+    const int64_t sb = kb / dma::LINE, se = (ke + dma::LINE - 1) / dma::LINE;
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave & 1, wn = wave >> 1;
     const int lr = lane & 31, lh = lane >> 5;
-
-    const int8_t *Pt = g.P + (int64_t)t * g.pplane + m0 * g.ldk;
-    const int8_t *Qt = g.Q + (int64_t)t * g.qplane + n0 * g.ldk;
-    int4_t ra[4], rb[4];
-    auto load = [&](int s) {
-        const int64_t k0 = (int64_t)s * BKB;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int e = v * NTG + tid;
-            const int line = e >> 3, kc = (e & 7) * 16;
-            ra[v] = *reinterpret_cast<const int4_t *>(Pt + line * g.ldk + k0 + kc);
-            rb[v] = *reinterpret_cast<const int4_t *>(Qt + line * g.ldk + k0 + kc);
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int e = v * NTG + tid;
-            const int line = e >> 3, kc = (e & 7) * 16;
-            *reinterpret_cast<int4_t *>(&As[buf][line * SKB + kc]) = ra[v];
-            *reinterpret_cast<int4_t *>(&Bs[buf][line * SKB + kc]) = rb[v];
-        }
-    };
 
     int16v acc[4][2];
 #pragma unroll
@@ -278,37 +256,11 @@ __global__ __launch_bounds__(NTG, 1) void gemm_i8_kernel(GemmI8Desc g, int tiles
 #pragma unroll
             for (int r = 0; r < 16; ++r)
                 acc[i][j][r] = 0;
-
-    if (sb < se) {
-        load(sb);
-        store(0);
-    }
-    __syncthreads();
-    for (int s = sb; s < se; ++s) {
-        const int buf = (s - sb) & 1;
-        if (s + 1 < se)
-            load(s + 1);
-        const int8_t *as = &As[buf][(wm * 128 + lr) * SKB + 16 * lh];
-        const int8_t *bs = &Bs[buf][(wn * 64 + lr) * SKB + 16 * lh];
-#pragma unroll
-        for (int ks = 0; ks < BKB / 32; ++ks) {
-            int4_t fa[4], fb[2];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                fa[i] = *reinterpret_cast<const int4_t *>(as + i * 32 * SKB + ks * 32);
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-                fb[j] = *reinterpret_cast<const int4_t *>(bs + j * 32 * SKB + ks * 32);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = mfma_i8(fa[i], fb[j], acc[i][j]);
-        }
-        if (s + 1 < se)
-            store(buf ^ 1);
-        __syncthreads();
-    }
+    const int64_t k0 = sb * dma::LINE;
+    dma::k_seg(reinterpret_cast<const char *>(g.P + (int64_t)t * g.pplane + m0 * g.ldk + k0),
+               reinterpret_cast<const char *>(g.Q + (int64_t)t * g.qplane + n0 * g.ldk + k0), g.ldk, g.ldk,
+               (int)(se - sb), acc, S0, S1, S2, S3,
+               [](dma::v4i a, dma::v4i b, int16v c) { return mfma_i8(a, b, c); });
 
     // residues in [0, p): q = floor(acc / p) from a double quotient (|acc| < 2^31,
     // exact up to one unit, then corrected)
