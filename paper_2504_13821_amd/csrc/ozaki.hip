@@ -319,27 +319,67 @@ __host__ __device__ constexpr int inv_mod(int a, int p)
     return t0 < 0 ? t0 + p : t0;
 }
 
+// x mod P in [0, P) for an integer-valued float |x| < 2^16, exactly: the
+// quotient estimate floor(x (1/P)) is off by at most one (its relative error
+// is below 2^-22 and a remainder r != 0 keeps x / P at least 1/P from an
+// integer), the fused multiply-add computes x - q P exactly (integers below
+// 2^24), and one correction each way brings it into [0, P).  Full-rate FP32
+// arithmetic in place of the quarter-rate 32-bit integer multiplies of a
+// division by a constant.
+template <int P>
+__device__ __forceinline__ float fmodp(float x)
+{
+    const float q = __builtin_floorf(x * (1.0f / (float)P));
+    float r = __builtin_fmaf(-q, (float)P, x);
+    r = r < 0.0f ? r + (float)P : r;
+    return r >= (float)P ? r - (float)P : r;
+}
+
 // digit T of the mixed-radix form: a_T = (((r_T - a_0) c_0T - a_1) c_1T - ...) mod p_T
-// with c_sT = p_s^-1 mod p_T
+// with c_sT = p_s^-1 mod p_T; digits and residues are integer-valued floats
+// below 256, so every product (v - a_S) c_sT is an integer below 2^16 in
+// magnitude, exact in FP32
 template <int T, int S>
-__device__ __forceinline__ int garner_step(int v, const int *a)
+__device__ __forceinline__ float garner_step(float v, const float *a)
 {
     if constexpr (S == T) {
         return v;
     } else {
         constexpr int P = mod_at(T);
         constexpr int C = inv_mod(mod_at(S) % P, P);
-        return garner_step<T, S + 1>(pmod<P>((v - a[S]) * C), a);
+        return garner_step<T, S + 1>(fmodp<P>((v - a[S]) * (float)C), a);
     }
 }
 
 template <int N, int T>
-__device__ __forceinline__ void garner_digits(const int *r, int *a)
+__device__ __forceinline__ void garner_digits(const float *r, float *a)
 {
     if constexpr (T < N) {
         a[T] = garner_step<T, 0>(r[T], a);
         garner_digits<N, T + 1>(r, a);
     }
+}
+
+// sum over t in [T0, T1) of d_t p_T0 ... p_(t-1) (Horner's rule from the top
+// digit; the partial values stay below the product of those moduli, under
+// 2^64 for eight of them)
+template <int T0, int T1>
+__device__ __forceinline__ uint64_t horner64(const uint32_t *d)
+{
+    uint64_t z = 0;
+#pragma unroll
+    for (int t = T1 - 1; t >= T0; --t)
+        z = z * (uint64_t)mod_at(t) + d[t];
+    return z;
+}
+
+// product of the moduli t in [T0, T1)
+__host__ __device__ constexpr uint64_t mod_prod(int t0, int t1)
+{
+    uint64_t w = 1;
+    for (int t = t0; t < t1; ++t)
+        w *= (uint64_t)mod_at(t);
+    return w;
 }
 
 template <int N>
@@ -359,29 +399,31 @@ __global__ __launch_bounds__(256) void garner_kernel(GarnerDesc d)
         const int64_t i = i0 + r;
         if (i >= d.M)
             break;
-        int rr[N], a[N];
+        float rr[N], a[N];
 #pragma unroll
         for (int t = 0; t < N; ++t)
-            rr[t] = (int)((w[t] >> (8 * r)) & 255u);
+            rr[t] = (float)((w[t] >> (8 * r)) & 255u);
         garner_digits<N, 0>(rr, a);
         // Z' = a_0 + p_0 (a_1 + p_1 (...)) in [0, P); Z = Z' - P when the top
         // digit is in the upper half (|Z| < P/4 leaves no ambiguity).  The
         // negative case takes the digit complement: P - Z' = 1 + sum (p_t - 1 - a_t) W_t.
-        // Horner's rule on a 128-bit unsigned integer (P < 2^128), exact; then
-        // one correctly rounded conversion to FP64 (the top 64 significant
-        // bits with a sticky bit for the rest), so an integer Z representable
-        // in FP64 comes out exactly.
-        const bool neg = 2 * a[N - 1] >= mod_at(N - 1);
-        uint64_t zh = 0, zl = 0;
+        // Exact 128-bit value (P < 2^128) as L + W_8 H, L and H the Horner
+        // sums of digits 0..7 and 8..15 (each under 2^64), W_8 = p_0 ... p_7;
+        // then one correctly rounded conversion to FP64 (the top 64
+        // significant bits with a sticky bit for the rest), so an integer Z
+        // representable in FP64 comes out exactly.
+        static_assert(N == 16, "two halves of eight digits");
+        const bool neg = 2.0f * a[N - 1] >= (float)mod_at(N - 1);
+        uint32_t dg[N];
 #pragma unroll
-        for (int t = N - 1; t >= 0; --t) {
-            const uint64_t pt = (uint64_t)mod_at(t);
-            const uint64_t dig = (uint64_t)(neg ? mod_at(t) - 1 - a[t] : a[t]);
-            const uint64_t plo = zl * pt;
-            zh = zh * pt + __umul64hi(zl, pt);
-            zl = plo + dig;
-            zh += zl < plo ? 1u : 0u;
-        }
+        for (int t = 0; t < N; ++t)
+            dg[t] = (uint32_t)(neg ? (float)(mod_at(t) - 1) - a[t] : a[t]);
+        constexpr uint64_t W8 = mod_prod(0, 8);
+        const uint64_t lo = horner64<0, 8>(dg), hi = horner64<8, 16>(dg);
+        uint64_t zl = hi * W8;
+        uint64_t zh = __umul64hi(hi, W8);
+        zl += lo;
+        zh += zl < lo ? 1u : 0u;
         if (neg) {   // + 1 of the complement
             zl += 1u;
             zh += zl == 0u ? 1u : 0u;
