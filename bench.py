@@ -850,7 +850,7 @@ def bench_serving(rt, count, rates=(0.1, 0.25, 0.5, 0.75, 0.9, 1.0, 1.2)):
         out = dict(pct(lat), solves_per_s=round(count / span, 1), busy_tflops=round(flops / span / 1e12, 3),
                    per_tag={k: pct(v) for k, v in sorted(by_tag.items())},
                    errors=bad, errors_by_status=by_status, failed_sample=failed,
-                   batched_requests=st["batched_requests"], launches=st["launches"],
+                   batched_requests=st["batched_requests"], launches=st["launches"], refine_turns=st["refine_turns"],
                    factor_hits=st["factor_hits"], factor_misses=st["factor_misses"],
                    evictions=st["evictions"], hbm_peak_GB=round(st["hbm_peak"] / 1e9, 2))
         out.pop("count")

@@ -520,6 +520,8 @@ typedef struct {
     int max_batch;          /* most requests folded into one batched launch */
     int64_t small_max;      /* FP64 requests with factor order <= small_max join batched launches */
     uint64_t synth_seed;    /* seed of synthetic factors and right-hand sides (rtri_synth_fill) */
+    int refine_requeue;     /* 0: a refined solve runs to the end in one turn of its slot; 1: it
+                               re-enters the queue after each correction (see rtri_request) */
 } rtri_server_cfg;
 
 /* One request: a TRSM (op 0) or TRMM (op 1) with the argument meaning of
@@ -530,7 +532,13 @@ typedef struct {
  * the device on first use and cached (evicted least recently used when the
  * budget needs room; never while a request uses it).  The right-hand side is
  * synthetic (kind 0, stream 2, id = rhs_id).  precision selects the FP64 path
- * or the mixed-precision refined TRSM (TRSM only).  If result != NULL the
+ * or the mixed-precision refined TRSM (TRSM only; tolerance 1e-12, at most 30
+ * corrections).  With refine_requeue set, a refined solve runs one correction
+ * per turn and re-enters the queue after each (its right-hand side and
+ * iteration state stay on the device; any slot may run its next correction;
+ * at most `slots` refined solves are started and unfinished at a time), so
+ * slots serve other requests between its corrections; either way the
+ * arithmetic, and so the result, is that of a refined solve run alone.  If result != NULL the
  * m-by-n result is copied there (host, column-major, ld = m) before the
  * request completes; the buffer must stay valid until then.  t_arrival is the
  * scheduled arrival time on the server clock; latency is measured from it. */
@@ -559,10 +567,13 @@ typedef struct {
     int64_t launches, batched_launches, batched_requests;
     int64_t factor_hits, factor_misses, evictions;
     int64_t hbm_in_use, hbm_peak;   /* device memory the server holds (factors and their factor objects'
-                                       parts, right-hand sides, slot workspace), now and at most; admission
-                                       also counts reservations for work not yet done (workspace growth,
-                                       factor-object parts, upper bounds), which these exclude */
+                                       parts, right-hand sides, refined solves' iteration state, slot
+                                       workspace), now and at most; admission also counts reservations for
+                                       work not yet done (workspace growth, factor-object parts, upper
+                                       bounds), which these exclude */
     double useful_flops;    /* sum of ka^2 * vectors over completed requests */
+    int64_t refine_turns;   /* turns run by refined solves (one per solve, or with refine_requeue
+                               one per correction, re-queued between them) */
 } rtri_server_counters;
 
 typedef struct rtri_server rtri_server;

@@ -115,7 +115,7 @@ rtri_synth_fill = _sig("rtri_synth_fill", _int, _vp, _int, _int, ctypes.c_uint64
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("slots", _int), ("hbm_budget", _i64), ("max_batch", _int), ("small_max", _i64),
-                ("synth_seed", ctypes.c_uint64)]
+                ("synth_seed", ctypes.c_uint64), ("refine_requeue", _int)]
 
 
 class Request(ctypes.Structure):
@@ -134,7 +134,7 @@ class Counters(ctypes.Structure):
     _fields_ = [("submitted", _i64), ("completed", _i64), ("failed", _i64), ("launches", _i64),
                 ("batched_launches", _i64), ("batched_requests", _i64), ("factor_hits", _i64),
                 ("factor_misses", _i64), ("evictions", _i64), ("hbm_in_use", _i64), ("hbm_peak", _i64),
-                ("useful_flops", ctypes.c_double)]
+                ("useful_flops", ctypes.c_double), ("refine_turns", _i64)]
 
 
 PREC_F64, PREC_MIXED_BF16, PREC_MIXED_F32 = 0, 1, 2
@@ -704,8 +704,9 @@ class Server:
     the rtri_request fields; 'result' may be a float64 numpy array (m x n,
     Fortran order) that receives the result."""
 
-    def __init__(self, slots=4, hbm_budget=64 << 30, max_batch=256, small_max=1024, seed=250413821):
-        cfg = ServerCfg(slots, hbm_budget, max_batch, small_max, seed)
+    def __init__(self, slots=4, hbm_budget=64 << 30, max_batch=256, small_max=1024, seed=250413821,
+                 refine_requeue=False):
+        cfg = ServerCfg(slots, hbm_budget, max_batch, small_max, seed, 1 if refine_requeue else 0)
         p = _vp()
         check(rtri_server_create(ctypes.byref(cfg), ctypes.byref(p)), "rtri_server_create")
         self._s = p

@@ -167,6 +167,108 @@ int plain_call(rtri_handle *h, rtri_factor *f, bool solve, int side, int trans, 
 
 }  // namespace
 
+// What the refined solve needs from A, made once per factor (the copy of A in
+// the GEMM type, the packed blocks of both plans, |op(A)|, the INT8 residue
+// planes when that residual is selected) and kept in its parts.
+static int refine_prep(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, int precision,
+                       MixedPrep &prep)
+{
+    const int tr = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    const ElemT gt = precision == RTRI_PREC_MIXED_BF16 ? ElemT::BF16 : ElemT::F32;
+    const double *A = static_cast<const double *>(f->A);
+    prep.ldag = ws_ld(f->ka);
+    prep.ag_trans = mixed_ag_trans(gt, side, tr);
+    {
+        std::lock_guard<std::mutex> lk(f->mu);
+        const Part *part = nullptr;
+        const int kcopy[6] = {(int)gt, prep.ag_trans ? 1 : 0, 0, 0, 0, 0};
+        hipError_t e = get_part(h, f, PART_COPY, kcopy, [&](Part &p) {
+            hipError_t e2 = part_alloc(h, p, (size_t)f->ka * (size_t)prep.ldag * elem_size(gt));
+            return e2 == hipSuccess ? launch_mixed_copy(h, gt, prep.ag_trans, f->ka, A, f->lda, p.mem, prep.ldag) : e2;
+        }, &part);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        prep.Acopy = part->mem;
+        PlanIn lo = mixed_lo_plan(h, side, f->uplo, tr, f->diag, m, n, gt, A, f->lda);
+        e = packed_blocks(h, f, lo);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        prep.lo_pack = lo.packed;
+        prep.lo_leaf = lo.leaf;
+        PlanIn mul = mixed_mul_plan(h, side, f->uplo, tr, f->diag, m, n, A, f->lda);
+        e = packed_blocks(h, f, mul);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        prep.mul_pack = mul.packed;
+        prep.mul_leaf = mul.leaf;
+        const int knorm[6] = {side, tr, 0, 0, 0, 0};
+        e = get_part(h, f, PART_NORM, knorm, [&](Part &p) {
+            // the norm is read back once, into host memory
+            hipError_t e2 = ensure_ws(h, WS_SCALARS, 64);
+            unsigned long long *sc = e2 == hipSuccess ? static_cast<unsigned long long *>(h->ws[WS_SCALARS]) : nullptr;
+            unsigned long long bits = 0;
+            if (e2 == hipSuccess)
+                e2 = launch_zero_u64(sc, 1, h->stream);
+            if (e2 == hipSuccess)
+                e2 = launch_mixed_norm(h, side, f->uplo, tr, f->diag, f->ka, A, f->lda, sc);
+            if (e2 == hipSuccess)
+                e2 = hipMemcpyAsync(&bits, sc, sizeof bits, hipMemcpyDeviceToHost, h->stream);
+            if (e2 == hipSuccess)
+                e2 = hipStreamSynchronize(h->stream);
+            if (e2 == hipSuccess)
+                std::memcpy(&p.value, &bits, sizeof bits);
+            p.stream = h->stream;
+            return e2;
+        }, &part);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        prep.have_anorm = true;
+        prep.anorm = part->value;
+        if (h->residual == 1 && ozaki_nmod(f->ka) > 0) {
+            const int koz[6] = {side, tr, 0, 0, 0, 0};
+            e = get_part(h, f, PART_OZAKI, koz, [&](Part &p) {
+                hipError_t e2 = part_alloc(h, p, ozaki_factor_bytes(side, f->ka));
+                return e2 == hipSuccess ? ozaki_split_factor(h, side, f->uplo, tr, f->diag, f->ka, A, f->lda, p.mem)
+                                        : e2;
+            }, &part);
+            if (e != hipSuccess)
+                return hip_fail(h, e);
+            prep.oz_planes = part->mem;
+        }
+    }
+    return RTRI_OK;
+}
+
+namespace rtri {
+
+int factor_refine_begin(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, double alpha,
+                        const double *B, int64_t ldb, int precision, double tol, int max_iter, rtri_refine_info *info,
+                        RefineState &st)
+{
+    MixedPrep prep;
+    const int rc = refine_prep(h, f, side, trans, m, n, precision, prep);
+    if (rc != RTRI_OK)
+        return rc;
+    const int tr = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    return refine_begin(h, side, f->uplo, tr, f->diag, m, n, alpha, static_cast<const double *>(f->A), f->lda, B, ldb,
+                        tol, max_iter, info, prep, st);
+}
+
+int factor_refine_step(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, int precision,
+                       double tol, int max_iter, rtri_refine_info *info, RefineState &st)
+{
+    MixedPrep prep;
+    const int rc = refine_prep(h, f, side, trans, m, n, precision, prep);
+    if (rc != RTRI_OK)
+        return rc;
+    const int tr = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
+    const ElemT gt = precision == RTRI_PREC_MIXED_BF16 ? ElemT::BF16 : ElemT::F32;
+    return refine_step(h, side, f->uplo, tr, f->diag, m, n, static_cast<const double *>(f->A), f->lda, gt, tol,
+                       max_iter, info, prep, st);
+}
+
+}  // namespace rtri
+
 extern "C" {
 
 int rtri_factor_create(rtri_handle *h, int uplo, int diag, int64_t ka, int dtype, const void *A, int64_t lda,
@@ -282,70 +384,13 @@ int rtri_factor_trsm(rtri_handle *h, rtri_factor *f, int side, int trans, int64_
         return plain_call(h, f, true, side, trans, m, n, alpha, B, ldb);
     }
     // refined solve: copy of A, packed blocks of both plans and |op(A)| from the factor
+    MixedPrep prep;
+    rc = refine_prep(h, f, side, trans, m, n, precision, prep);
+    if (rc != RTRI_OK)
+        return rc;
     const int tr = trans == RTRI_CONJTRANS ? RTRI_TRANS : trans;
     const ElemT gt = precision == RTRI_PREC_MIXED_BF16 ? ElemT::BF16 : ElemT::F32;
     const double *A = static_cast<const double *>(f->A);
-    MixedPrep prep;
-    prep.ldag = ws_ld(f->ka);
-    prep.ag_trans = mixed_ag_trans(gt, side, tr);
-    {
-        std::lock_guard<std::mutex> lk(f->mu);
-        const Part *part = nullptr;
-        const int kcopy[6] = {(int)gt, prep.ag_trans ? 1 : 0, 0, 0, 0, 0};
-        hipError_t e = get_part(h, f, PART_COPY, kcopy, [&](Part &p) {
-            hipError_t e2 = part_alloc(h, p, (size_t)f->ka * (size_t)prep.ldag * elem_size(gt));
-            return e2 == hipSuccess ? launch_mixed_copy(h, gt, prep.ag_trans, f->ka, A, f->lda, p.mem, prep.ldag) : e2;
-        }, &part);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        prep.Acopy = part->mem;
-        PlanIn lo = mixed_lo_plan(h, side, f->uplo, tr, f->diag, m, n, gt, A, f->lda);
-        e = packed_blocks(h, f, lo);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        prep.lo_pack = lo.packed;
-        prep.lo_leaf = lo.leaf;
-        PlanIn mul = mixed_mul_plan(h, side, f->uplo, tr, f->diag, m, n, A, f->lda);
-        e = packed_blocks(h, f, mul);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        prep.mul_pack = mul.packed;
-        prep.mul_leaf = mul.leaf;
-        const int knorm[6] = {side, tr, 0, 0, 0, 0};
-        e = get_part(h, f, PART_NORM, knorm, [&](Part &p) {
-            // the norm is read back once, into host memory
-            hipError_t e2 = ensure_ws(h, WS_SCALARS, 64);
-            unsigned long long *sc = e2 == hipSuccess ? static_cast<unsigned long long *>(h->ws[WS_SCALARS]) : nullptr;
-            unsigned long long bits = 0;
-            if (e2 == hipSuccess)
-                e2 = launch_zero_u64(sc, 1, h->stream);
-            if (e2 == hipSuccess)
-                e2 = launch_mixed_norm(h, side, f->uplo, tr, f->diag, f->ka, A, f->lda, sc);
-            if (e2 == hipSuccess)
-                e2 = hipMemcpyAsync(&bits, sc, sizeof bits, hipMemcpyDeviceToHost, h->stream);
-            if (e2 == hipSuccess)
-                e2 = hipStreamSynchronize(h->stream);
-            if (e2 == hipSuccess)
-                std::memcpy(&p.value, &bits, sizeof bits);
-            p.stream = h->stream;
-            return e2;
-        }, &part);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        prep.have_anorm = true;
-        prep.anorm = part->value;
-        if (h->residual == 1 && ozaki_nmod(f->ka) > 0) {
-            const int koz[6] = {side, tr, 0, 0, 0, 0};
-            e = get_part(h, f, PART_OZAKI, koz, [&](Part &p) {
-                hipError_t e2 = part_alloc(h, p, ozaki_factor_bytes(side, f->ka));
-                return e2 == hipSuccess ? ozaki_split_factor(h, side, f->uplo, tr, f->diag, f->ka, A, f->lda, p.mem)
-                                        : e2;
-            }, &part);
-            if (e != hipSuccess)
-                return hip_fail(h, e);
-            prep.oz_planes = part->mem;
-        }
-    }
     return mixed_core(h, side, f->uplo, tr, f->diag, m, n, alpha, A, f->lda, static_cast<double *>(B), ldb, gt, tol,
                       max_iter, info, prep);
 }

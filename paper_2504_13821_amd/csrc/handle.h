@@ -28,11 +28,7 @@ enum WsSlot {
     WS_PACK = 0,     // packed diagonal blocks of the current plan
     WS_PACK2,        // packed blocks kept across the refinement steps
     WS_ACOPY,        // converted copy of A (mixed precision)
-    WS_PANEL32,      // FP32 right-hand side of the low-precision solve
-    WS_X,            // FP64 iterate
-    WS_R0,           // FP64 alpha * B
-    WS_R,            // FP64 residual
-    WS_W,            // FP64 op(A) * X
+    WS_REFINE,       // state of a refined solve run to the end (RefineState: X, R0, R, W, the FP32 panel)
     WS_SCALARS,      // small reduction results
     WS_SAVE,         // copy of a TRMM panel's original values (all leaves in one launch)
     WS_SPLIT,        // split-K partial products, one region per stream an update may run on
@@ -178,6 +174,46 @@ inline bool mixed_ag_trans(ElemT gt, int side, int tr)
 int mixed_core(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
                const double *A, int64_t lda, double *B, int64_t ldb, ElemT gt, double tol, int max_iter,
                rtri_refine_info *info, const MixedPrep &prep);
+// The refinement in phases, so that a caller can run other work between its
+// corrections (the serving loop re-queues refined requests once per
+// correction): refine_begin (|op(A)|, R0 = alpha B, max |R0|), refine_step
+// (one correction: low-precision solve, X update, residual and eta; one
+// host read of two scalars), repeated until done, then refine_end (X into
+// B).  The state's matrices (ld-padded m x n: X, R0, R, W in FP64, the FP32
+// panel D, four scalars) live in refine_state_bytes(m, n) bytes of device
+// memory given to refine_state_place; any handle with the same options may
+// run any phase (the plans are rebuilt per phase).  Per element the
+// arithmetic is that of mixed_core, which runs the phases back to back.
+struct RefineState {
+    float *D = nullptr;
+    double *X = nullptr, *R0 = nullptr, *R = nullptr, *W = nullptr;
+    unsigned long long *sc = nullptr;
+    int64_t ld = 0;
+    const void *oz = nullptr;   // op(A)'s INT8 residue planes (INT8-product residual)
+    double anorm = 0.0, rmax = 0.0, eta = 0.0, eta_prev = 0.0;
+    int iters = 0;
+    bool converged = false, stalled = false, done = false;
+    bool lo_packed = false, mul_packed = false;   // the plans' blocks packed (skip from now on)
+};
+size_t refine_state_bytes(int64_t m, int64_t n);
+void refine_state_place(RefineState &st, void *mem, int64_t m, int64_t n);
+int refine_begin(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
+                 const double *A, int64_t lda, const double *B, int64_t ldb, double tol, int max_iter,
+                 rtri_refine_info *info, const MixedPrep &prep, RefineState &st);
+int refine_step(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, const double *A,
+                int64_t lda, ElemT gt, double tol, int max_iter, rtri_refine_info *info, const MixedPrep &prep,
+                RefineState &st);
+int refine_end(rtri_handle *h, int64_t m, int64_t n, double *B, int64_t ldb, rtri_refine_info *info,
+               const RefineState &st);
+// the refined solve against a factor object in phases (factor.hip): arguments
+// as rtri_factor_trsm checks them, m, n > 0, alpha != 0, a mixed precision;
+// the factor's parts (copy of A, packed blocks, |op(A)|, residue planes) are
+// made by the first phase that needs them
+int factor_refine_begin(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, double alpha,
+                        const double *B, int64_t ldb, int precision, double tol, int max_iter, rtri_refine_info *info,
+                        RefineState &st);
+int factor_refine_step(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, int precision,
+                       double tol, int max_iter, rtri_refine_info *info, RefineState &st);
 // lines of op(A) (side L) or op(A)^T (side R) summed into out[0] (anorm)
 hipError_t launch_mixed_norm(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t ka, const double *A,
                              int64_t lda, unsigned long long *out);

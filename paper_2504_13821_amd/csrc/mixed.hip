@@ -104,143 +104,193 @@ PlanIn mixed_mul_plan(rtri_handle *h, int side, int uplo, int tr, int diag, int6
     return mul;
 }
 
-int mixed_core(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
-               const double *A, int64_t lda, double *B, int64_t ldb, ElemT gt, double tol, int max_iter,
-               rtri_refine_info *info, const MixedPrep &prep)
+size_t refine_state_bytes(int64_t m, int64_t n)
 {
-    hipStream_t st = h->stream;
-    hipError_t e;
-    int rc;
-    const bool left = side == RTRI_LEFT;
-    const int64_t ka = left ? m : n;
-    const size_t mn = (size_t)m * (size_t)n;
+    const size_t ln = (size_t)ws_ld(m) * (size_t)n;
+    return ln * 4 + 4 * ln * 8 + 256;
+}
 
+void refine_state_place(RefineState &st, void *mem, int64_t m, int64_t n)
+{
     const int64_t ld = ws_ld(m);
     const size_t ln = (size_t)ld * (size_t)n;
-    const size_t need[] = {ln * 4, ln * 8, ln * 8, ln * 8, ln * 8, 64};
-    const int slot[] = {WS_PANEL32, WS_X, WS_R0, WS_R, WS_W, WS_SCALARS};
-    for (int i = 0; i < 6; ++i) {
-        e = ensure_ws(h, slot[i], need[i]);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-    }
-    float *D = static_cast<float *>(h->ws[WS_PANEL32]);
-    double *X = static_cast<double *>(h->ws[WS_X]);
-    double *R0 = static_cast<double *>(h->ws[WS_R0]);
-    double *R = static_cast<double *>(h->ws[WS_R]);
-    double *W = static_cast<double *>(h->ws[WS_W]);
-    unsigned long long *sc = static_cast<unsigned long long *>(h->ws[WS_SCALARS]);
+    char *p = static_cast<char *>(mem);
+    st.ld = ld;
+    st.X = reinterpret_cast<double *>(p);
+    st.R0 = st.X + ln;
+    st.R = st.R0 + ln;
+    st.W = st.R + ln;
+    st.sc = reinterpret_cast<unsigned long long *>(st.W + ln);
+    st.D = reinterpret_cast<float *>(p + 4 * ln * 8 + 256);   // after the 4 scalars (kept 256-byte aligned)
+}
 
-    // once per call: |op(A)| (unless known), alpha B, max |R|
+// the loop's continuation test (the refinement's stopping rules)
+static bool refine_more(const RefineState &st, int max_iter)
+{
+    return !st.converged && !st.stalled && st.iters < max_iter && st.rmax > 0.0 && std::isfinite(st.rmax);
+}
+
+int refine_begin(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
+                 const double *A, int64_t lda, const double *B, int64_t ldb, double tol, int max_iter,
+                 rtri_refine_info *info, const MixedPrep &prep, RefineState &st)
+{
+    hipStream_t st_ = h->stream;
+    const int64_t ka = side == RTRI_LEFT ? m : n;
+    const size_t mn = (size_t)m * (size_t)n;
     auto other = [&](double bytes, auto &&f) { return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, bytes, f); };
-    e = launch_zero_u64(sc, 4, st);
+    // |op(A)| (unless known), alpha B, max |R|
+    hipError_t e = launch_zero_u64(st.sc, 4, st_);
     if (e == hipSuccess && !prep.have_anorm)
-        e = launch_mixed_norm(h, side, uplo, tr, diag, ka, A, lda, sc + 2);
+        e = launch_mixed_norm(h, side, uplo, tr, diag, ka, A, lda, st.sc + 2);
     if (e == hipSuccess)
-        e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, B, ldb, R0, ld, m, n, alpha, st); });
+        e = other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, B, ldb, st.R0, st.ld, m, n, alpha, st_); });
     // the first residual is alpha B itself (X = 0): it is read from R0, and the
     // first correction is assigned to X rather than added
     if (e == hipSuccess)
-        e = other(8.0 * mn, [&] { return launch_max_abs(R0, ld, m, n, sc + 1, st); });
+        e = other(8.0 * mn, [&] { return launch_max_abs(st.R0, st.ld, m, n, st.sc + 1, st_); });
     unsigned long long host[4];
     if (e == hipSuccess)
-        e = hipMemcpyAsync(host, sc, sizeof host, hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(host, st.sc, sizeof host, hipMemcpyDeviceToHost, st_);
     if (e == hipSuccess)
-        e = hipStreamSynchronize(st);
+        e = hipStreamSynchronize(st_);
     if (e != hipSuccess)
         return hip_fail(h, e);
-    const double anorm = prep.have_anorm ? prep.anorm : from_bits(host[2]);
-    double rmax = from_bits(host[1]);
+    st.anorm = prep.have_anorm ? prep.anorm : from_bits(host[2]);
+    st.rmax = from_bits(host[1]);
     if (info != nullptr)
-        info->anorm = anorm;
+        info->anorm = st.anorm;
+    // residual product from exact INT8 products: op(A)'s residue planes once
+    st.oz = prep.oz_planes;
+    if (h->residual == 1 && ozaki_nmod(ka) > 0 && st.oz == nullptr) {
+        e = ensure_ws(h, WS_OZA, ozaki_factor_bytes(side, ka));
+        if (e == hipSuccess)
+            e = ozaki_split_factor(h, side, uplo, tr, diag, ka, A, lda, h->ws[WS_OZA]);
+        if (e != hipSuccess)
+            return hip_fail(h, e);
+        st.oz = h->ws[WS_OZA];
+    }
+    st.eta = st.rmax == 0.0 ? 0.0 : INFINITY;
+    st.eta_prev = INFINITY;
+    st.iters = 0;
+    st.converged = st.eta <= tol;
+    st.stalled = false;
+    st.done = !refine_more(st, max_iter);
+    return RTRI_OK;
+}
+
+int refine_step(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, const double *A,
+                int64_t lda, ElemT gt, double tol, int max_iter, rtri_refine_info *info, const MixedPrep &prep,
+                RefineState &st)
+{
+    hipStream_t st_ = h->stream;
+    const bool left = side == RTRI_LEFT;
+    const int64_t ka = left ? m : n;
+    const size_t mn = (size_t)m * (size_t)n;
+    const int64_t ld = st.ld;
+    auto other = [&](double bytes, auto &&f) { return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, bytes, f); };
 
     PlanIn lo = mixed_lo_plan(h, side, uplo, tr, diag, m, n, gt, A, lda);
-    lo.B = reinterpret_cast<char *>(D);
+    lo.B = reinterpret_cast<char *>(st.D);
     lo.ldb = ld;
     lo.Ag = static_cast<const char *>(prep.Acopy);
     lo.ldag = prep.ldag;
     lo.ag_trans = prep.ag_trans;
     if (prep.lo_pack != nullptr && prep.lo_leaf == lo.leaf)
         lo.packed = prep.lo_pack;
+    lo.skip_pack = st.lo_packed;
     PlanIn mul = mixed_mul_plan(h, side, uplo, tr, diag, m, n, A, lda);
-    mul.B = reinterpret_cast<char *>(W);
+    mul.B = reinterpret_cast<char *>(st.W);
     mul.ldb = ld;
     if (prep.mul_pack != nullptr && prep.mul_leaf == mul.leaf)
         mul.packed = prep.mul_pack;
-    // residual product from exact INT8 products: op(A)'s residue planes once
-    const bool int8_resid = h->residual == 1 && ozaki_nmod(ka) > 0;
-    const void *oz_planes = prep.oz_planes;
-    if (int8_resid && oz_planes == nullptr) {
-        e = ensure_ws(h, WS_OZA, ozaki_factor_bytes(side, ka));
-        if (e == hipSuccess)
-            e = ozaki_split_factor(h, side, uplo, tr, diag, ka, A, lda, h->ws[WS_OZA]);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        oz_planes = h->ws[WS_OZA];
-    }
+    mul.skip_pack = st.mul_packed;
+    const bool int8_resid = h->residual == 1 && ozaki_nmod(ka) > 0 && st.oz != nullptr;
 
-    double eta = rmax == 0.0 ? 0.0 : INFINITY, eta_prev = INFINITY;
-    int iters = 0;
-    bool converged = eta <= tol;
-    while (!converged && iters < max_iter && rmax > 0.0 && std::isfinite(rmax)) {
-        const double s = std::ldexp(1.0, (int)std::ceil(std::log2(rmax)));
-        const double *Rk = iters == 0 ? R0 : R;
-        e = other(12.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F32, Rk, ld, D, ld, m, n, 1.0 / s, st); });
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        rc = run_plan(h, lo);
-        if (rc != RTRI_OK)
-            return rc;
-        lo.skip_pack = true;
-        // X += s D (X = s D the first time), and W = X for the residual's product (one pass)
-        const bool assign = iters == 0;
-        e = other((assign ? 20.0 : 28.0) * mn,
-                  [&] { return launch_add_scaled(X, ld, D, ld, m, n, s, assign, W, ld, st); });
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        if (int8_resid) {
-            rc = ozaki_product(h, side, uplo, tr, m, n, 1.0, oz_planes, W, ld, W, ld);
-        } else {
-            rc = run_plan(h, mul);
-            mul.skip_pack = true;
-        }
-        if (rc != RTRI_OK)
-            return rc;
-        e = launch_zero_u64(sc, 2, st);
-        if (e == hipSuccess)
-            e = other(32.0 * mn, [&] {
-                return launch_resid_eta(R0, ld, W, ld, R, ld, X, ld, m, n, left, anorm, sc, st);
-            });
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(host, sc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(st);
-        if (e != hipSuccess)
-            return hip_fail(h, e);
-        eta = from_bits(host[0]);
-        rmax = from_bits(host[1]);
-        if (info != nullptr && iters < 32)
-            info->eta_hist[iters] = eta;
-        ++iters;
-        if (eta <= tol) {
-            converged = true;
-            break;
-        }
-        if (!(eta <= 0.5 * eta_prev))   // stagnation (or NaN)
-            break;
-        eta_prev = eta;
+    const double s = std::ldexp(1.0, (int)std::ceil(std::log2(st.rmax)));
+    const double *Rk = st.iters == 0 ? st.R0 : st.R;
+    hipError_t e = other(12.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F32, Rk, ld, st.D, ld, m, n, 1.0 / s, st_); });
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    int rc = run_plan(h, lo);
+    if (rc != RTRI_OK)
+        return rc;
+    st.lo_packed = true;
+    // X += s D (X = s D the first time), and W = X for the residual's product (one pass)
+    const bool assign = st.iters == 0;
+    e = other((assign ? 20.0 : 28.0) * mn,
+              [&] { return launch_add_scaled(st.X, ld, st.D, ld, m, n, s, assign, st.W, ld, st_); });
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    if (int8_resid) {
+        rc = ozaki_product(h, side, uplo, tr, m, n, 1.0, st.oz, st.W, ld, st.W, ld);
+    } else {
+        rc = run_plan(h, mul);
+        st.mul_packed = true;
     }
+    if (rc != RTRI_OK)
+        return rc;
+    e = launch_zero_u64(st.sc, 2, st_);
+    if (e == hipSuccess)
+        e = other(32.0 * mn, [&] {
+            return launch_resid_eta(st.R0, ld, st.W, ld, st.R, ld, st.X, ld, m, n, left, st.anorm, st.sc, st_);
+        });
+    unsigned long long host[2];
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, st.sc, sizeof host, hipMemcpyDeviceToHost, st_);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st_);
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    st.eta = from_bits(host[0]);
+    st.rmax = from_bits(host[1]);
+    if (info != nullptr && st.iters < 32)
+        info->eta_hist[st.iters] = st.eta;
+    ++st.iters;
+    if (st.eta <= tol)
+        st.converged = true;
+    else if (!(st.eta <= 0.5 * st.eta_prev))   // stagnation (or NaN)
+        st.stalled = true;
+    st.eta_prev = st.eta;
+    st.done = !refine_more(st, max_iter);
+    return RTRI_OK;
+}
+
+int refine_end(rtri_handle *h, int64_t m, int64_t n, double *B, int64_t ldb, rtri_refine_info *info,
+               const RefineState &st)
+{
+    const size_t mn = (size_t)m * (size_t)n;
     // no correction made (alpha B is zero, or not finite): X = 0
-    e = iters == 0 ? other(8.0 * mn, [&] { return launch_fill(DType::F64, B, m, n, ldb, 0.0, st); })
-                   : other(16.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F64, X, ld, B, ldb, m, n, 1.0, st); });
+    const hipError_t e =
+        timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, (st.iters == 0 ? 8.0 : 16.0) * mn, [&] {
+            return st.iters == 0 ? launch_fill(DType::F64, B, m, n, ldb, 0.0, h->stream)
+                                 : launch_convert(ElemT::F64, ElemT::F64, st.X, st.ld, B, ldb, m, n, 1.0, h->stream);
+        });
     if (e != hipSuccess)
         return hip_fail(h, e);
     if (info != nullptr) {
-        info->iters = iters;
-        info->converged = converged ? 1 : 0;
-        info->eta = eta;
+        info->iters = st.iters;
+        info->converged = st.converged ? 1 : 0;
+        info->eta = st.eta;
     }
-    return converged ? RTRI_OK : RTRI_NOT_CONVERGED;
+    return st.converged ? RTRI_OK : RTRI_NOT_CONVERGED;
+}
+
+int mixed_core(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
+               const double *A, int64_t lda, double *B, int64_t ldb, ElemT gt, double tol, int max_iter,
+               rtri_refine_info *info, const MixedPrep &prep)
+{
+    // the whole refinement on this handle: its state in the handle's workspace
+    hipError_t e = ensure_ws(h, WS_REFINE, refine_state_bytes(m, n));
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    RefineState st;
+    refine_state_place(st, h->ws[WS_REFINE], m, n);
+    int rc = refine_begin(h, side, uplo, tr, diag, m, n, alpha, A, lda, B, ldb, tol, max_iter, info, prep, st);
+    while (rc == RTRI_OK && !st.done)
+        rc = refine_step(h, side, uplo, tr, diag, m, n, A, lda, gt, tol, max_iter, info, prep, st);
+    if (rc != RTRI_OK)
+        return rc;
+    return refine_end(h, m, n, B, ldb, info, st);
 }
 
 }  // namespace rtri

@@ -6,7 +6,13 @@
 //      - a small FP64 request (factor order <= small_max) opens a batch: the
 //        slot keeps taking small FP64 requests from the queue front, up to
 //        max_batch, while their memory fits the budget;
-//      - any other request (large, or mixed precision) runs alone;
+//      - any other request (large, or mixed precision) runs alone; with
+//        refine_requeue a refined (mixed-precision) solve runs one
+//        correction per turn and re-enters the queue after each (its
+//        right-hand side and iteration state stay on the device; everything
+//        else it reads is the factor object's), so slots serve other
+//        requests between its corrections and any slot may run its next one;
+//        at most one refined solve per slot is started and unfinished;
 //      admission reserves the request's right-hand side and workspace and, for
 //      a factor not resident yet, the factor itself; least-recently-used
 //      factors nobody is using are evicted when the budget needs room.  A new
@@ -46,7 +52,22 @@ struct Req {
     int64_t ka;
     size_t rhs_bytes, ws_bytes;
     bool small;
+    // a refined solve run in phases: one correction per turn, re-queued between
+    bool refine = false;
+    size_t state_bytes = 0;     // its iteration state (refine_state_bytes) and the padding before it
+    int owner = -1;             // slot whose pool holds its buffers (set by the first turn)
+    double *rhs = nullptr;      // right-hand side, then the solution, on the device
+    void *state = nullptr;
+    RefineState st;
+    rtri_refine_info info{};
+    double t_start = 0.0, t_requeue = 0.0;
 };
+
+// a refined solve's state follows its right-hand side in one block
+size_t rhs_span(const Req &q)
+{
+    return (q.rhs_bytes + 255) & ~(size_t)255;
+}
 
 struct Factor {
     double *ptr = nullptr;
@@ -65,6 +86,8 @@ struct Factor {
 struct Work {
     std::vector<Req> reqs;
     bool batched = false;
+    bool cont = false;        // a later turn of a refined solve (admitted by its first)
+    bool finished = true;     // a refined solve's turn completed it
     size_t ws_extra = 0;      // device memory reserved for the slot's workspace growth
     size_t part_extra = 0;    // reserved for parts a factor object may make (work run alone)
     size_t tables = 0;        // upper bound of the batch tables (batched work)
@@ -78,6 +101,8 @@ struct rtri_server {
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Req> pending;
+    std::deque<Req> cont;   // refined solves between corrections, in re-queue order
+    int refining = 0;       // refined solves started and not finished (at most one per slot)
     std::unordered_map<uint64_t, Factor> factors;
     std::vector<rtri_completion> done;
     int64_t used = 0;       // held + reserved: what admission checks against the budget
@@ -119,7 +144,7 @@ constexpr size_t WS_MIN = (size_t)1 << 16;   // smallest workspace block a handl
 
 // upper bound of the workspace any handle may need for request r, whatever
 // its leaf size (the largest packed form is the 256-row one)
-size_t ws_bound(const rtri_request &r, int64_t ka)
+size_t ws_bound(const rtri_request &r, int64_t ka, bool state_in_ws)
 {
     const size_t mn = (size_t)r.m * (size_t)r.n;
     const size_t pack = (size_t)((ka + 255) / 256 + 1) * (size_t)pack_elems(256) + (size_t)ka * 136;
@@ -127,8 +152,10 @@ size_t ws_bound(const rtri_request &r, int64_t ka)
     const size_t split = may_split(ka) ? SPLIT_WS_BYTES : 0;
     if (r.precision == RTRI_PREC_F64)
         return 8 * pack + WS_MIN + (r.op == 1 ? mn * 8 + WS_MIN : 0) + split;
-    const size_t ln = (size_t)ws_ld(r.m) * (size_t)r.n;
-    return (size_t)ka * (size_t)ws_ld(ka) * 4 + ln * (4 + 8 * 4) + mn * 8 + 12 * pack + 10 * WS_MIN + split;
+    // the iteration state: in the handle's workspace when the solve runs in one
+    // turn, else the request's own (Req::state_bytes)
+    const size_t state = state_in_ws ? refine_state_bytes(r.m, r.n) : 0;
+    return (size_t)ka * (size_t)ws_ld(ka) * 4 + mn * 8 + 12 * pack + 10 * WS_MIN + split + state;
 }
 
 // device memory the slot's handle allocates to run q alone: for every
@@ -157,12 +184,13 @@ size_t alone_growth(const rtri_handle *h, const Req &q)
         if (r.op == 1)
             need[WS_SAVE] = save_bytes();
     } else {
-        // the refinement's matrices use the padded leading dimension ws_ld
-        const size_t ln = (size_t)ws_ld(r.m) * (size_t)r.n;
-        need[WS_PANEL32] = ln * 4;
-        need[WS_X] = need[WS_R0] = need[WS_R] = need[WS_W] = ln * 8;
+        // the norm's scalars and the residual product's panel copy are the
+        // handle's; so is the iteration state of a solve run in one turn (a
+        // re-queued one holds its own: Req::state_bytes)
         need[WS_SCALARS] = 64;
         need[WS_SAVE] = save_bytes();
+        if (q.refine && q.state_bytes == 0)
+            need[WS_REFINE] = refine_state_bytes(r.m, r.n);
     }
     size_t g = 0;
     for (int i = 0; i < WS_COUNT; ++i)
@@ -268,7 +296,7 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool 
         ws_extra = alone_growth(slot.h, q);
         part_extra = part_growth(slot.h, q);
     }
-    const int64_t need = (int64_t)(fbytes + q.rhs_bytes + ws_extra + part_extra);
+    const int64_t need = (int64_t)(fbytes + q.rhs_bytes + q.state_bytes + ws_extra + part_extra);
     while (s->used + need > s->cfg.hbm_budget)
         if (!evict_one(s, slot.stream))
             return false;
@@ -310,7 +338,7 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool 
     }
     f->refs += 1;
     f->last_use = ++s->use_clock;
-    s->used += (int64_t)(q.rhs_bytes + ws_extra + part_extra);
+    s->used += (int64_t)(q.rhs_bytes + q.state_bytes + ws_extra + part_extra);
     s->reserved += (int64_t)(ws_extra + part_extra);
     w.ws_extra += ws_extra;
     w.part_extra += part_extra;
@@ -328,10 +356,29 @@ bool consistent(rtri_server *s, const Req &q)
     return it == s->factors.end() || (it->second.ka == q.ka && it->second.uplo == q.r.uplo);
 }
 
-// called with the lock held; fills w (possibly empty)
+// the next turn of the refined solve re-queued first, if any (any slot may
+// run it: the previous turn ended with its stream synchronised)
+static bool take_cont(rtri_server *s, Work &w)
+{
+    if (s->cont.empty())
+        return false;
+    w.reqs.push_back(s->cont.front());
+    w.cont = true;
+    s->cont.pop_front();
+    return true;
+}
+
+// called with the lock held; fills w (possibly empty).  A refined solve's next
+// turn goes before the pending head if it was re-queued before that arrived
+// (arrival order), and whenever the head cannot be admitted now.
 void take_work(rtri_server *s, rtri_server::Slot &slot, Work &w)
 {
     const double t = now_s(s);
+    if (!s->cont.empty() && (s->pending.empty() || s->pending.front().r.t_arrival > t ||
+                             s->cont.front().t_requeue <= s->pending.front().r.t_arrival)) {
+        take_cont(s, w);
+        return;
+    }
     while (!s->pending.empty() && s->pending.front().r.t_arrival <= t) {
         Req &head = s->pending.front();
         if (!consistent(s, head)) {
@@ -339,19 +386,29 @@ void take_work(rtri_server *s, rtri_server::Slot &slot, Work &w)
             s->pending.pop_front();
             continue;
         }
-        if ((int64_t)(head.ka * head.ka * 8 + head.rhs_bytes + head.ws_bytes) > s->cfg.hbm_budget) {
+        if ((int64_t)(head.ka * head.ka * 8 + head.rhs_bytes + head.state_bytes + head.ws_bytes) > s->cfg.hbm_budget) {
             complete_now(s, head, RTRI_ERR_NOMEM);
             s->pending.pop_front();
             continue;
         }
         break;
     }
-    if (s->pending.empty() || s->pending.front().r.t_arrival > t)
+    if (s->pending.empty() || s->pending.front().r.t_arrival > t) {
+        take_cont(s, w);
         return;
+    }
     const Req head = s->pending.front();
-    if (!admit(s, slot, head, w, head.small))
+    if (head.refine && s->refining >= (int)s->slots.size()) {
+        take_cont(s, w);   // finish a started refinement before starting another
         return;
+    }
+    if (!admit(s, slot, head, w, head.small)) {
+        take_cont(s, w);
+        return;
+    }
     s->pending.pop_front();
+    if (head.refine)
+        s->refining += 1;
     if (!head.small)
         return;
     w.batched = true;
@@ -440,6 +497,89 @@ void execute(rtri_server *s, rtri_server::Slot &slot, Work &w, std::vector<rtri_
     }
 }
 
+// One turn of a refined solve: the first allocates its right-hand side
+// from the slot's pool in its stream order (that slot is the owner), with
+// refine_requeue the state in the same block (else it is the handle's
+// workspace), generates the right-hand side and runs refine_begin; a turn
+// then runs corrections to the end, or one with refine_requeue (each ends
+// with a stream synchronisation, for the two scalars it reads back, so the
+// next turn may run on any slot's stream).  When the refinement is done: X
+// into the right-hand side, the result to the host, a synchronisation, then
+// the block freed in the owner's stream order; the completion is recorded
+// (w.finished).
+void execute_refine(rtri_server *s, rtri_server::Slot &slot, Work &w, std::vector<rtri_completion> &out)
+{
+    rtri_handle *h = slot.h;
+    hipStream_t st = slot.stream;
+    Req &q = w.reqs[0];
+    const rtri_request &r = q.r;
+    constexpr double tol = 1e-12;
+    constexpr int max_iter = 30;
+    const Factor *fac;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        fac = &s->factors.at(r.factor_id);   // pinned by refs until the request completes
+    }
+    rtri_factor *fo = fac->fo[r.diag];
+    hipError_t e = hipSuccess;
+    int rc = RTRI_OK;
+    if (!w.cont) {
+        q.owner = slot.idx;
+        q.t_start = now_s(s);
+        if (fac->ready != nullptr)
+            e = hipStreamWaitEvent(st, fac->ready, 0);
+        const bool own = q.state_bytes != 0;
+        if (e == hipSuccess)
+            e = hipMallocFromPoolAsync((void **)&q.rhs, own ? rhs_span(q) + q.state_bytes : q.rhs_bytes, slot.pool,
+                                       st);
+        if (e == hipSuccess && !own)
+            e = ensure_ws(h, WS_REFINE, refine_state_bytes(r.m, r.n));
+        if (e == hipSuccess)
+            q.state = own ? reinterpret_cast<char *>(q.rhs) + rhs_span(q) : h->ws[WS_REFINE];
+        if (e == hipSuccess && rtri_synth_fill(h, RTRI_F64, 0, s->cfg.synth_seed, 2u, r.rhs_id, r.m, r.n, 0.0, q.rhs,
+                                               r.m) != RTRI_OK)
+            e = hipErrorUnknown;
+        if (e == hipSuccess) {
+            refine_state_place(q.st, q.state, r.m, r.n);
+            rc = factor_refine_begin(h, fo, r.side, r.trans, r.m, r.n, r.alpha, q.rhs, r.m, r.precision, tol, max_iter,
+                                     &q.info, q.st);
+        }
+    }
+    while (e == hipSuccess && rc == RTRI_OK && !q.st.done) {
+        rc = factor_refine_step(h, fo, r.side, r.trans, r.m, r.n, r.precision, tol, max_iter, &q.info, q.st);
+        if (s->cfg.refine_requeue)
+            break;
+    }
+    w.finished = e != hipSuccess || rc != RTRI_OK || q.st.done;
+    if (!w.finished) {
+        q.t_requeue = now_s(s);
+        return;
+    }
+    if (e == hipSuccess && rc == RTRI_OK) {
+        rc = refine_end(h, r.m, r.n, q.rhs, r.m, &q.info, q.st);
+        if (r.result != nullptr && rc == RTRI_OK)
+            e = hipMemcpyAsync(r.result, q.rhs, q.rhs_bytes, hipMemcpyDeviceToHost, st);
+    }
+    const hipError_t se = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = se;
+    // nothing reads it any more: back to the owner's pool
+    hipStream_t ost = q.owner >= 0 ? s->slots[q.owner].stream : st;
+    if (q.rhs != nullptr)
+        (void)hipFreeAsync(q.rhs, ost);
+    q.rhs = nullptr;
+    q.state = nullptr;
+    rtri_completion c{};
+    c.ticket = q.ticket;
+    c.status = e != hipSuccess ? RTRI_ERR_HIP : rc;
+    c.iters = q.info.iters;
+    c.eta = q.info.eta;
+    c.t_arrival = r.t_arrival;
+    c.t_start = q.t_start;
+    c.t_done = now_s(s);
+    out.push_back(c);
+}
+
 void worker(rtri_server *s, int idx)
 {
     rtri_server::Slot &slot = s->slots[idx];
@@ -450,13 +590,13 @@ void worker(rtri_server *s, int idx)
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
-                if (s->stopping && s->pending.empty())
+                if (s->stopping && s->pending.empty() && s->cont.empty())
                     return;
                 take_work(s, slot, w);
                 if (!w.reqs.empty())
                     break;
-                if (!s->pending.empty()) {
-                    const double wait = s->pending.front().r.t_arrival - now_s(s);
+                if (!s->pending.empty() || !s->cont.empty()) {
+                    const double wait = s->pending.empty() ? 0.0 : s->pending.front().r.t_arrival - now_s(s);
                     // not yet arrived, or waiting for memory: wake at the arrival or on any release
                     s->cv.wait_for(lk, std::chrono::duration<double>(wait > 0 ? std::min(wait, 0.01) : 0.001));
                 } else {
@@ -465,14 +605,17 @@ void worker(rtri_server *s, int idx)
             }
         }
         out.clear();
-        execute(s, slot, w, out);
+        if (!w.batched && w.reqs[0].refine)
+            execute_refine(s, slot, w, out);
+        else
+            execute(s, slot, w, out);
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            for (size_t i = 0; i < w.reqs.size(); ++i) {
+            for (size_t i = 0; i < w.reqs.size() && w.finished; ++i) {
                 const Req &q = w.reqs[i];
                 Factor &f = s->factors.at(q.r.factor_id);
                 f.refs -= 1;
-                s->used -= (int64_t)q.rhs_bytes;
+                s->used -= (int64_t)(q.rhs_bytes + q.state_bytes);
                 const int64_t vecs = q.r.side == RTRI_LEFT ? q.r.n : q.r.m;
                 if (out[i].status == RTRI_OK)
                     s->st.useful_flops += (double)q.ka * q.ka * (double)vecs;
@@ -490,8 +633,16 @@ void worker(rtri_server *s, int idx)
                 s->used += (int64_t)now - (int64_t)f.part_bytes - (int64_t)w.part_extra;
                 f.part_bytes = now;
             }
-            s->st.completed += (int64_t)w.reqs.size();
+            if (w.finished)
+                s->st.completed += (int64_t)w.reqs.size();
+            else
+                s->cont.push_back(w.reqs[0]);   // its next correction, in re-queue order
             s->st.launches += 1;
+            if (!w.batched && w.reqs[0].refine) {
+                s->st.refine_turns += 1;
+                if (w.finished)
+                    s->refining -= 1;
+            }
             if (w.batched) {
                 s->st.batched_launches += 1;
                 s->st.batched_requests += (int64_t)w.reqs.size();
@@ -500,7 +651,8 @@ void worker(rtri_server *s, int idx)
             s->st.hbm_in_use = s->used - s->reserved;
             s->st.hbm_peak = std::max(s->st.hbm_peak, s->st.hbm_in_use);
             s->done.insert(s->done.end(), out.begin(), out.end());
-            s->outstanding -= (int64_t)w.reqs.size();
+            if (w.finished)
+                s->outstanding -= (int64_t)w.reqs.size();
         }
         s->cv.notify_all();
     }
@@ -609,8 +761,11 @@ int rtri_server_submit(rtri_server *s, const rtri_request *r, uint64_t *ticket)
     q.r = *r;
     q.ka = r->side == RTRI_LEFT ? r->m : r->n;
     q.rhs_bytes = (size_t)std::max<int64_t>(1, r->m * r->n) * 8;
-    q.ws_bytes = ws_bound(*r, q.ka);
+    const bool requeue = s->cfg.refine_requeue != 0;
     q.small = r->precision == RTRI_PREC_F64 && q.ka <= s->cfg.small_max && r->m > 0 && r->n > 0;
+    q.refine = r->precision != RTRI_PREC_F64 && r->op == 0 && r->alpha != 0.0 && r->m > 0 && r->n > 0;
+    q.state_bytes = q.refine && requeue ? refine_state_bytes(r->m, r->n) + (rhs_span(q) - q.rhs_bytes) : 0;
+    q.ws_bytes = ws_bound(*r, q.ka, q.refine && !requeue);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         q.ticket = s->next_ticket++;

@@ -101,6 +101,8 @@ def test_serving_alone_vs_mix(rt, h, orc):
     assert all(c["status"] == 0 for c in comps), [c for c in comps if c["status"] != 0][:3]
     assert stats["batched_launches"] > 0 and stats["batched_requests"] > stats["batched_launches"]
     assert stats["factor_hits"] > 0
+    # without refine_requeue a refined solve runs to the end in one turn
+    assert stats["refine_turns"] == sum(1 for r, _ in results.values() if r["precision"])
     for c in comps:
         assert c["t_done"] >= c["t_start"] >= c["t_arrival"] - 1e-6
     for tk, (r, res) in results.items():
@@ -116,6 +118,42 @@ def test_serving_alone_vs_mix(rt, h, orc):
             assert e <= (1e-12 if r["precision"] else 1e-13), (r, e)
         else:
             assert orc.trmm_eta("L", r["uplo"], r["trans"], "N", 1.0, A, B, res) <= 1e-13
+
+
+@pytest.mark.parametrize("slots", [1, 3])
+def test_serving_refined_requeued_per_correction(rt, h, orc, slots):
+    """With refine_requeue, refined (mixed-precision) solves run one
+    correction per turn and re-enter the queue between turns: each refined
+    request takes as many turns as it makes corrections (the first also sets
+    up its residual); with one slot and FP64 requests arriving throughout,
+    FP64 work completes between the corrections of a refined request; with
+    several, a solve's turns may run on different slots.  Every result is
+    still bitwise the result of the same request alone."""
+    g = synth.rng(synth.W_SERVE, 3)
+    fac = [(3000 + f, int(synth.loguniform_int(g, 256, 1536, 1)[0]), "L" if f % 2 else "U") for f in range(12)]
+    reqs = []
+    for i in range(60):
+        fid, ka, uplo = fac[i % 12]
+        prec = (1 if i % 6 == 0 else 2) if i % 3 == 0 else 0
+        reqs.append(dict(op="trsm", side="L", uplo=uplo, trans="N", diag="N", m=ka, n=int(g.integers(1, 96)),
+                         alpha=1.0, precision=prec, factor_id=fid, rhs_id=70000 + i))
+    say("serving refined re-queue", len(reqs), "slots", slots)
+    results, comps, stats = _run_stream(rt, reqs, rate=3000.0, slots=slots, max_batch=8, small_max=128,
+                                        refine_requeue=True)
+    assert len(comps) == len(reqs)
+    assert all(c["status"] == 0 for c in comps), [c for c in comps if c["status"] != 0][:3]
+    by_ticket = {c["ticket"]: c for c in comps}
+    refined = [(tk, r) for tk, (r, _) in results.items() if r["precision"]]
+    assert stats["refine_turns"] == sum(by_ticket[tk]["iters"] for tk, _ in refined)
+    assert all(by_ticket[tk]["iters"] >= 1 for tk, _ in refined)
+    # some FP64 request started after a refined request's first turn and
+    # completed before its last (the slot ran it between two corrections)
+    interleaved = any(by_ticket[tk]["t_start"] < c["t_start"] and c["t_done"] < by_ticket[tk]["t_done"]
+                      for tk, r in refined if by_ticket[tk]["iters"] >= 2
+                      for c in comps if c["iters"] == 0)
+    assert interleaved or slots > 1
+    for tk, (r, res) in results.items():
+        assert np.array_equal(res, _alone(rt, h, r)), r
 
 
 def test_serving_small_budget(rt, h):
