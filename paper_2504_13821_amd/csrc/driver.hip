@@ -426,6 +426,20 @@ static hipError_t run_grouped(rtri_handle *h, const PlanIn &p, const std::vector
             return dma[(size_t)x] > dma[(size_t)y];
         return work[(size_t)x] > work[(size_t)y];
     });
+    // The 64x64 tiles of a launch are mostly resident together (several
+    // workgroups per CU), so where the dispatcher places them, not the order
+    // they finish in, decides each CU's load.  Workgroup i lands on CU
+    // i mod (CU count) when the launch fits: reversing every other round of
+    // that many tiles gives each CU about the same work (a triangle's tiles
+    // range from a few K steps to the whole order).
+    if (!g16) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            for (size_t r0 = (size_t)cus; r0 < order.size(); r0 += 2 * (size_t)cus)
+                std::reverse(order.begin() + (std::ptrdiff_t)r0,
+                             order.begin() + (std::ptrdiff_t)std::min(order.size(), r0 + (size_t)cus));
+    }
     std::vector<int> start(count.size(), 0);
     std::vector<GroupTile> tiles;
     tiles.reserve(order.size());

@@ -81,13 +81,16 @@ template <typename T, bool TP, bool TQ, bool VEC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void grouped_kernel(
     const GemmDesc *descs, const GroupEntry *ents, const GroupTile *tiles)
 {
-    __shared__ __attribute__((aligned(16))) T As[2 * lds_elems<T, 64, TP>()];
-    __shared__ __attribute__((aligned(16))) T Bs[2 * lds_elems<T, 64, !TQ>()];
+    // FP32: two k-steps per LDS stage (a 64x64 FP32 k-step is too short to
+    // cover one barrier and one prefetch)
+    constexpr int KS = sizeof(T) == 4 ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) T As[2 * lds_elems<T, 64, TP, KS>()];
+    __shared__ __attribute__((aligned(16))) T Bs[2 * lds_elems<T, 64, !TQ, KS>()];
     const GroupTile tl = tiles[blockIdx.x];
     for (int e = tl.first; e < tl.first + tl.count; ++e) {
         const GroupEntry en = ents[e];
         const GemmDesc g = descs[en.desc];
-        gemm_tile<T, 64, 64, TP, TQ, VEC, 2, 2, sizeof(T) == 8>(g, en.m0, en.n0, As, Bs);
+        gemm_tile<T, 64, 64, TP, TQ, VEC, 2, 2, sizeof(T) == 8, KS>(g, en.m0, en.n0, As, Bs);
     }
 }
 

@@ -67,24 +67,29 @@ __device__ __forceinline__ void st4(float *p, float4_t v) { *reinterpret_cast<fl
 // The paddings make the MFMA fragment reads bank-conflict free: 16-byte reads
 // of k pairs in the KC layout, 8-byte reads of 16 consecutive rows per lane
 // group (groups 1152 B apart) in the MC layout.
-template <typename T> constexpr int lds_sk() { return sizeof(T) == 8 ? BK + 2 : BK + 4; }
-template <int R> constexpr int lds_sm() { return R + 16; }
-template <typename T, int R, bool KC> constexpr int lds_elems() { return KC ? R * lds_sk<T>() : BK * lds_sm<R>(); }
-
-template <typename T, int R, bool KC>
-__device__ __forceinline__ T lds_at(const T *ls, int row, int k)
+// A stage may hold KS consecutive k-steps (KS * BK values along K).
+template <typename T, int KS = 1> constexpr int lds_sk() { return sizeof(T) == 8 ? KS * BK + 2 : KS * BK + 4; }
+template <typename T, int R> constexpr int lds_sm() { return sizeof(T) == 8 ? R + 16 : R + 4; }
+template <typename T, int R, bool KC, int KS = 1> constexpr int lds_elems()
 {
-    return KC ? ls[row * lds_sk<T>() + k] : ls[k * lds_sm<R>() + row];
+    return KC ? R * lds_sk<T, KS>() : KS * BK * lds_sm<T, R>();
 }
 
-// Loader of one operand tile (R rows of the M or N dimension, BK along K) into
+template <typename T, int R, bool KC, int KS = 1>
+__device__ __forceinline__ T lds_at(const T *ls, int row, int k)
+{
+    return KC ? ls[row * lds_sk<T, KS>() + k] : ls[k * lds_sm<T, R>() + row];
+}
+
+// Loader of one operand tile (R rows of the M or N dimension, KS * BK along K) into
 // registers, then into LDS as Ls[row][k] (k contiguous, padded rows).
 //   KC = true : element (row, k) at base[k + row*ld]   (k contiguous in memory)
 //   KC = false: element (row, k) at base[row + k*ld]   (rows contiguous in memory)
-template <typename T, int R, bool KC, bool VEC, int NTH = NT>
+template <typename T, int R, bool KC, bool VEC, int NTH = NT, int KS = 1>
 struct TileLoader {
+    static constexpr int BKS = KS * BK;                     // k values per stage
     static constexpr int W = 16 / sizeof(T);               // elements per 16-byte load
-    static constexpr int PER = R * BK / NTH;                // elements per thread
+    static constexpr int PER = R * BKS / NTH;               // elements per thread
     static constexpr int NV = PER / W;                      // 16-byte loads per thread
     static_assert(PER % W == 0, "tile too small");
     T reg[PER];
@@ -93,8 +98,8 @@ struct TileLoader {
     {
         const int e = v * NTH + tid;                         // index of the W-vector
         if (KC) {
-            k = (e % (BK / W)) * W;
-            row = e / (BK / W);
+            k = (e % (BKS / W)) * W;
+            row = e / (BKS / W);
         } else {
             row = (e % (R / W)) * W;
             k = e / (R / W);
@@ -149,7 +154,7 @@ struct TileLoader {
         for (int v = 0; v < NV; ++v) {
             int row, k;
             coords(v, tid, row, k);
-            T *dst = KC ? lds + row * lds_sk<T>() + k : lds + k * lds_sm<R>() + row;
+            T *dst = KC ? lds + row * lds_sk<T, KS>() + k : lds + k * lds_sm<T, R>() + row;
 #pragma unroll
             for (int w = 0; w < W; ++w)
                 dst[w] = reg[v * W + w];
@@ -165,14 +170,18 @@ struct TileLoader {
 // that step's operand loads) instead of in the epilogue, for short K where the
 // epilogue's reads would otherwise follow all the MFMA work (FP64: the FP32
 // k-step is too short to cover the read, measured slower there).
-template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC, int WM = 2, int WN = 2, bool CPF = false>
+// KS: k-steps per LDS stage (one barrier and one prefetch per stage); the
+// MFMA sequence, and so every result, is that of KS = 1.
+template <typename T, int BM, int BN, bool TP, bool TQ, bool VEC, int WM = 2, int WN = 2, bool CPF = false,
+          int KS = 1>
 __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t n0, T *As, T *Bs,
                                           int tid = threadIdx.x)
 {
     constexpr int NTH = 64 * WM * WN;
     constexpr int FM = BM / WM / 16, FN = BN / WN / 16;
+    constexpr int BKS = KS * BK;
     constexpr bool KCA = TP, KCB = !TQ;           // operand layouts (see lds_at)
-    constexpr int EA = lds_elems<T, BM, KCA>(), EB = lds_elems<T, BN, KCB>();
+    constexpr int EA = lds_elems<T, BM, KCA, KS>(), EB = lds_elems<T, BN, KCB, KS>();
     using AccT = Acc<T>;
     using V = typename AccT::V;
     const int wave = tid / 64, lane = tid % 64;
@@ -189,8 +198,8 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
     const int rlim_n = (int)min<int64_t>(BN, g.N - n0);
     const bool full_mn = rlim_m == BM && rlim_n == BN;
 
-    TileLoader<T, BM, TP, VEC, NTH> la;
-    TileLoader<T, BN, !TQ, VEC, NTH> lb;
+    TileLoader<T, BM, TP, VEC, NTH, KS> la;
+    TileLoader<T, BN, !TQ, VEC, NTH, KS> lb;
 
     V acc[FM][FN];
 #pragma unroll
@@ -200,7 +209,7 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
             acc[i][j] = V{0, 0, 0, 0};
 
     const int64_t K = g.K;
-    const int nk = (int)((K + BK - 1) / BK);
+    const int nk = (int)((K + BKS - 1) / BKS);
 
     // C block (i, j) of this lane: rows 4*lg .. 4*lg+3 of its 16-row block
     T *C = static_cast<T *>(g.C);
@@ -214,14 +223,14 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
     V cpre[CPF ? FM : 1][CPF ? FN : 1];
 
     auto load_step = [&](int kt) {
-        const int64_t k0 = (int64_t)kt * BK;
+        const int64_t k0 = (int64_t)kt * BKS;
         const T *pa = TP ? Pt + k0 : Pt + k0 * ldp;
         const T *pb = TQ ? Qt + k0 * ldq : Qt + k0;
-        if (full_mn && k0 + BK <= K) {
+        if (full_mn && k0 + BKS <= K) {
             la.load_full(pa, ldp, tid);
             lb.load_full(pb, ldq, tid);
         } else {
-            const int klim = (int)min<int64_t>(BK, K - k0);
+            const int klim = (int)min<int64_t>(BKS, K - k0);
             la.load_edge(pa, ldp, tid, rlim_m, klim);
             lb.load_edge(pb, ldq, tid, rlim_n, klim);
         }
@@ -250,25 +259,32 @@ __device__ __forceinline__ void gemm_tile(const GemmDesc &g, int64_t m0, int64_t
         // (one 16-byte read for FP64)
         const int ra = wm * (BM / WM) + lrow<T>(lc), rbq = wn * (BN / WN) + lc;
 #pragma unroll
-        for (int t2 = 0; t2 < 4; t2 += 2) {
-            T fa[FM][2], fb[FN][2];
+        for (int h = 0; h < KS; ++h) {
+            // a k-step wholly past K adds nothing: skipped (uniform)
+            if (h > 0 && (int64_t)kt * BKS + h * BK >= K)
+                break;
 #pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                fa[i][0] = lds_at<T, BM, KCA>((As + cur * EA), ra + i * 16, 4 * lg + t2);
-                fa[i][1] = lds_at<T, BM, KCA>((As + cur * EA), ra + i * 16, 4 * lg + t2 + 1);
+            for (int t2 = 0; t2 < 4; t2 += 2) {
+                T fa[FM][2], fb[FN][2];
+                const int kk = h * BK + 4 * lg + t2;
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    fa[i][0] = lds_at<T, BM, KCA, KS>((As + cur * EA), ra + i * 16, kk);
+                    fa[i][1] = lds_at<T, BM, KCA, KS>((As + cur * EA), ra + i * 16, kk + 1);
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    fb[j][0] = lds_at<T, BN, KCB, KS>((Bs + cur * EB), rbq + j * 16, kk);
+                    fb[j][1] = lds_at<T, BN, KCB, KS>((Bs + cur * EB), rbq + j * 16, kk + 1);
+                }
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            acc[i][j] = AccT::mfma(fa[i][t], fb[j][t], acc[i][j]);
             }
-#pragma unroll
-            for (int j = 0; j < FN; ++j) {
-                fb[j][0] = lds_at<T, BN, KCB>((Bs + cur * EB), rbq + j * 16, 4 * lg + t2);
-                fb[j][1] = lds_at<T, BN, KCB>((Bs + cur * EB), rbq + j * 16, 4 * lg + t2 + 1);
-            }
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        acc[i][j] = AccT::mfma(fa[i][t], fb[j][t], acc[i][j]);
         }
 
         if (kt + 1 < nk) {
