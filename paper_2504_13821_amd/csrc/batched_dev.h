@@ -37,9 +37,13 @@ struct BItem {
 
 // 64-row leaves run on the matrix cores (canonical staging + A-operand tiles),
 // 16/32-row leaves as one-lane-per-vector substitution in wavefront 0
+// FP32 GEMM tiles stage two k-steps per LDS buffer (same MFMA sequence)
+template <typename T> constexpr int gemm_ks() { return sizeof(T) == 4 ? 2 : 1; }
+
 template <typename T, int NB>
 struct Smem {
-    static constexpr int GEMM = 2 * gk::lds_elems<T, 64, true>() + 2 * gk::lds_elems<T, 64, false>() + 64;
+    static constexpr int GEMM =
+        2 * gk::lds_elems<T, 64, true, gemm_ks<T>()>() + 2 * gk::lds_elems<T, 64, false, gemm_ks<T>()>() + 64;
     static constexpr int LEAF = NB == 64 ? lk::tri_n<64>() + mk::ntiles<64>() * mk::TE
                                          : lk::tri_n<NB>() + lk::WAVE * (NB + 1);
     static constexpr int N = GEMM > LEAF ? GEMM : LEAF;
@@ -48,7 +52,7 @@ struct Smem {
 template <typename T, bool TP, bool TQ>
 __device__ __forceinline__ void run_gemm(const GemmDesc &g, T *smem)
 {
-    constexpr int EA = gk::lds_elems<T, 64, TP>();
+    constexpr int EA = gk::lds_elems<T, 64, TP, gemm_ks<T>()>();
     T *As = smem;
     T *Bs = smem + 2 * EA;
     // an opaque copy of the thread index: the offsets derived from it are
@@ -58,7 +62,7 @@ __device__ __forceinline__ void run_gemm(const GemmDesc &g, T *smem)
     asm volatile("" : "+v"(tid));
     for (int64_t m0 = 0; m0 < g.M; m0 += 64)
         for (int64_t n0 = 0; n0 < g.N; n0 += 64)
-            gk::gemm_tile<T, 64, 64, TP, TQ, false>(g, m0, n0, As, Bs, tid);
+            gk::gemm_tile<T, 64, 64, TP, TQ, false, 2, 2, false, gemm_ks<T>()>(g, m0, n0, As, Bs, tid);
 }
 
 // The chunk's vectors [v0, v0 + 64) against one diagonal block of 64 rows, on
