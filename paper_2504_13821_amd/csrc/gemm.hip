@@ -49,8 +49,10 @@ gemm_kernel(GemmDesc g, int tiles_m, int tiles_n, int64_t kslice, T *part, int64
         g.s = 1.0;
     }
     constexpr bool KCA = TP, KCB = !TQ;
-    __shared__ __attribute__((aligned(16))) T As[2 * lds_elems<T, BM, KCA>()];
-    __shared__ __attribute__((aligned(16))) T Bs[2 * lds_elems<T, BN, KCB>()];
+    // FP32 64x64 tiles: two k-steps per LDS stage (same MFMA sequence)
+    constexpr int KS = sizeof(T) == 4 && BM == 64 && BN == 64 ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) T As[2 * lds_elems<T, BM, KCA, KS>()];
+    __shared__ __attribute__((aligned(16))) T Bs[2 * lds_elems<T, BN, KCB, KS>()];
 
     // XCD-aware tile order: consecutive workgroup ids are dealt round-robin to
     // the 8 XCDs, so regroup them so each XCD walks a contiguous range of
@@ -69,8 +71,8 @@ gemm_kernel(GemmDesc g, int tiles_m, int tiles_n, int64_t kslice, T *part, int64
     const int tm = first_m + in_band % gsize;
     const int tn = in_band / gsize;
     // the 64x64 tile serves the short-K updates: FP64 reads C during the K loop
-    gemm_tile<T, BM, BN, TP, TQ, VEC, WM, WN, BM == 64 && sizeof(T) == 8>(g, (int64_t)tm * BM, (int64_t)tn * BN,
-                                                                           As, Bs);
+    gemm_tile<T, BM, BN, TP, TQ, VEC, WM, WN, BM == 64 && sizeof(T) == 8, KS>(g, (int64_t)tm * BM,
+                                                                               (int64_t)tn * BN, As, Bs);
 }
 
 // Grouped updates (launch_gemm_grouped): the workgroup's tile takes its
