@@ -34,7 +34,7 @@ HBM_PEAK = 8000.0                                                    # GB/s
 # PMC passes (FETCH_SIZE x 2 + WRITE_SIZE x 1, factors from a 2 GiB copy in the
 # same process; profiles/gemm_f64_16384_traffic.txt).  Valid only for the GEMM
 # sources they were taken on: reported as null once those change.
-GEMM_TRAFFIC = {"bytes_per_launch": 1.0385e9, "sources_sha256_16": "9f98194aa2c2435d"}
+GEMM_TRAFFIC = {"bytes_per_launch": 1.0394e9, "sources_sha256_16": "6ee4c57ad51e1707"}
 
 
 def gemm_sources_digest():
