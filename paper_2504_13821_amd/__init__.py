@@ -115,7 +115,7 @@ rtri_synth_fill = _sig("rtri_synth_fill", _int, _vp, _int, _int, ctypes.c_uint64
 
 class ServerCfg(ctypes.Structure):
     _fields_ = [("slots", _int), ("hbm_budget", _i64), ("max_batch", _int), ("small_max", _i64),
-                ("synth_seed", ctypes.c_uint64), ("refine_requeue", _int)]
+                ("synth_seed", ctypes.c_uint64), ("refine_requeue", _int), ("mixed_batch", _int)]
 
 
 class Request(ctypes.Structure):
@@ -705,8 +705,9 @@ class Server:
     Fortran order) that receives the result."""
 
     def __init__(self, slots=4, hbm_budget=64 << 30, max_batch=256, small_max=1024, seed=250413821,
-                 refine_requeue=False):
-        cfg = ServerCfg(slots, hbm_budget, max_batch, small_max, seed, 1 if refine_requeue else 0)
+                 refine_requeue=False, mixed_batch=False):
+        cfg = ServerCfg(slots, hbm_budget, max_batch, small_max, seed, 1 if refine_requeue else 0,
+                        1 if mixed_batch else 0)
         p = _vp()
         check(rtri_server_create(ctypes.byref(cfg), ctypes.byref(p)), "rtri_server_create")
         self._s = p

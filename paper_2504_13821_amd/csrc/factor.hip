@@ -254,6 +254,12 @@ int factor_refine_begin(rtri_handle *h, rtri_factor *f, int side, int trans, int
                         tol, max_iter, info, prep, st);
 }
 
+int factor_refine_prep(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, int precision,
+                       MixedPrep &prep)
+{
+    return refine_prep(h, f, side, trans, m, n, precision, prep);
+}
+
 int factor_refine_step(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, int precision,
                        double tol, int max_iter, rtri_refine_info *info, RefineState &st)
 {

@@ -194,6 +194,7 @@ struct RefineState {
     int iters = 0;
     bool converged = false, stalled = false, done = false;
     bool lo_packed = false, mul_packed = false;   // the plans' blocks packed (skip from now on)
+    double scale = 1.0;   // this correction's power-of-two scale s (D = R / s)
 };
 size_t refine_state_bytes(int64_t m, int64_t n);
 void refine_state_place(RefineState &st, void *mem, int64_t m, int64_t n);
@@ -205,6 +206,26 @@ int refine_step(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m,
                 RefineState &st);
 int refine_end(rtri_handle *h, int64_t m, int64_t n, double *B, int64_t ldb, rtri_refine_info *info,
                const RefineState &st);
+// The same phases split into what is enqueued on h's stream and the host
+// halves that read the scalars back once the caller has synchronised it, for
+// callers that run several refinements in lockstep (refine_begin and
+// refine_step are these with their own solve, product and synchronisation):
+//   begin: refine_begin_enqueue, sync, refine_begin_finish (host4: 4 words);
+//   step:  refine_step_convert (D = R / s), the low-precision solve of D,
+//          refine_step_update (X += s D, W = X), W := op(A) W in FP64,
+//          refine_step_resid (R, eta, max |R|; host2: 2 words), sync,
+//          refine_step_finish.
+hipError_t refine_begin_enqueue(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n,
+                                double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                                const MixedPrep &prep, RefineState &st, unsigned long long *host4);
+void refine_begin_finish(const unsigned long long *host4, double tol, int max_iter, rtri_refine_info *info,
+                         const MixedPrep &prep, RefineState &st);
+hipError_t refine_step_convert(rtri_handle *h, int64_t m, int64_t n, RefineState &st);
+hipError_t refine_step_update(rtri_handle *h, int64_t m, int64_t n, RefineState &st);
+hipError_t refine_step_resid(rtri_handle *h, int side, int64_t m, int64_t n, RefineState &st,
+                             unsigned long long *host2);
+void refine_step_finish(const unsigned long long *host2, double tol, int max_iter, rtri_refine_info *info,
+                        RefineState &st);
 // the refined solve against a factor object in phases (factor.hip): arguments
 // as rtri_factor_trsm checks them, m, n > 0, alpha != 0, a mixed precision;
 // the factor's parts (copy of A, packed blocks, |op(A)|, residue planes) are
@@ -214,6 +235,10 @@ int factor_refine_begin(rtri_handle *h, rtri_factor *f, int side, int trans, int
                         RefineState &st);
 int factor_refine_step(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, int precision,
                        double tol, int max_iter, rtri_refine_info *info, RefineState &st);
+// the factor's parts a refined solve reads (GEMM-type copy, packed blocks,
+// |op(A)|, residue planes), made if missing, for the split phases above
+int factor_refine_prep(rtri_handle *h, rtri_factor *f, int side, int trans, int64_t m, int64_t n, int precision,
+                       MixedPrep &prep);
 // lines of op(A) (side L) or op(A)^T (side R) summed into out[0] (anorm)
 hipError_t launch_mixed_norm(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t ka, const double *A,
                              int64_t lda, unsigned long long *out);

@@ -130,9 +130,9 @@ static bool refine_more(const RefineState &st, int max_iter)
     return !st.converged && !st.stalled && st.iters < max_iter && st.rmax > 0.0 && std::isfinite(st.rmax);
 }
 
-int refine_begin(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
-                 const double *A, int64_t lda, const double *B, int64_t ldb, double tol, int max_iter,
-                 rtri_refine_info *info, const MixedPrep &prep, RefineState &st)
+hipError_t refine_begin_enqueue(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n,
+                                double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                                const MixedPrep &prep, RefineState &st, unsigned long long *host4)
 {
     hipStream_t st_ = h->stream;
     const int64_t ka = side == RTRI_LEFT ? m : n;
@@ -148,19 +148,40 @@ int refine_begin(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m
     // first correction is assigned to X rather than added
     if (e == hipSuccess)
         e = other(8.0 * mn, [&] { return launch_max_abs(st.R0, st.ld, m, n, st.sc + 1, st_); });
-    unsigned long long host[4];
     if (e == hipSuccess)
-        e = hipMemcpyAsync(host, st.sc, sizeof host, hipMemcpyDeviceToHost, st_);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(st_);
-    if (e != hipSuccess)
-        return hip_fail(h, e);
-    st.anorm = prep.have_anorm ? prep.anorm : from_bits(host[2]);
-    st.rmax = from_bits(host[1]);
+        e = hipMemcpyAsync(host4, st.sc, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st_);
+    return e;
+}
+
+void refine_begin_finish(const unsigned long long *host4, double tol, int max_iter, rtri_refine_info *info,
+                         const MixedPrep &prep, RefineState &st)
+{
+    st.anorm = prep.have_anorm ? prep.anorm : from_bits(host4[2]);
+    st.rmax = from_bits(host4[1]);
     if (info != nullptr)
         info->anorm = st.anorm;
-    // residual product from exact INT8 products: op(A)'s residue planes once
     st.oz = prep.oz_planes;
+    st.eta = st.rmax == 0.0 ? 0.0 : INFINITY;
+    st.eta_prev = INFINITY;
+    st.iters = 0;
+    st.converged = st.eta <= tol;
+    st.stalled = false;
+    st.done = !refine_more(st, max_iter);
+}
+
+int refine_begin(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, double alpha,
+                 const double *A, int64_t lda, const double *B, int64_t ldb, double tol, int max_iter,
+                 rtri_refine_info *info, const MixedPrep &prep, RefineState &st)
+{
+    const int64_t ka = side == RTRI_LEFT ? m : n;
+    unsigned long long host[4];
+    hipError_t e = refine_begin_enqueue(h, side, uplo, tr, diag, m, n, alpha, A, lda, B, ldb, prep, st, host);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return hip_fail(h, e);
+    refine_begin_finish(host, tol, max_iter, info, prep, st);
+    // residual product from exact INT8 products: op(A)'s residue planes once
     if (h->residual == 1 && ozaki_nmod(ka) > 0 && st.oz == nullptr) {
         e = ensure_ws(h, WS_OZA, ozaki_factor_bytes(side, ka));
         if (e == hipSuccess)
@@ -169,25 +190,66 @@ int refine_begin(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m
             return hip_fail(h, e);
         st.oz = h->ws[WS_OZA];
     }
-    st.eta = st.rmax == 0.0 ? 0.0 : INFINITY;
-    st.eta_prev = INFINITY;
-    st.iters = 0;
-    st.converged = st.eta <= tol;
-    st.stalled = false;
-    st.done = !refine_more(st, max_iter);
     return RTRI_OK;
+}
+
+hipError_t refine_step_convert(rtri_handle *h, int64_t m, int64_t n, RefineState &st)
+{
+    const size_t mn = (size_t)m * (size_t)n;
+    st.scale = std::ldexp(1.0, (int)std::ceil(std::log2(st.rmax)));
+    const double *Rk = st.iters == 0 ? st.R0 : st.R;
+    return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, 12.0 * mn, [&] {
+        return launch_convert(ElemT::F64, ElemT::F32, Rk, st.ld, st.D, st.ld, m, n, 1.0 / st.scale, h->stream);
+    });
+}
+
+hipError_t refine_step_update(rtri_handle *h, int64_t m, int64_t n, RefineState &st)
+{
+    const size_t mn = (size_t)m * (size_t)n;
+    // X += s D (X = s D the first time), and W = X for the residual's product (one pass)
+    const bool assign = st.iters == 0;
+    return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, (assign ? 20.0 : 28.0) * mn, [&] {
+        return launch_add_scaled(st.X, st.ld, st.D, st.ld, m, n, st.scale, assign, st.W, st.ld, h->stream);
+    });
+}
+
+hipError_t refine_step_resid(rtri_handle *h, int side, int64_t m, int64_t n, RefineState &st,
+                             unsigned long long *host2)
+{
+    const size_t mn = (size_t)m * (size_t)n;
+    hipError_t e = launch_zero_u64(st.sc, 2, h->stream);
+    if (e == hipSuccess)
+        e = timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, 32.0 * mn, [&] {
+            return launch_resid_eta(st.R0, st.ld, st.W, st.ld, st.R, st.ld, st.X, st.ld, m, n, side == RTRI_LEFT,
+                                    st.anorm, st.sc, h->stream);
+        });
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host2, st.sc, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, h->stream);
+    return e;
+}
+
+void refine_step_finish(const unsigned long long *host2, double tol, int max_iter, rtri_refine_info *info,
+                        RefineState &st)
+{
+    st.eta = from_bits(host2[0]);
+    st.rmax = from_bits(host2[1]);
+    if (info != nullptr && st.iters < 32)
+        info->eta_hist[st.iters] = st.eta;
+    ++st.iters;
+    if (st.eta <= tol)
+        st.converged = true;
+    else if (!(st.eta <= 0.5 * st.eta_prev))   // stagnation (or NaN)
+        st.stalled = true;
+    st.eta_prev = st.eta;
+    st.done = !refine_more(st, max_iter);
 }
 
 int refine_step(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m, int64_t n, const double *A,
                 int64_t lda, ElemT gt, double tol, int max_iter, rtri_refine_info *info, const MixedPrep &prep,
                 RefineState &st)
 {
-    hipStream_t st_ = h->stream;
-    const bool left = side == RTRI_LEFT;
-    const int64_t ka = left ? m : n;
-    const size_t mn = (size_t)m * (size_t)n;
+    const int64_t ka = side == RTRI_LEFT ? m : n;
     const int64_t ld = st.ld;
-    auto other = [&](double bytes, auto &&f) { return timed(h, RTRI_KCLASS_OTHER, RTRI_F64, 0.0, bytes, f); };
 
     PlanIn lo = mixed_lo_plan(h, side, uplo, tr, diag, m, n, gt, A, lda);
     lo.B = reinterpret_cast<char *>(st.D);
@@ -206,19 +268,14 @@ int refine_step(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m,
     mul.skip_pack = st.mul_packed;
     const bool int8_resid = h->residual == 1 && ozaki_nmod(ka) > 0 && st.oz != nullptr;
 
-    const double s = std::ldexp(1.0, (int)std::ceil(std::log2(st.rmax)));
-    const double *Rk = st.iters == 0 ? st.R0 : st.R;
-    hipError_t e = other(12.0 * mn, [&] { return launch_convert(ElemT::F64, ElemT::F32, Rk, ld, st.D, ld, m, n, 1.0 / s, st_); });
+    hipError_t e = refine_step_convert(h, m, n, st);
     if (e != hipSuccess)
         return hip_fail(h, e);
     int rc = run_plan(h, lo);
     if (rc != RTRI_OK)
         return rc;
     st.lo_packed = true;
-    // X += s D (X = s D the first time), and W = X for the residual's product (one pass)
-    const bool assign = st.iters == 0;
-    e = other((assign ? 20.0 : 28.0) * mn,
-              [&] { return launch_add_scaled(st.X, ld, st.D, ld, m, n, s, assign, st.W, ld, st_); });
+    e = refine_step_update(h, m, n, st);
     if (e != hipSuccess)
         return hip_fail(h, e);
     if (int8_resid) {
@@ -229,29 +286,13 @@ int refine_step(rtri_handle *h, int side, int uplo, int tr, int diag, int64_t m,
     }
     if (rc != RTRI_OK)
         return rc;
-    e = launch_zero_u64(st.sc, 2, st_);
-    if (e == hipSuccess)
-        e = other(32.0 * mn, [&] {
-            return launch_resid_eta(st.R0, ld, st.W, ld, st.R, ld, st.X, ld, m, n, left, st.anorm, st.sc, st_);
-        });
     unsigned long long host[2];
+    e = refine_step_resid(h, side, m, n, st, host);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(host, st.sc, sizeof host, hipMemcpyDeviceToHost, st_);
-    if (e == hipSuccess)
-        e = hipStreamSynchronize(st_);
+        e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess)
         return hip_fail(h, e);
-    st.eta = from_bits(host[0]);
-    st.rmax = from_bits(host[1]);
-    if (info != nullptr && st.iters < 32)
-        info->eta_hist[st.iters] = st.eta;
-    ++st.iters;
-    if (st.eta <= tol)
-        st.converged = true;
-    else if (!(st.eta <= 0.5 * st.eta_prev))   // stagnation (or NaN)
-        st.stalled = true;
-    st.eta_prev = st.eta;
-    st.done = !refine_more(st, max_iter);
+    refine_step_finish(host, tol, max_iter, info, st);
     return RTRI_OK;
 }
 

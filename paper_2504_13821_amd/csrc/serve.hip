@@ -31,6 +31,7 @@
 // admitted as slots and memory free up, and their work overlaps on the device.
 // Per request the arithmetic is the same alone or in any batch (the batched
 // kernel reproduces the single-call path bit for bit).
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -54,6 +55,7 @@ struct Req {
     bool small;
     // a refined solve run in phases: one correction per turn, re-queued between
     bool refine = false;
+    bool mixed_batch = false;   // a small refined solve with FP32 updates, run in a lockstep batch
     size_t state_bytes = 0;     // its iteration state (refine_state_bytes) and the padding before it
     int owner = -1;             // slot whose pool holds its buffers (set by the first turn)
     double *rhs = nullptr;      // right-hand side, then the solution, on the device
@@ -86,6 +88,7 @@ struct Factor {
 struct Work {
     std::vector<Req> reqs;
     bool batched = false;
+    bool mixed = false;       // a lockstep batch of small refined solves (batched is set too)
     bool cont = false;        // a later turn of a refined solve (admitted by its first)
     bool finished = true;     // a refined solve's turn completed it
     size_t ws_extra = 0;      // device memory reserved for the slot's workspace growth
@@ -123,6 +126,7 @@ struct rtri_server {
         hipMemPool_t pool = nullptr;
         rtri_handle *h = nullptr;
         BatchScratch sc;
+        BatchScratch sc2;     // a lockstep refinement round's second batched launch (the residual products)
         size_t ws_held = 0;   // workspace the slot's handle keeps allocated (counted in used)
     };
     std::vector<Slot> slots;
@@ -280,7 +284,7 @@ void complete_now(rtri_server *s, const Req &q, int status)
 
 // Reserve what request q needs for slot `slot`; creates (and starts generating)
 // a missing synthetic factor.  Returns false if it does not fit right now.
-bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool batched)
+bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool batched, bool mixed = false)
 {
     auto it = s->factors.find(q.r.factor_id);
     const bool have = it != s->factors.end();
@@ -290,7 +294,13 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool 
     size_t ws_extra = 0, tables = w.tables, part_extra = 0;
     if (batched) {
         tables += batch_entry_bound(q) + (w.reqs.empty() ? 1024 : 0);
-        const size_t grow = 2 * tables > slot.sc.dev_bytes ? 2 * tables - slot.sc.dev_bytes : 0;
+        size_t grow = 2 * tables > slot.sc.dev_bytes ? 2 * tables - slot.sc.dev_bytes : 0;
+        if (mixed) {
+            // both launches of a round have their own scratch; the factor
+            // object makes the GEMM-type copy and |op(A)| on first use
+            grow += 2 * tables > slot.sc2.dev_bytes ? 2 * tables - slot.sc2.dev_bytes : 0;
+            part_extra = part_growth(slot.h, q);
+        }
         ws_extra = grow > w.ws_extra ? grow - w.ws_extra : 0;
     } else {
         ws_extra = alone_growth(slot.h, q);
@@ -328,7 +338,7 @@ bool admit(rtri_server *s, rtri_server::Slot &slot, const Req &q, Work &w, bool 
         s->st.factor_hits += 1;
     }
     f = &it->second;
-    if (!batched && f->fo[q.r.diag] == nullptr) {
+    if ((!batched || mixed) && f->fo[q.r.diag] == nullptr) {
         // no device work: the object reads the factor in place
         if (rtri_factor_create(slot.h, f->uplo, q.r.diag, f->ka, RTRI_F64, f->ptr, f->lda, 0, &f->fo[q.r.diag]) !=
             RTRI_OK) {
@@ -398,26 +408,29 @@ void take_work(rtri_server *s, rtri_server::Slot &slot, Work &w)
         return;
     }
     const Req head = s->pending.front();
-    if (head.refine && s->refining >= (int)s->slots.size()) {
+    const bool mb = head.mixed_batch;
+    if (head.refine && !mb && s->refining >= (int)s->slots.size()) {
         take_cont(s, w);   // finish a started refinement before starting another
         return;
     }
-    if (!admit(s, slot, head, w, head.small)) {
+    if (!admit(s, slot, head, w, head.small || mb, mb)) {
         take_cont(s, w);
         return;
     }
     s->pending.pop_front();
-    if (head.refine)
+    if (head.refine && !mb)
         s->refining += 1;
-    if (!head.small)
+    if (!head.small && !mb)
         return;
     w.batched = true;
-    // continuous batching: more small FP64 requests that have arrived, in order
+    w.mixed = mb;
+    // continuous batching: more small requests of the same kind (FP64, or
+    // refined with FP32 updates) that have arrived, in order
     while ((int)w.reqs.size() < s->cfg.max_batch && !s->pending.empty()) {
         const Req &q = s->pending.front();
-        if (q.r.t_arrival > t || !q.small || !consistent(s, q))
+        if (q.r.t_arrival > t || (mb ? !q.mixed_batch : !q.small) || !consistent(s, q))
             break;
-        if (!admit(s, slot, q, w, true))
+        if (!admit(s, slot, q, w, true, mb))
             break;
         s->pending.pop_front();
     }
@@ -580,6 +593,148 @@ void execute_refine(rtri_server *s, rtri_server::Slot &slot, Work &w, std::vecto
     out.push_back(c);
 }
 
+// A lockstep batch of small refined solves with FP32 updates: each round of
+// corrections is folded into two batched launches, the FP32 solves of every
+// member still refining (against the factor objects' FP32 copies of A) and
+// their FP64 residual products (against the FP64 factors); the element-wise
+// phases run per member on the slot's stream, and one synchronisation per
+// round reads every member's scalars.  A member's arithmetic is the batched
+// kernel's: it meets the refined solve's tolerance, but is not bitwise the
+// refined solve run alone.
+void execute_mixed_batch(rtri_server *s, rtri_server::Slot &slot, Work &w, std::vector<rtri_completion> &out)
+{
+    rtri_handle *h = slot.h;
+    hipStream_t st = slot.stream;
+    const double t_start = now_s(s);
+    constexpr double tol = 1e-12;
+    constexpr int max_iter = 30;
+    const size_t k = w.reqs.size();
+    std::vector<const Factor *> fac(k, nullptr);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (size_t i = 0; i < k; ++i)
+            fac[i] = &s->factors.at(w.reqs[i].r.factor_id);   // pinned by refs: the entry stays
+    }
+    auto trans_of = [](const rtri_request &r) { return r.trans == RTRI_CONJTRANS ? RTRI_TRANS : r.trans; };
+    std::vector<MixedPrep> prep(k);
+    std::vector<int> status(k, RTRI_OK);
+    std::vector<unsigned long long> host(4 * k, 0);
+    hipError_t e = hipSuccess;
+    // each member: its block (right-hand side, then state), the right-hand
+    // side, the factor object's parts, alpha B and max |alpha B|
+    for (size_t i = 0; i < k && e == hipSuccess; ++i) {
+        Req &q = w.reqs[i];
+        const rtri_request &r = q.r;
+        q.owner = slot.idx;
+        if (fac[i]->ready != nullptr)
+            e = hipStreamWaitEvent(st, fac[i]->ready, 0);
+        if (e == hipSuccess)
+            e = hipMallocFromPoolAsync((void **)&q.rhs, rhs_span(q) + q.state_bytes, slot.pool, st);
+        if (e != hipSuccess)
+            break;
+        q.state = reinterpret_cast<char *>(q.rhs) + rhs_span(q);
+        refine_state_place(q.st, q.state, r.m, r.n);
+        if (rtri_synth_fill(h, RTRI_F64, 0, s->cfg.synth_seed, 2u, r.rhs_id, r.m, r.n, 0.0, q.rhs, r.m) != RTRI_OK) {
+            e = hipErrorUnknown;
+            break;
+        }
+        status[i] = factor_refine_prep(h, fac[i]->fo[r.diag], r.side, r.trans, r.m, r.n, r.precision, prep[i]);
+        if (status[i] != RTRI_OK)
+            continue;
+        e = refine_begin_enqueue(h, r.side, r.uplo, trans_of(r), r.diag, r.m, r.n, r.alpha, fac[i]->ptr,
+                                 fac[i]->lda, q.rhs, r.m, prep[i], q.st, &host[4 * i]);
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        for (size_t i = 0; i < k; ++i)
+            if (status[i] == RTRI_OK)
+                refine_begin_finish(&host[4 * i], tol, max_iter, &w.reqs[i].info, prep[i], w.reqs[i].st);
+    // rounds of corrections over the members still refining
+    std::vector<size_t> act;
+    std::vector<rtri_batch_entry> be;
+    while (e == hipSuccess) {
+        act.clear();
+        for (size_t i = 0; i < k; ++i)
+            if (status[i] == RTRI_OK && !w.reqs[i].st.done)
+                act.push_back(i);
+        if (act.empty())
+            break;
+        for (size_t x = 0; x < act.size() && e == hipSuccess; ++x)
+            e = refine_step_convert(h, w.reqs[act[x]].r.m, w.reqs[act[x]].r.n, w.reqs[act[x]].st);
+        // op(A32) D = R / s for every member: one batched FP32 launch
+        be.clear();
+        for (size_t i : act) {
+            const Req &q = w.reqs[i];
+            const rtri_request &r = q.r;
+            be.push_back(rtri_batch_entry{0, r.side, r.uplo, trans_of(r), r.diag, r.m, r.n, 1.0, prep[i].Acopy,
+                                          prep[i].ldag, q.st.D, q.st.ld});
+        }
+        int bad = -1;
+        int rc = e == hipSuccess ? batch_run_async(h, RTRI_F32, (int)be.size(), be.data(), slot.sc, &bad, nullptr)
+                                 : RTRI_OK;
+        for (size_t x = 0; x < act.size() && e == hipSuccess && rc == RTRI_OK; ++x)
+            e = refine_step_update(h, w.reqs[act[x]].r.m, w.reqs[act[x]].r.n, w.reqs[act[x]].st);
+        // W := op(A) W in FP64 for every member: one batched launch
+        be.clear();
+        for (size_t i : act) {
+            const Req &q = w.reqs[i];
+            const rtri_request &r = q.r;
+            be.push_back(rtri_batch_entry{1, r.side, r.uplo, trans_of(r), r.diag, r.m, r.n, 1.0, fac[i]->ptr,
+                                          fac[i]->lda, q.st.W, q.st.ld});
+        }
+        if (e == hipSuccess && rc == RTRI_OK)
+            rc = batch_run_async(h, RTRI_F64, (int)be.size(), be.data(), slot.sc2, &bad, nullptr);
+        for (size_t x = 0; x < act.size() && e == hipSuccess && rc == RTRI_OK; ++x) {
+            const size_t i = act[x];
+            e = refine_step_resid(h, w.reqs[i].r.side, w.reqs[i].r.m, w.reqs[i].r.n, w.reqs[i].st, &host[4 * i]);
+        }
+        const hipError_t se = hipStreamSynchronize(st);   // also before the staging is reused
+        if (e == hipSuccess)
+            e = se;
+        if (rc != RTRI_OK) {
+            for (size_t i : act)
+                status[i] = rc;
+            break;
+        }
+        if (e == hipSuccess)
+            for (size_t i : act)
+                refine_step_finish(&host[4 * i], tol, max_iter, &w.reqs[i].info, w.reqs[i].st);
+    }
+    // X into the right-hand side, the results to the host
+    for (size_t i = 0; i < k && e == hipSuccess; ++i) {
+        Req &q = w.reqs[i];
+        if (status[i] != RTRI_OK)
+            continue;
+        status[i] = refine_end(h, q.r.m, q.r.n, q.rhs, q.r.m, &q.info, q.st);
+        if (q.r.result != nullptr && status[i] == RTRI_OK)
+            e = hipMemcpyAsync(q.r.result, q.rhs, q.rhs_bytes, hipMemcpyDeviceToHost, st);
+    }
+    for (Req &q : w.reqs)
+        if (q.rhs != nullptr) {
+            (void)hipFreeAsync(q.rhs, st);
+            q.rhs = nullptr;
+            q.state = nullptr;
+        }
+    const hipError_t se = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = se;
+    const double t_done = now_s(s);
+    for (size_t i = 0; i < k; ++i) {
+        const Req &q = w.reqs[i];
+        rtri_completion c{};
+        c.ticket = q.ticket;
+        c.status = e != hipSuccess ? RTRI_ERR_HIP : status[i];
+        c.batched = 1;
+        c.iters = q.info.iters;
+        c.eta = q.info.eta;
+        c.t_arrival = q.r.t_arrival;
+        c.t_start = t_start;
+        c.t_done = t_done;
+        out.push_back(c);
+    }
+}
+
 void worker(rtri_server *s, int idx)
 {
     rtri_server::Slot &slot = s->slots[idx];
@@ -605,7 +760,9 @@ void worker(rtri_server *s, int idx)
             }
         }
         out.clear();
-        if (!w.batched && w.reqs[0].refine)
+        if (w.mixed)
+            execute_mixed_batch(s, slot, w, out);
+        else if (!w.batched && w.reqs[0].refine)
             execute_refine(s, slot, w, out);
         else
             execute(s, slot, w, out);
@@ -623,15 +780,22 @@ void worker(rtri_server *s, int idx)
                     s->st.failed += 1;
             }
             // the slot keeps its largest workspace and batch scratch: count what it holds now
-            const size_t held = handle_ws_bytes(slot.h) + slot.sc.dev_bytes;
+            const size_t held = handle_ws_bytes(slot.h) + slot.sc.dev_bytes + slot.sc2.dev_bytes;
             s->used += (int64_t)held - (int64_t)(slot.ws_held + w.ws_extra);
             slot.ws_held = held;
             // parts the factor objects made replace the reservation for them
-            if (!w.batched) {
-                Factor &f = s->factors.at(w.reqs[0].r.factor_id);
-                const size_t now = factor_object_bytes(f);
-                s->used += (int64_t)now - (int64_t)f.part_bytes - (int64_t)w.part_extra;
-                f.part_bytes = now;
+            if (!w.batched || w.mixed) {
+                std::vector<uint64_t> ids;
+                for (const Req &q : w.reqs)
+                    if (std::find(ids.begin(), ids.end(), q.r.factor_id) == ids.end())
+                        ids.push_back(q.r.factor_id);
+                for (uint64_t id : ids) {
+                    Factor &f = s->factors.at(id);
+                    const size_t now = factor_object_bytes(f);
+                    s->used += (int64_t)now - (int64_t)f.part_bytes;
+                    f.part_bytes = now;
+                }
+                s->used -= (int64_t)w.part_extra;
             }
             if (w.finished)
                 s->st.completed += (int64_t)w.reqs.size();
@@ -764,8 +928,11 @@ int rtri_server_submit(rtri_server *s, const rtri_request *r, uint64_t *ticket)
     const bool requeue = s->cfg.refine_requeue != 0;
     q.small = r->precision == RTRI_PREC_F64 && q.ka <= s->cfg.small_max && r->m > 0 && r->n > 0;
     q.refine = r->precision != RTRI_PREC_F64 && r->op == 0 && r->alpha != 0.0 && r->m > 0 && r->n > 0;
-    q.state_bytes = q.refine && requeue ? refine_state_bytes(r->m, r->n) + (rhs_span(q) - q.rhs_bytes) : 0;
-    q.ws_bytes = ws_bound(*r, q.ka, q.refine && !requeue);
+    q.mixed_batch = s->cfg.mixed_batch != 0 && q.refine && r->precision == RTRI_PREC_MIXED_F32 &&
+                    q.ka <= s->cfg.small_max;
+    const bool own_state = q.refine && (requeue || q.mixed_batch);
+    q.state_bytes = own_state ? refine_state_bytes(r->m, r->n) + (rhs_span(q) - q.rhs_bytes) : 0;
+    q.ws_bytes = ws_bound(*r, q.ka, q.refine && !own_state);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         q.ticket = s->next_ticket++;
@@ -848,6 +1015,7 @@ int rtri_server_destroy(rtri_server *s)
         (void)hipStreamSynchronize(sl.stream);
     for (auto &sl : s->slots) {
         batch_scratch_free(sl.sc);
+        batch_scratch_free(sl.sc2);
         rtri_destroy(sl.h);
         (void)hipMemPoolDestroy(sl.pool);
         (void)hipStreamDestroy(sl.stream);

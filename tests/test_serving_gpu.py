@@ -156,6 +156,46 @@ def test_serving_refined_requeued_per_correction(rt, h, orc, slots):
         assert np.array_equal(res, _alone(rt, h, r)), r
 
 
+@pytest.mark.parametrize("slots", [1, 3])
+def test_serving_mixed_batch(rt, h, orc, slots):
+    """With mixed_batch, small refined solves with FP32 updates run in lockstep
+    batches (one batched FP32 solve and one batched FP64 residual product per
+    round of corrections): every such request converges (eta <= 1e-12 against
+    the oracle on the host twin of its inputs), at least one batch holds
+    several of them, refined requests with BF16 updates still run alone, and
+    FP64 results stay bitwise the alone results."""
+    g = synth.rng(synth.W_SERVE, 4)
+    fac = [(5000 + f, int(synth.loguniform_int(g, 16, 600, 1)[0]), "L" if f % 2 else "U") for f in range(10)]
+    reqs = []
+    for i in range(90):
+        fid, ka, uplo = fac[int(g.integers(0, 10))]
+        prec = 2 if i % 3 else (0 if i % 2 else 1)
+        reqs.append(dict(op="trsm", side="L", uplo=uplo, trans="N" if g.random() < 0.5 else "T", diag="N", m=ka,
+                         n=int(g.integers(1, 80)), alpha=1.0 if i % 5 else -0.5, precision=prec, factor_id=fid,
+                         rhs_id=90000 + i))
+    say("serving mixed batch", len(reqs), "slots", slots)
+    results, comps, stats = _run_stream(rt, reqs, rate=20000.0, slots=slots, max_batch=16, small_max=1024,
+                                        mixed_batch=True)
+    assert len(comps) == len(reqs)
+    assert all(c["status"] == 0 for c in comps), [c for c in comps if c["status"] != 0][:3]
+    by_ticket = {c["ticket"]: c for c in comps}
+    f32 = [tk for tk, (r, _) in results.items() if r["precision"] == 2]
+    assert all(by_ticket[tk]["batched"] and by_ticket[tk]["iters"] >= 1 for tk in f32)
+    # at least one batch of several refined solves: completions sharing a start time
+    starts = [by_ticket[tk]["t_start"] for tk in f32]
+    assert max(starts.count(t) for t in starts) >= 2
+    assert stats["refine_turns"] == sum(1 for r, _ in results.values() if r["precision"] == 1)
+    for tk, (r, res) in results.items():
+        if r["precision"] == 2:
+            ka = r["m"]
+            A = synth.philox_matrix(1 if r["uplo"] == "L" else 2, SEED, 1, r["factor_id"], ka, ka, float(ka))
+            B = synth.philox_matrix(0, SEED, 2, r["rhs_id"], r["m"], r["n"])
+            e = orc.trsm_eta("L", r["uplo"], r["trans"], "N", r["alpha"], A, B, res)
+            assert e <= 1e-12, (r, e)
+        else:
+            assert np.array_equal(res, _alone(rt, h, r)), r
+
+
 def test_serving_small_budget(rt, h):
     """A 48 MB budget against about 150 MB of distinct factors (up to 19 MB
     each): factors are evicted and requests wait for memory; every result is
