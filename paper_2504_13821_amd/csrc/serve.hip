@@ -13,6 +13,8 @@
 //        else it reads is the factor object's), so slots serve other
 //        requests between its corrections and any slot may run its next one;
 //        at most one refined solve per slot is started and unfinished;
+//      - with mixed_batch, a small refined request with FP32 updates opens a
+//        lockstep batch of such requests (execute_mixed_batch);
 //      admission reserves the request's right-hand side and workspace and, for
 //      a factor not resident yet, the factor itself; least-recently-used
 //      factors nobody is using are evicted when the budget needs room.  A new
