@@ -522,10 +522,12 @@ typedef struct {
     uint64_t synth_seed;    /* seed of synthetic factors and right-hand sides (rtri_synth_fill) */
     int refine_requeue;     /* 0: a refined solve runs to the end in one turn of its slot; 1: it
                                re-enters the queue after each correction (see rtri_request) */
-    int mixed_batch;        /* 1: refined solves with FP32 updates and factor order <= small_max
-                               run in lockstep batches: per round of corrections one batched FP32
-                               solve and one batched FP64 residual product over the batch; results
-                               meet the same tolerance, not bitwise the alone solve */
+    int mixed_batch;        /* 1: a refined solve with FP32 updates and factor order <= small_max
+                               opens a lockstep batch of the arrived requests of its kind when
+                               another is waiting (else it runs alone): per round of corrections
+                               one batched FP32 solve and one batched FP64 residual product over
+                               the batch; results meet the same tolerance, not bitwise the alone
+                               solve */
 } rtri_server_cfg;
 
 /* One request: a TRSM (op 0) or TRMM (op 1) with the argument meaning of

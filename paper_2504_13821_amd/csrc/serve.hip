@@ -67,6 +67,10 @@ struct Req {
     double t_start = 0.0, t_requeue = 0.0;
 };
 
+// how far past the queue head a lockstep batch of small refined solves looks
+// for members
+constexpr int MIX_WINDOW = 512;
+
 // a refined solve's state follows its right-hand side in one block
 size_t rhs_span(const Req &q)
 {
@@ -410,7 +414,21 @@ void take_work(rtri_server *s, rtri_server::Slot &slot, Work &w)
         return;
     }
     const Req head = s->pending.front();
-    const bool mb = head.mixed_batch;
+    // a lockstep batch pays only with company: another arrived request of its
+    // kind among the next MIX_WINDOW; else the head runs alone (its state in
+    // its own block, as with refine_requeue)
+    bool mb = false;
+    if (head.mixed_batch) {
+        int seen = 0;
+        for (auto it = std::next(s->pending.begin()); it != s->pending.end() && seen < MIX_WINDOW; ++it, ++seen) {
+            if (it->r.t_arrival > t)
+                break;
+            if (it->mixed_batch && consistent(s, *it)) {
+                mb = true;
+                break;
+            }
+        }
+    }
     if (head.refine && !mb && s->refining >= (int)s->slots.size()) {
         take_cont(s, w);   // finish a started refinement before starting another
         return;
@@ -426,13 +444,30 @@ void take_work(rtri_server *s, rtri_server::Slot &slot, Work &w)
         return;
     w.batched = true;
     w.mixed = mb;
-    // continuous batching: more small requests of the same kind (FP64, or
-    // refined with FP32 updates) that have arrived, in order
+    if (mb) {
+        // the arrived requests of its kind among the next MIX_WINDOW join it,
+        // in arrival order, ahead of the others in between
+        int seen = 0;
+        for (auto it = s->pending.begin();
+             it != s->pending.end() && seen < MIX_WINDOW && (int)w.reqs.size() < s->cfg.max_batch; ++seen) {
+            if (it->r.t_arrival > t)
+                break;
+            if (!it->mixed_batch || !consistent(s, *it)) {
+                ++it;
+                continue;
+            }
+            if (!admit(s, slot, *it, w, true, true))
+                break;
+            it = s->pending.erase(it);
+        }
+        return;
+    }
+    // continuous batching: more small FP64 requests that have arrived, in order
     while ((int)w.reqs.size() < s->cfg.max_batch && !s->pending.empty()) {
         const Req &q = s->pending.front();
-        if (q.r.t_arrival > t || (mb ? !q.mixed_batch : !q.small) || !consistent(s, q))
+        if (q.r.t_arrival > t || !q.small || !consistent(s, q))
             break;
-        if (!admit(s, slot, q, w, true, mb))
+        if (!admit(s, slot, q, w, true))
             break;
         s->pending.pop_front();
     }

@@ -159,11 +159,12 @@ def test_serving_refined_requeued_per_correction(rt, h, orc, slots):
 @pytest.mark.parametrize("slots", [1, 3])
 def test_serving_mixed_batch(rt, h, orc, slots):
     """With mixed_batch, small refined solves with FP32 updates run in lockstep
-    batches (one batched FP32 solve and one batched FP64 residual product per
-    round of corrections): every such request converges (eta <= 1e-12 against
-    the oracle on the host twin of its inputs), at least one batch holds
-    several of them, refined requests with BF16 updates still run alone, and
-    FP64 results stay bitwise the alone results."""
+    batches when another such request is waiting (one batched FP32 solve and
+    one batched FP64 residual product per round of corrections), else alone:
+    every such request converges (eta <= 1e-12 against the oracle on the host
+    twin of its inputs), at least one batch holds several of them, refined
+    requests with BF16 updates still run alone, and FP64 results stay bitwise
+    the alone results."""
     g = synth.rng(synth.W_SERVE, 4)
     fac = [(5000 + f, int(synth.loguniform_int(g, 16, 600, 1)[0]), "L" if f % 2 else "U") for f in range(10)]
     reqs = []
@@ -180,11 +181,13 @@ def test_serving_mixed_batch(rt, h, orc, slots):
     assert all(c["status"] == 0 for c in comps), [c for c in comps if c["status"] != 0][:3]
     by_ticket = {c["ticket"]: c for c in comps}
     f32 = [tk for tk, (r, _) in results.items() if r["precision"] == 2]
-    assert all(by_ticket[tk]["batched"] and by_ticket[tk]["iters"] >= 1 for tk in f32)
+    assert all(by_ticket[tk]["iters"] >= 1 for tk in f32)
     # at least one batch of several refined solves: completions sharing a start time
-    starts = [by_ticket[tk]["t_start"] for tk in f32]
-    assert max(starts.count(t) for t in starts) >= 2
-    assert stats["refine_turns"] == sum(1 for r, _ in results.values() if r["precision"] == 1)
+    starts = [by_ticket[tk]["t_start"] for tk in f32 if by_ticket[tk]["batched"]]
+    assert starts and max(starts.count(t) for t in starts) >= 2
+    # a request with no company waiting ran alone (one turn), as did every BF16-update one
+    alone = sum(1 for tk in f32 if not by_ticket[tk]["batched"])
+    assert stats["refine_turns"] == sum(1 for r, _ in results.values() if r["precision"] == 1) + alone
     for tk, (r, res) in results.items():
         if r["precision"] == 2:
             ka = r["m"]
