@@ -522,8 +522,8 @@ typedef struct {
     uint64_t synth_seed;    /* seed of synthetic factors and right-hand sides (rtri_synth_fill) */
     int refine_requeue;     /* 0: a refined solve runs to the end in one turn of its slot; 1: it
                                re-enters the queue after each correction (see rtri_request) */
-    int mixed_batch;        /* 1: a refined solve with FP32 updates and factor order <= small_max
-                               opens a lockstep batch of the arrived requests of its kind when
+    int mixed_batch;        /* 1: a refined solve with FP32 updates and factor order
+                               <= min(small_max, 256) opens a lockstep batch of the arrived requests of its kind when
                                another is waiting (else it runs alone): per round of corrections
                                one batched FP32 solve and one batched FP64 residual product over
                                the batch; results meet the same tolerance, not bitwise the alone

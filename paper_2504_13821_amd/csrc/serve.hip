@@ -68,8 +68,10 @@ struct Req {
 };
 
 // how far past the queue head a lockstep batch of small refined solves looks
-// for members
+// for members, and the largest factor order it takes (a larger problem walked
+// by the batched kernel's workgroups holds the whole batch back)
 constexpr int MIX_WINDOW = 512;
+constexpr int64_t MIX_MAX_ORDER = 256;
 
 // a refined solve's state follows its right-hand side in one block
 size_t rhs_span(const Req &q)
@@ -966,7 +968,7 @@ int rtri_server_submit(rtri_server *s, const rtri_request *r, uint64_t *ticket)
     q.small = r->precision == RTRI_PREC_F64 && q.ka <= s->cfg.small_max && r->m > 0 && r->n > 0;
     q.refine = r->precision != RTRI_PREC_F64 && r->op == 0 && r->alpha != 0.0 && r->m > 0 && r->n > 0;
     q.mixed_batch = s->cfg.mixed_batch != 0 && q.refine && r->precision == RTRI_PREC_MIXED_F32 &&
-                    q.ka <= s->cfg.small_max;
+                    q.ka <= std::min<int64_t>(s->cfg.small_max, MIX_MAX_ORDER);
     const bool own_state = q.refine && (requeue || q.mixed_batch);
     q.state_bytes = own_state ? refine_state_bytes(r->m, r->n) + (rhs_span(q) - q.rhs_bytes) : 0;
     q.ws_bytes = ws_bound(*r, q.ka, q.refine && !own_state);
