@@ -1,12 +1,12 @@
 """The FP64 / FP32 GEMM update on its own, across tile shapes and K.
 
-FP32 64x64 tiles stage two k-steps (32 values of K) per LDS buffer; 128x128
-tiles stage one.  Both issue, for every element of C, the same MFMA sequence
-over K (k-steps of 16 in order, within a step lane group g taking k = 4g + t in
-MFMA number t), so the two tile shapes must agree bit for bit for every K:
-ragged K included, where the last stage holds one k-step, or part of one, and
-the second half of a stage is skipped.  FP64 tiles stage one k-step in both
-shapes (the same check as a control).
+FP32 64x64 tiles stage two k-steps (32 values of K) per LDS buffer; the
+128x128 tiles (4 or 8 wavefronts) stage one.  All issue, for every element of
+C, the same MFMA sequence over K (k-steps of 16 in order, within a step lane
+group g taking k = 4g + t in MFMA number t), so the tile shapes must agree bit
+for bit for every K: ragged K included, where the last stage holds one k-step,
+or part of one, and the second half of a stage is skipped.  FP64 tiles stage
+one k-step in every shape (the same check as a control).
 
 Bound against the exact result (FP64 reference of the rounded inputs):
 |got - exact| <= 2 (K + 2) u (|beta C| + |s| |op(P)| |op(Q)|) elementwise,
@@ -73,8 +73,10 @@ def test_tile_shapes_agree_over_k(rt, h, dt, tp, tq, beta):
         g = synth.rng(synth.W_TEST, 3100, K, ord(tp) * 3 + ord(tq), int(beta * 4))
         P, Q, C = _operands(M, N, K, tp, tq, g, dt)
         c64 = _run(rt, h, 2, tp, tq, s, P, Q, beta, C, dt)    # 64x64 tiles
-        c128 = _run(rt, h, 1, tp, tq, s, P, Q, beta, C, dt)   # 128x128 tiles
+        c128 = _run(rt, h, 1, tp, tq, s, P, Q, beta, C, dt)   # 128x128 tiles, 4 wavefronts
+        c8w = _run(rt, h, 3, tp, tq, s, P, Q, beta, C, dt)    # 128x128 tiles, 8 wavefronts
         assert np.array_equal(c64, c128), (dt, tp, tq, beta, K, float(np.max(np.abs(c64 - c128))))
+        assert np.array_equal(c64, c8w), (dt, tp, tq, beta, K, float(np.max(np.abs(c64 - c8w))))
         op_p = P.T if tp == "T" else P
         op_q = Q.T if tq == "T" else Q
         exact = beta * C + s * (op_p @ op_q)
