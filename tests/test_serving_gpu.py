@@ -171,9 +171,12 @@ def test_serving_mixed_batch(rt, h, orc, slots):
     for i in range(90):
         fid, ka, uplo = fac[int(g.integers(0, 10))]
         prec = 2 if i % 3 else (0 if i % 2 else 1)
-        reqs.append(dict(op="trsm", side="L", uplo=uplo, trans="N" if g.random() < 0.5 else "T", diag="N", m=ka,
-                         n=int(g.integers(1, 80)), alpha=1.0 if i % 5 else -0.5, precision=prec, factor_id=fid,
-                         rhs_id=90000 + i))
+        other = int(g.integers(1, 80))
+        # refined requests with FP32 updates also on side R (factor order n)
+        side = "R" if prec == 2 and i % 4 == 1 else "L"
+        m, n = (ka, other) if side == "L" else (other, ka)
+        reqs.append(dict(op="trsm", side=side, uplo=uplo, trans="N" if g.random() < 0.5 else "T", diag="N", m=m,
+                         n=n, alpha=1.0 if i % 5 else -0.5, precision=prec, factor_id=fid, rhs_id=90000 + i))
     say("serving mixed batch", len(reqs), "slots", slots)
     results, comps, stats = _run_stream(rt, reqs, rate=20000.0, slots=slots, max_batch=16, small_max=1024,
                                         mixed_batch=True)
@@ -190,10 +193,10 @@ def test_serving_mixed_batch(rt, h, orc, slots):
     assert stats["refine_turns"] == sum(1 for r, _ in results.values() if r["precision"] == 1) + alone
     for tk, (r, res) in results.items():
         if r["precision"] == 2:
-            ka = r["m"]
+            ka = r["m"] if r["side"] == "L" else r["n"]
             A = synth.philox_matrix(1 if r["uplo"] == "L" else 2, SEED, 1, r["factor_id"], ka, ka, float(ka))
             B = synth.philox_matrix(0, SEED, 2, r["rhs_id"], r["m"], r["n"])
-            e = orc.trsm_eta("L", r["uplo"], r["trans"], "N", r["alpha"], A, B, res)
+            e = orc.trsm_eta(r["side"], r["uplo"], r["trans"], "N", r["alpha"], A, B, res)
             assert e <= 1e-12, (r, e)
         else:
             assert np.array_equal(res, _alone(rt, h, r)), r
