@@ -82,3 +82,22 @@ def test_rect256_variants_4096(rt, h, orc, dt, op, diag, side, uplo, trans):
         Bs, Xs = np.asfortranarray(B[idx, :]), np.asfortranarray(X[idx, :])
     e = eta(orc, op, side, uplo, trans, diag, 0.5, A, Bs, Xs)
     assert e <= TOL[dt], (dt, op, side, uplo, trans, diag, e)
+
+
+@pytest.mark.parametrize("op", ["trsm", "trmm"])
+@pytest.mark.parametrize("m,n,uplo,trans", [(5000, 256, "L", "N"), (5000, 256, "U", "T"), (9001, 200, "L", "T"),
+                                            (9001, 200, "U", "N")])
+def test_rect256_ragged(rt, h, orc, op, m, n, uplo, trans):
+    """Narrow panels whose order is not a multiple of the tiles or leaves, with
+    200 or 256 vectors: the grouped TRMM launch with edge tiles (tile order by
+    CU rounds, two k-steps per LDS stage, a last stage ending inside K) and the
+    TRSM's split-K updates, FP32, against the oracle on sampled columns."""
+    say("rect256 ragged", op, m, n, uplo, trans, "leaf", h.leaf("f32", op, m, n))
+    g = synth.rng(synth.W_TEST, 6100, m, n, ord(uplo) + 2 * ord(trans), 1 if op == "trsm" else 2)
+    A = rounded(synth.tri(m, uplo, g, "base"), "f32")
+    B = rounded(synth.dense(m, n, g), "f32")
+    X = run_op(rt, h, op, "L", uplo, trans, "N", -1.25, A, B, "f32")
+    idx = np.sort(g.choice(n, 12, replace=False))
+    Bs, Xs = np.asfortranarray(B[:, idx]), np.asfortranarray(X[:, idx])
+    e = eta(orc, op, "L", uplo, trans, "N", -1.25, A, Bs, Xs)
+    assert e <= TOL["f32"], (op, m, n, uplo, trans, e)
